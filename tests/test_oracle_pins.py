@@ -1,0 +1,380 @@
+"""Pins of the HSMA oracle against facts fixed by the paper and mathematics.
+
+Each test names what it pins.  None of them retypes an oracle formula: the
+references are the Madelung constant printed in the paper (Sec. III), tin-foil
+Ewald sums (tests/ewald.py), closed forms and invariants.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import ewald
+import oracle
+from oracle import hsma
+
+MADELUNG = 1.74756459463318219  # Sec. III, first example
+
+
+def nacl(n_side, L):
+    a = L / n_side
+    idx = [(i, j, k) for i in range(n_side) for j in range(n_side) for k in range(n_side)]
+    x = np.array([[(i + 0.5) * a, (j + 0.5) * a, (k + 0.5) * a] for i, j, k in idx])
+    q = np.array([(-1.0) ** (i + j + k) for i, j, k in idx])
+    return x, q, a
+
+
+# ---------------------------------------------------------------- whole method
+def test_madelung_c1_config():
+    """8 ions, L=1, p=8, K=600, M=1000, R=2.7L: the Madelung constant."""
+    x, q, a = nacl(2, 1.0)
+    plan = oracle.make_plan(1.0, oracle.BC_PERIODIC, 8, 1000, 600, 2.7)
+    r = oracle.solve(plan, x, q)
+    M = -2.0 * a * r["energy"] / len(q)
+    assert abs(M - MADELUNG) / MADELUNG < 1e-5
+
+
+def test_madelung_paper_layout_64_ions():
+    """The paper's layout: 64 unit charges on a lattice in a box of side 2."""
+    x, q, a = nacl(4, 2.0)
+    plan = oracle.make_plan(2.0, oracle.BC_PERIODIC, 16, 2500, 900, 2.7 * 2.0)
+    r = oracle.solve(plan, x, q)
+    M = -2.0 * a * r["energy"] / len(q)
+    assert abs(M - MADELUNG) / MADELUNG < 1e-7
+
+
+def test_madelung_decays_with_p():
+    """Spectral convergence in P (error bounds of Sec. II.A)."""
+    x, q, a = nacl(2, 1.0)
+    errs = []
+    for p in (8, 12, 16, 20):
+        plan = oracle.make_plan(1.0, oracle.BC_PERIODIC, p, 1000, max(600, 3 * (p + 1) ** 2), 2.7)
+        M = -2.0 * a * oracle.solve(plan, x, q)["energy"] / len(q)
+        errs.append(abs(M - MADELUNG) / MADELUNG)
+    assert errs[-1] < 5e-9
+    assert errs[0] > errs[2] > errs[3]
+
+
+def _rand_system(rng, n, bc, L=1.0):
+    x = rng.random((n, 3)) * L
+    if bc == oracle.BC_SLAB:
+        x[:, 2] *= 0.5
+    q = np.array([1.0, -1.0] * (n // 2))
+    rng.shuffle(q)
+    return x, q
+
+
+@pytest.mark.parametrize("bc,p,tolE,tolP,tolF", [
+    (oracle.BC_PERIODIC, 16, 5e-7, 5e-7, 2e-5),
+    (oracle.BC_PERIODIC, 20, 5e-9, 2e-8, 1e-7),
+    (oracle.BC_METALLIC, 16, 5e-8, 5e-8, 5e-8),
+    (oracle.BC_METALLIC, 20, 5e-10, 5e-9, 1e-9),
+    (oracle.BC_SLAB, 16, 5e-7, 5e-7, 2e-7),
+])
+def test_against_ewald(bc, p, tolE, tolP, tolF):
+    """Tin-foil Ewald (periodic), the 2L mirror cell (grounded cube) and the
+    doubled cell (grounded slab): energy (per charge), potential and forces,
+    within the method's truncation error at this P (R = 2.7L)."""
+    rng = np.random.default_rng(100 + 10 * bc + p)
+    L = 1.0
+    plan = oracle.make_plan(L, bc, p, 2500, 3 * (p + 1) ** 2, 2.7)
+    for n in (2, 6, 12):
+        x, q = _rand_system(rng, n, bc)
+        if bc == oracle.BC_PERIODIC:
+            rphi, rfld, rE = ewald.ewald(x, q, L)
+        elif bc == oracle.BC_METALLIC:
+            rphi, rfld, rE = ewald.grounded_cube(x, q, L)
+        else:
+            rphi, rfld, rE = ewald.grounded_slab(x, q, L)
+        r = oracle.solve(plan, x, q)
+        assert abs(r["energy"] - rE) <= tolE * n
+        dphi = r["phi"] - rphi
+        if bc == oracle.BC_PERIODIC:
+            dphi -= dphi.mean()   # potential gauge: A_00 = 0 vs zero-mean Ewald
+        assert np.abs(dphi).max() <= tolP * np.abs(rphi).max()
+        assert np.abs(r["field"] - rfld).max() <= tolF * np.abs(rfld).max()
+
+
+def test_paper_cavity_example():
+    """Second example of Sec. III: +2 at (0.1,0,0), -1 at (0.8,0.8,0.8) and
+    (-0.9,-0.9,-0.9) in a grounded box of side 2 centred at the origin."""
+    L = 2.0
+    c = np.array([[0.1, 0.0, 0.0], [0.8, 0.8, 0.8], [-0.9, -0.9, -0.9]])
+    q = np.array([2.0, -1.0, -1.0])
+    x = c + L / 2
+    _, rfld, rE = ewald.grounded_cube(x, q, L)
+    plan = oracle.make_plan(L, oracle.BC_METALLIC, 20, 2500, 1400, 2.7 * L)
+    r = oracle.solve(plan, x, q)
+    assert abs(r["energy"] - rE) / abs(rE) < 1e-9
+    assert np.abs(r["field"] - rfld).max() / np.abs(rfld).max() < 1e-8
+
+
+def test_periodic_force_balance():
+    """Periodic forces sum to zero (the force reference used in Sec. III)."""
+    rng = np.random.default_rng(5)
+    x, q = _rand_system(rng, 20, oracle.BC_PERIODIC)
+    plan = oracle.make_plan(1.0, oracle.BC_PERIODIC, 16, 2500, 900, 2.7)
+    F = oracle.solve(plan, x, q)["forces"]
+    assert np.abs(F.sum(axis=0)).max() < 1e-6 * np.abs(F).max()
+
+
+def test_metallic_potential_vanishes_on_walls():
+    """Grounded cube: Phi_in + Phi_out ~ 0 at wall points other than the
+    monitoring points."""
+    rng = np.random.default_rng(9)
+    L = 1.0
+    x, q = _rand_system(rng, 10, oracle.BC_METALLIC)
+    plan = oracle.make_plan(L, oracle.BC_METALLIC, 16, 2500, 900, 2.7)
+    r = oracle.solve(plan, x, q)
+    src = np.concatenate([hsma.normalize(x, L, oracle.BC_METALLIC), q[:, None]], axis=1)
+    w = rng.random((50, 3)) - 0.5
+    w[np.arange(50), rng.integers(0, 3, 50)] = 0.5 * rng.choice([-1.0, 1.0], 50)
+    phi_in = oracle.potential_at(oracle.BC_METALLIC, L, src, w)
+    phi_out, _ = oracle.surface_sum(w, r["surf"])
+    assert np.abs(phi_in + phi_out).max() < 2e-5 * np.abs(phi_in).max()
+
+
+def test_metallic_cube_symmetry():
+    """The grounded-cube energy is invariant under the symmetries of the cube
+    (here: axis permutations and reflections), to method accuracy."""
+    rng = np.random.default_rng(11)
+    L = 1.0
+    x, q = _rand_system(rng, 8, oracle.BC_METALLIC)
+    plan = oracle.make_plan(L, oracle.BC_METALLIC, 16, 2500, 900, 2.7)
+    E0 = oracle.solve(plan, x, q)["energy"]
+    for perm, flip in (((1, 2, 0), (1, 1, 1)), ((0, 1, 2), (-1, 1, 1)), ((2, 0, 1), (1, -1, -1))):
+        c = (x - 0.5)[:, perm] * np.array(flip) + 0.5
+        E1 = oracle.solve(plan, c, q)["energy"]
+        assert abs(E1 - E0) < 1e-8 * abs(E0)
+
+
+def test_energy_homogeneous_in_charge():
+    """E(c q) = c^2 E(q) (the method is linear in the charges)."""
+    rng = np.random.default_rng(12)
+    x, q = _rand_system(rng, 10, oracle.BC_PERIODIC)
+    plan = oracle.make_plan(1.0, oracle.BC_PERIODIC, 8, 1000, 600, 2.7)
+    E1 = oracle.solve(plan, x, q)["energy"]
+    E3 = oracle.solve(plan, x, 3.0 * q)["energy"]
+    assert abs(E3 - 9.0 * E1) < 1e-12 * abs(E3)
+
+
+# ---------------------------------------------------------------- geometry
+def test_fibonacci_monitoring_grid():
+    """Sec. II.A: points on the circumsphere, sin(latitude) uniform on
+    (-1 + 1/K, 1 - 1/K), twins inside the box and an integer lattice shift away."""
+    L, K = 1.0, 600
+    X, Xt = oracle.monitoring_points(oracle.BC_PERIODIC, L, K, 0)
+    R0 = math.sqrt(3) / 2 * L
+    assert np.allclose(np.linalg.norm(X, axis=1), R0, rtol=0, atol=1e-14)
+    z = np.sort(X[:, 2] / R0)
+    assert np.allclose(z, np.linspace(-1 + 1 / K, 1 - 1 / K, K), atol=1e-14)
+    assert np.all(np.abs(Xt) <= L / 2 + 1e-15)
+    k = (X - Xt) / L
+    assert np.allclose(k, np.round(k), atol=1e-14)
+    # golden-ratio azimuth: consecutive points advance by 2 pi w
+    w = (math.sqrt(5) - 1) / 2
+    az = np.arctan2(X[:, 1], X[:, 0])
+    step = np.mod(np.diff(az) - 2 * math.pi * w, 2 * math.pi)
+    assert np.all(np.minimum(step, 2 * math.pi - step) < 1e-12)
+
+
+def test_splitmix64_reference_value():
+    """SplitMix64 (Steele, Lea & Flood 2014) from state 0: first output
+    0xE220A8397B1DCDAF."""
+    assert oracle.splitmix64_uniform(0, 0) == (0xE220A8397B1DCDAF >> 11) * 2.0 ** -53
+
+
+def test_metallic_face_points():
+    L, K = 1.0, 600
+    X, Xt = oracle.monitoring_points(oracle.BC_METALLIC, L, K, 42)
+    assert Xt is None
+    for i in range(K):
+        f = i % 6
+        assert X[i, f // 2] == (0.5 if f % 2 else -0.5) * L
+    assert np.all(np.abs(X) <= 0.5 * L)
+
+
+@pytest.mark.parametrize("M,count,F2", [(1000, 1222, 610), (1440, 1222, 610), (2500, 1976, 987),
+                                        (2560, 1976, 987), (4000, 3196, 1597)])
+def test_hannay_nye_counts(M, count, F2):
+    S, w, n, f1, f2 = oracle.integration_points(1.0, M)
+    assert len(S) == count and f2 == F2
+    a, b = 1, 1
+    while b < f2:
+        a, b = b, a + b
+    assert b == f2 and a == f1
+
+
+def test_fibonacci_quadrature_closed_forms():
+    """Sec. II.B quadrature: total weight 4 pi R^2; single-layer potential of a
+    uniform sphere 4 pi R inside; integral of z^2 is 4 pi R^4 / 3."""
+    R = 2.7
+    S, w, n, _, _ = oracle.integration_points(R, 1222)
+    assert abs(w.sum() - 4 * math.pi * R * R) < 1e-12 * 4 * math.pi * R * R
+    assert np.allclose(np.linalg.norm(S, axis=1), R, atol=1e-13)
+    assert np.allclose(n * R, S, atol=1e-13)
+    for r in ([0.1, 0.2, -0.3], [1.0, -0.5, 0.4], [0.0, 0.0, 0.0]):
+        v = np.sum(w / np.linalg.norm(S - np.array(r), axis=1))
+        assert abs(v - 4 * math.pi * R) < 1e-12 * 4 * math.pi * R
+    assert abs(np.sum(w * S[:, 2] ** 2) - 4 * math.pi * R ** 4 / 3) < 1e-12 * R ** 4
+
+
+# ---------------------------------------------------------------- basis
+def test_basis_closed_forms_low_degree():
+    """r^n Y_nm for n <= 2 in Cartesian closed form (orthonormal, no
+    Condon-Shortley phase), scaled by R0^-n."""
+    rng = np.random.default_rng(3)
+    P = rng.standard_normal((20, 3))
+    R0 = 0.7
+    B = oracle.basis(P, 2, R0)
+    x, y, z = P.T
+    c0 = 1 / math.sqrt(4 * math.pi)
+    c1 = math.sqrt(3 / (4 * math.pi)) / R0
+    c2 = 1 / R0 ** 2
+    ref = np.stack([
+        np.full(20, c0),
+        c1 * y, c1 * z, c1 * x,
+        c2 * math.sqrt(15 / (4 * math.pi)) * x * y,
+        c2 * math.sqrt(15 / (4 * math.pi)) * y * z,
+        c2 * math.sqrt(5 / (16 * math.pi)) * (3 * z * z - (x * x + y * y + z * z)),
+        c2 * math.sqrt(15 / (4 * math.pi)) * x * z,
+        c2 * math.sqrt(15 / (16 * math.pi)) * (x * x - y * y),
+    ], axis=1)
+    assert np.allclose(B, ref, rtol=1e-13, atol=1e-14)
+
+
+def test_basis_is_harmonic():
+    """Laplacian of every r^n Y_nm vanishes (finite differences, n <= 10)."""
+    rng = np.random.default_rng(4)
+    P = rng.random((10, 3)) - 0.5
+    h = 1e-3
+    lap = -6 * oracle.basis(P, 10, 1.0)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        lap += oracle.basis(P + e, 10, 1.0) + oracle.basis(P - e, 10, 1.0)
+    lap /= h * h
+    assert np.abs(lap).max() < 1e-4
+
+
+def test_basis_orthonormal_on_unit_sphere():
+    """Gauss-Legendre in cos(theta) x trapezoid in phi, exact to degree 2P."""
+    P = 12
+    xg, wg = np.polynomial.legendre.leggauss(P + 2)
+    nph = 2 * P + 3
+    ph = 2 * math.pi * np.arange(nph) / nph
+    ct, pp = np.meshgrid(xg, ph, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    pts = np.stack([st * np.cos(pp), st * np.sin(pp), ct], axis=-1).reshape(-1, 3)
+    wts = (wg[:, None] * np.full(nph, 2 * math.pi / nph)[None, :]).reshape(-1)
+    B = oracle.basis(pts, P, 1.0)
+    G = B.T @ (wts[:, None] * B)
+    assert np.allclose(G, np.eye((P + 1) ** 2), atol=1e-12)
+
+
+# ---------------------------------------------------------------- LS + mapping
+def _planted(r):
+    """A harmonic polynomial evaluated directly (not through the basis)."""
+    x, y, z = r.T
+    return 0.3 + 0.7 * x - 0.2 * z + (x * x - y * y) + 1.5 * x * y * z + 0.4 * (z ** 3 - 1.5 * z * (x * x + y * y))
+
+
+def test_least_squares_recovers_planted_harmonic():
+    """Metallic fit with Phi_in replaced by minus a harmonic polynomial of
+    degree 3 <= P: the fitted series must reproduce it inside the box
+    (Sec. II.A least squares; Householder QR cross-checked with lstsq)."""
+    plan = oracle.make_plan(1.0, oracle.BC_METALLIC, 6, 1000, 300, 2.7)
+    b = -_planted(plan["X"])
+    A = hsma.coefficients_from_rhs(plan, b)
+    A_np = np.linalg.lstsq(plan["F"], -b, rcond=None)[0]
+    assert np.allclose(A, A_np, atol=1e-11)
+    rng = np.random.default_rng(1)
+    r = rng.random((30, 3)) - 0.5
+    assert np.allclose(oracle.basis(r, 6, plan["R0"]) @ A, _planted(r), atol=1e-12)
+
+
+def test_surface_mapping_reproduces_series_inside():
+    """Green's second identity (Eq. (green)) with the Fibonacci quadrature: the
+    surface charges and dipoles reproduce the harmonic polynomial at interior
+    points, up to the quadrature error."""
+    plan = oracle.make_plan(1.0, oracle.BC_METALLIC, 6, 4000, 300, 2.7)
+    A = hsma.coefficients_from_rhs(plan, -_planted(plan["X"]))
+    surf = hsma.surface_images(plan, A)
+    rng = np.random.default_rng(2)
+    r = rng.random((30, 3)) - 0.5
+    phi, fld = oracle.surface_sum(r, surf)
+    assert np.allclose(phi, _planted(r), atol=1e-11)
+    # field = -grad of the polynomial, by central differences
+    h = 1e-5
+    g = np.zeros_like(r)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        g[:, a] = (_planted(r + e) - _planted(r - e)) / (2 * h)
+    assert np.allclose(fld, -g, atol=1e-8)
+
+
+def test_exact_dipole_matches_paper_charge_layers():
+    """Eq. (cd): the central-difference charge layers at R_s -+ dr/2 converge to
+    the exact dipole as O(dr^2)."""
+    rng = np.random.default_rng(8)
+    x, q = _rand_system(rng, 6, oracle.BC_METALLIC)
+    plan = oracle.make_plan(1.0, oracle.BC_METALLIC, 10, 1000, 400, 2.7)
+    ex = oracle.solve(plan, x, q)
+    errs = []
+    for dr in (1e-2 * 2.7, 5e-3 * 2.7):
+        pl = oracle.solve(plan, x, q, dipole="layers", dr=dr)
+        errs.append(np.abs(pl["phi"] - ex["phi"]).max())
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.05)
+    pl = oracle.solve(plan, x, q, dipole="layers", dr=1e-4 * 2.7)
+    assert np.abs(pl["phi"] - ex["phi"]).max() < 1e-7 * np.abs(ex["phi"]).max()
+
+
+# ---------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("bc", [oracle.BC_PERIODIC, oracle.BC_METALLIC, oracle.BC_SLAB])
+def test_adjoint_charge_derivative_exact(bc):
+    """E is exactly quadratic in q: central differences along neutral
+    directions e_j - e_k are exact up to rounding; Euler: sum q dE/dq = 2E."""
+    rng = np.random.default_rng(20 + bc)
+    x, q = _rand_system(rng, 8, bc)
+    plan = oracle.make_plan(1.0, bc, 8, 1000, 600, 2.7)
+    E, dx, dq = oracle.adjoint(plan, x, q)
+    assert E == pytest.approx(oracle.solve(plan, x, q)["energy"], rel=1e-13)
+    assert abs(np.sum(q * dq) - 2 * E) < 1e-11 * abs(E)
+    for j, k in ((0, 1), (2, 5), (3, 7)):
+        h = 1e-2
+        d = np.zeros_like(q)
+        d[j], d[k] = h, -h
+        fd = (oracle.solve(plan, x, q + d)["energy"] - oracle.solve(plan, x, q - d)["energy"]) / (2 * h)
+        assert fd == pytest.approx(dq[j] - dq[k], rel=1e-9, abs=1e-9)
+
+
+@pytest.mark.parametrize("bc", [oracle.BC_PERIODIC, oracle.BC_METALLIC, oracle.BC_SLAB])
+def test_adjoint_position_derivative_fd(bc):
+    """dE/dx against central differences with Richardson extrapolation."""
+    rng = np.random.default_rng(30 + bc)
+    x, q = _rand_system(rng, 6, bc)
+    x = 0.1 + 0.8 * x   # keep away from walls so that +-h stays inside
+    plan = oracle.make_plan(1.0, bc, 8, 1000, 600, 2.7)
+    E, dx, dq = oracle.adjoint(plan, x, q)
+
+    def fd(i, a, h):
+        e = np.zeros_like(x)
+        e[i, a] = h
+        return (oracle.solve(plan, x + e, q)["energy"] - oracle.solve(plan, x - e, q)["energy"]) / (2 * h)
+
+    for i, a in ((0, 0), (3, 2), (5, 1)):
+        h = 1e-3
+        rich = (4 * fd(i, a, h / 2) - fd(i, a, h)) / 3
+        assert rich == pytest.approx(dx[i, a], rel=1e-7, abs=1e-7 * np.abs(dx).max())
+
+
+def test_adjoint_force_vs_field_force():
+    """The field force -q grad(phi) (A held fixed, Sec. III) and the exact
+    -dE/dx agree to the method accuracy (they differ only through the fit)."""
+    rng = np.random.default_rng(40)
+    x, q = _rand_system(rng, 10, oracle.BC_PERIODIC)
+    plan = oracle.make_plan(1.0, oracle.BC_PERIODIC, 16, 2500, 900, 2.7)
+    E, dx, dq = oracle.adjoint(plan, x, q)
+    F = oracle.solve(plan, x, q)["forces"]
+    assert np.abs(-dx - F).max() < 1e-6 * np.abs(F).max()
