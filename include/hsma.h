@@ -1,0 +1,183 @@
+/*
+ * hsma.h -- C ABI of the MI355X (gfx950) hot path of the harmonic surface
+ * mapping algorithm (HSMA) of Zhao, Liang & Xu, "Harmonic surface mapping
+ * algorithm for fast electrostatic sums", arXiv:1806.04801.
+ *
+ * Problem (paper Sec. II, Eq. (sum)): N point charges q_j at r_j in a cube of
+ * side L with a boundary condition represented by image charges; in Gaussian
+ * units the potential is Phi(r) = sum q / |r - r'| over sources and images.
+ * The library returns the energy E = 1/2 sum_i q_i phi_i, the per-particle
+ * potential phi_i (bare self term left out, self-images included) and the
+ * forces F_i = q_i E(r_i) = -q_i grad phi(r_i) with the harmonic coefficients
+ * held fixed (paper Sec. III, forces as gradients of the potential).
+ *
+ * Conventions shared by every entry point:
+ *   - Coordinates are API coordinates: [0, L)^3 for periodic and grounded
+ *     cube, [0, L) x [0, L) x [0, L/2] for the grounded slab.  Arrays of
+ *     positions and forces are N x 3 row-major doubles; charges N doubles.
+ *   - Periodic positions are wrapped into the box; grounded-cube and slab
+ *     positions must lie strictly inside (HSMA_E_OUT_OF_BOX otherwise).
+ *   - Periodic and slab systems must be neutral: |sum q| <= 1e-12 sum |q|
+ *     (HSMA_E_NOT_NEUTRAL).
+ *   - The periodic potential is defined up to a constant; the library fixes
+ *     it by A_00 = 0 (the constant harmonic carries no information in the
+ *     periodic residual of Sec. II.A).
+ *   - No exception crosses the ABI.  Every function returns a status; the
+ *     text of the last error of the calling thread is in hsma_last_error().
+ *     After an error the contents of output arrays are unspecified.
+ *   - The caller owns every array it passes.  A plan owns its device-resident
+ *     matrices and is immutable after creation: it may be used from several
+ *     host threads on distinct streams, each with its own workspace.
+ */
+#ifndef HSMA_H
+#define HSMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HSMA_BC_PERIODIC = 0,        /* periodic in x, y, z (Sec. II, periodic image sum) */
+    HSMA_BC_METALLIC = 1,        /* grounded cube: Eq. (diel) in the conducting limit gamma = -1 */
+    HSMA_BC_SLAB_METALLIC_Z = 2  /* periodic in x, y, grounded walls at z = 0 and z = L/2 (mirror
+                                    reflections plus periodic extension, Sec. I) */
+} hsma_bc;
+
+typedef enum {
+    HSMA_FP64 = 0,        /* every sum in double precision */
+    HSMA_FP32_COMP = 1    /* near and right-hand-side pair sums in single precision with
+                             two-sum compensated accumulation; basis, least squares, mapping,
+                             surface sum and final reductions in double precision */
+} hsma_precision;
+
+typedef enum {
+    HSMA_OK = 0,
+    HSMA_E_INVALID = -1,      /* bad argument (sizes, NULL, non-finite input, K < unknowns, R <= R0) */
+    HSMA_E_NOT_NEUTRAL = -2,  /* periodic or slab system with non-zero total charge */
+    HSMA_E_OUT_OF_BOX = -3,   /* grounded-cube or slab position on or outside a wall */
+    HSMA_E_NOMEM = -5,        /* device allocation failed or workspace too small */
+    HSMA_E_DEVICE = -6,       /* HIP runtime error */
+    HSMA_E_ILLCOND = -7       /* least-squares matrix numerically rank deficient */
+} hsma_status;
+
+typedef struct hsma_plan_s* hsma_plan;
+
+/* Full plan description; hsma_plan_create fills the defaults. */
+typedef struct {
+    double L;          /* box side (> 0) */
+    int bc;            /* hsma_bc */
+    int p;             /* harmonic truncation degree P >= 1 (Eq. (harmonic)); N_b = (P+1)^2 */
+    int M;             /* requested Fibonacci surface points; the plan uses the Hannay-Nye count
+                          2(F2+1) nearest to M (Sec. II.B), reported as M_eff */
+    int K;             /* monitoring points N_m (Sec. II.A); K >= unknowns */
+    double R;          /* auxiliary sphere radius R_s > sqrt(3) L / 2 (alpha > 1, Sec. III) */
+    int precision;     /* hsma_precision */
+    uint64_t seed;     /* SplitMix64 seed of the grounded-cube face monitoring points */
+} hsma_plan_desc;
+
+typedef struct {
+    int n_basis;       /* N_b = (P+1)^2 */
+    int n_unknowns;    /* fitted coefficients: N_b (grounded cube) or N_b - 1 (periodic, slab) */
+    int K;             /* monitoring points */
+    int n_check;       /* evaluation points of the right-hand side: K, or 2K with the twins */
+    int M_eff;         /* surface points 2(F2+1) */
+    int F1, F2;        /* Fibonacci pair of the surface quadrature */
+    double R0;         /* circumsphere radius sqrt(3) L / 2 */
+    double Rs;         /* auxiliary sphere radius */
+    int precision;
+    int bc;
+    size_t bytes_resident;  /* device bytes held by the plan */
+} hsma_plan_info_t;
+
+/* Optional device outputs of the intermediate stages (any pointer may be NULL). */
+typedef struct {
+    double* b;           /* K values of the least-squares right-hand side */
+    double* A;           /* N_b coefficients A_nm, index n^2 + n + m */
+    double* surf;        /* M_eff x 8: X, Y, Z, Q, p_x, p_y, p_z, 0 of the surface images */
+    double* phi_near;    /* N near-field potentials */
+    double* field_near;  /* N x 3 near fields */
+    double* phi_out;     /* N far-field potentials (surface images) */
+    double* field_out;   /* N x 3 far fields */
+} hsma_intermediates;
+
+/* Status text and the calling thread's last error message. */
+const char* hsma_status_string(int status);
+const char* hsma_last_error(void);
+int hsma_version(void);
+
+/*
+ * Preparation step (Sec. II.C, Table I): monitoring points (Fibonacci grid on
+ * the circumsphere with twins for periodic systems, seeded points on the faces
+ * of the grounded cube), the fitting matrix of real solid harmonics r^n Y_nm,
+ * its Householder QR, the pseudo-inverse R^-1 Q^T, the Hannay-Nye points and
+ * weights on the sphere R_s and the mapping matrix.  Runs on the current HIP
+ * device and keeps every matrix resident there.  *out receives the plan.
+ * Errors: HSMA_E_INVALID, HSMA_E_NOMEM, HSMA_E_DEVICE, HSMA_E_ILLCOND.
+ */
+hsma_status hsma_plan_create(double L, int bc, int p, int M, int K, double R, hsma_plan* out);
+hsma_status hsma_plan_create_ex(const hsma_plan_desc* desc, hsma_plan* out);
+void        hsma_plan_destroy(hsma_plan plan);
+hsma_status hsma_plan_info(hsma_plan plan, hsma_plan_info_t* info);
+
+/*
+ * Host copies of plan geometry, in centred coordinates (box centred at 0):
+ *   which = 0: monitoring points (K x 3)      w unused
+ *   which = 1: twin points (K x 3, periodic)  w unused
+ *   which = 2: surface points (M_eff x 3)     w = quadrature weights (M_eff)
+ * xyz and w are host arrays of the stated sizes (w may be NULL).
+ */
+hsma_status hsma_plan_points(hsma_plan plan, int which, double* xyz, double* w);
+
+/* Device bytes of workspace needed by the device entry points for N particles. */
+size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
+
+/*
+ * Update step (Sec. II.C) on host arrays: x (N x 3), q (N); outputs energy
+ * (one double), phi (N or NULL) and forces (N x 3 or NULL).  Allocates its
+ * own device buffers and synchronizes before returning.
+ */
+hsma_status hsma_energy_forces(hsma_plan plan, const double* x, const double* q, int64_t N,
+                               double* energy, double* phi, double* forces);
+
+/*
+ * Update step on device arrays (all pointers device memory of the plan's
+ * device): x (N x 3), q (N), phi (N or NULL), forces (N x 3 or NULL),
+ * workspace of hsma_workspace_bytes(plan, N) bytes, all work enqueued on
+ * `stream` (a hipStream_t; NULL = default stream).  energy is a host double
+ * written after the stream has drained (the call waits for it).  dbg (may be
+ * NULL) requests copies of the intermediate stages.
+ */
+hsma_status hsma_energy_forces_device(hsma_plan plan, const double* x, const double* q, int64_t N,
+                                      void* stream, void* workspace, size_t workspace_bytes,
+                                      double* energy, double* phi, double* forces,
+                                      const hsma_intermediates* dbg);
+
+/*
+ * Exact gradient of the computed energy (adjoint of the update step):
+ * dEdx (N x 3) and dEdq (N) on the device, energy on the host.  Unlike the
+ * forces above, -dEdx also differentiates the least-squares coefficients with
+ * respect to the positions.  Same conventions as hsma_energy_forces_device.
+ */
+hsma_status hsma_energy_grad_device(hsma_plan plan, const double* x, const double* q, int64_t N,
+                                    void* stream, void* workspace, size_t workspace_bytes,
+                                    double* energy, double* dEdx, double* dEdq);
+
+/*
+ * Kernel timing for measurement: when enabled, the library records HIP events
+ * around every launch of the near-field pair kernel (kernel class 0), the
+ * right-hand-side pair kernel (1) and the surface kernel (2) on the stream it
+ * launches them on.  hsma_timing_read waits for the recorded events, returns
+ * the summed milliseconds and launch counts per class (arrays of 3) and
+ * clears the record.
+ */
+hsma_status hsma_timing_enable(int enable);
+hsma_status hsma_timing_read(double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSMA_H */

@@ -1,0 +1,303 @@
+// C ABI of the HSMA library: argument checks, plans, host and device entry
+// points, kernel timing.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hsma_internal.h"
+#include "solve.h"
+
+namespace hsma {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+hsma_status fail(hsma_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+// ---------------------------------------------------------------- timing
+struct TimingRec {
+    int cls;
+    hipEvent_t a, b;
+};
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimingRec> g_trecs;
+static std::vector<hipEvent_t> g_tpool;
+static thread_local hipEvent_t g_pending[3] = {nullptr, nullptr, nullptr};
+
+static hipEvent_t take_event() {
+    if (!g_tpool.empty()) {
+        hipEvent_t e = g_tpool.back();
+        g_tpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void timing_begin(int cls, hipStream_t s) {
+    if (!g_timing) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s) == hipSuccess) g_pending[cls] = e;
+}
+
+void timing_end(int cls, hipStream_t s) {
+    if (!g_timing || g_pending[cls] == nullptr) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s) == hipSuccess) g_trecs.push_back({cls, g_pending[cls], e});
+    g_pending[cls] = nullptr;
+}
+
+}  // namespace hsma
+
+using namespace hsma;
+
+extern "C" {
+
+const char* hsma_status_string(int st) {
+    switch (st) {
+        case HSMA_OK: return "ok";
+        case HSMA_E_INVALID: return "invalid argument";
+        case HSMA_E_NOT_NEUTRAL: return "system not neutral";
+        case HSMA_E_OUT_OF_BOX: return "position outside the box";
+        case HSMA_E_NOMEM: return "out of device memory or workspace too small";
+        case HSMA_E_DEVICE: return "HIP runtime error";
+        case HSMA_E_ILLCOND: return "fitting matrix rank deficient";
+        default: return "unknown status";
+    }
+}
+
+const char* hsma_last_error(void) { return g_last_error.c_str(); }
+
+int hsma_version(void) { return 1; }
+
+hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
+    if (d == nullptr || out == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (!(d->L > 0.0) || !std::isfinite(d->L)) return fail(HSMA_E_INVALID, "L must be > 0");
+    if (d->bc < 0 || d->bc > 2) return fail(HSMA_E_INVALID, "unknown boundary condition");
+    if (d->p < 1 || d->p > 40) return fail(HSMA_E_INVALID, "p must be in [1, 40]");
+    if (d->precision != HSMA_FP64 && d->precision != HSMA_FP32_COMP)
+        return fail(HSMA_E_INVALID, "unknown precision");
+    const double R0 = std::sqrt(3.0) * d->L / 2.0;
+    if (!(d->R > R0) || !std::isfinite(d->R))
+        return fail(HSMA_E_INVALID, "R must exceed the circumsphere radius sqrt(3) L / 2");
+    const int nb = (d->p + 1) * (d->p + 1);
+    const int nu = (d->bc == HSMA_BC_METALLIC) ? nb : nb - 1;
+    if (d->K < nu || d->K > (1 << 24)) return fail(HSMA_E_INVALID, "K must be >= number of unknowns");
+    if (d->M < 4 || d->M > (1 << 22)) return fail(HSMA_E_INVALID, "M out of range");
+    hsma_plan_s* pl = new (std::nothrow) hsma_plan_s();
+    if (pl == nullptr) return fail(HSMA_E_NOMEM, "host allocation failed");
+    pl->desc = *d;
+    pl->bc = d->bc;
+    pl->img = (d->bc == HSMA_BC_METALLIC) ? IMG_METALLIC : IMG_PERIODIC;
+    pl->p = d->p;
+    pl->nb = nb;
+    pl->nu = nu;
+    pl->K = d->K;
+    pl->L = d->L;
+    pl->R0 = R0;
+    pl->Rs = d->R;
+    pl->precision = d->precision;
+    hsma_status st = build_plan(pl);
+    if (st != HSMA_OK) {
+        free_plan(pl);
+        delete pl;
+        return st;
+    }
+    if (pl->M < 2 * nb) {
+        free_plan(pl);
+        delete pl;
+        return fail(HSMA_E_INVALID, "too few surface points for the degree (M_eff < 2 N_b)");
+    }
+    *out = pl;
+    return HSMA_OK;
+}
+
+hsma_status hsma_plan_create(double L, int bc, int p, int M, int K, double R, hsma_plan* out) {
+    hsma_plan_desc d;
+    std::memset(&d, 0, sizeof(d));
+    d.L = L;
+    d.bc = bc;
+    d.p = p;
+    d.M = M;
+    d.K = K;
+    d.R = R;
+    d.precision = HSMA_FP64;
+    d.seed = 12345;
+    return hsma_plan_create_ex(&d, out);
+}
+
+void hsma_plan_destroy(hsma_plan pl) {
+    if (pl == nullptr) return;
+    free_plan(pl);
+    delete pl;
+}
+
+hsma_status hsma_plan_info(hsma_plan pl, hsma_plan_info_t* info) {
+    if (pl == nullptr || info == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
+    info->n_basis = pl->nb;
+    info->n_unknowns = pl->nu;
+    info->K = pl->K;
+    info->n_check = pl->nchk;
+    info->M_eff = pl->M;
+    info->F1 = pl->F1;
+    info->F2 = pl->F2;
+    info->R0 = pl->R0;
+    info->Rs = pl->Rs;
+    info->precision = pl->precision;
+    info->bc = pl->bc;
+    info->bytes_resident = pl->bytes;
+    return HSMA_OK;
+}
+
+hsma_status hsma_plan_points(hsma_plan pl, int which, double* xyz, double* w) {
+    if (pl == nullptr || xyz == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
+    if (which == 0) {
+        std::memcpy(xyz, pl->chk.data(), sizeof(double) * 3 * pl->K);
+    } else if (which == 1) {
+        if (pl->img != IMG_PERIODIC) return fail(HSMA_E_INVALID, "no twin points for this plan");
+        std::memcpy(xyz, pl->chk.data() + 3 * (size_t)pl->K, sizeof(double) * 3 * pl->K);
+    } else if (which == 2) {
+        std::memcpy(xyz, pl->spts.data(), sizeof(double) * 3 * pl->M);
+        if (w) std::memcpy(w, pl->swts.data(), sizeof(double) * pl->M);
+    } else {
+        return fail(HSMA_E_INVALID, "which must be 0, 1 or 2");
+    }
+    return HSMA_OK;
+}
+
+size_t hsma_workspace_bytes(hsma_plan pl, int64_t N) {
+    if (pl == nullptr || N < 0) return 0;
+    return make_layout(pl, N, true).total;
+}
+
+static hsma_status check_sizes(hsma_plan pl, int64_t N) {
+    if (pl == nullptr) return fail(HSMA_E_INVALID, "NULL plan");
+    if (N < 1 || N > (int64_t)1 << 28) return fail(HSMA_E_INVALID, "N out of range");
+    if (pl->bc == HSMA_BC_SLAB_METALLIC_Z && N > (int64_t)1 << 27)
+        return fail(HSMA_E_INVALID, "N out of range for the slab");
+    return HSMA_OK;
+}
+
+hsma_status hsma_energy_forces_device(hsma_plan pl, const double* x, const double* q, int64_t N,
+                                      void* stream, void* workspace, size_t workspace_bytes,
+                                      double* energy, double* phi, double* forces,
+                                      const hsma_intermediates* dbg) {
+    hsma_status st = check_sizes(pl, N);
+    if (st != HSMA_OK) return st;
+    if (x == nullptr || q == nullptr || workspace == nullptr || energy == nullptr)
+        return fail(HSMA_E_INVALID, "NULL argument");
+    const Layout ly = make_layout(pl, N, false);
+    if (workspace_bytes < ly.total) return fail(HSMA_E_NOMEM, "workspace too small");
+    HSMA_HIP(hipSetDevice(pl->device));
+    hipStream_t s = (hipStream_t)stream;
+    st = forward(pl, ly, x, q, (char*)workspace, s, phi, forces, dbg);
+    if (st != HSMA_OK) return st;
+    return read_result(ly, (char*)workspace, s, energy);
+}
+
+hsma_status hsma_energy_grad_device(hsma_plan pl, const double* x, const double* q, int64_t N,
+                                    void* stream, void* workspace, size_t workspace_bytes,
+                                    double* energy, double* dEdx, double* dEdq) {
+    hsma_status st = check_sizes(pl, N);
+    if (st != HSMA_OK) return st;
+    if (x == nullptr || q == nullptr || workspace == nullptr || energy == nullptr ||
+        dEdx == nullptr || dEdq == nullptr)
+        return fail(HSMA_E_INVALID, "NULL argument");
+    const Layout ly = make_layout(pl, N, true);
+    if (workspace_bytes < ly.total) return fail(HSMA_E_NOMEM, "workspace too small");
+    HSMA_HIP(hipSetDevice(pl->device));
+    hipStream_t s = (hipStream_t)stream;
+    st = forward(pl, ly, x, q, (char*)workspace, s, nullptr, nullptr, nullptr);
+    if (st != HSMA_OK) return st;
+    st = backward(pl, ly, (char*)workspace, s, dEdx, dEdq);
+    if (st != HSMA_OK) return st;
+    return read_result(ly, (char*)workspace, s, energy);
+}
+
+hsma_status hsma_energy_forces(hsma_plan pl, const double* x, const double* q, int64_t N,
+                               double* energy, double* phi, double* forces) {
+    hsma_status st = check_sizes(pl, N);
+    if (st != HSMA_OK) return st;
+    if (x == nullptr || q == nullptr || energy == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
+    // host-side validation before any device work
+    double qs = 0.0, qa = 0.0;
+    const double h = 0.5 * pl->L;
+    for (int64_t i = 0; i < N; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            const double v = x[3 * i + a];
+            if (!std::isfinite(v)) return fail(HSMA_E_INVALID, "non-finite position");
+            if (pl->bc == HSMA_BC_METALLIC && !(std::fabs(v - h) < h))
+                return fail(HSMA_E_OUT_OF_BOX, "position on or outside a grounded wall");
+            if (pl->bc == HSMA_BC_SLAB_METALLIC_Z && a == 2 && !(v > 0.0 && v < h))
+                return fail(HSMA_E_OUT_OF_BOX, "position on or outside a slab wall");
+        }
+        if (!std::isfinite(q[i])) return fail(HSMA_E_INVALID, "non-finite charge");
+        qs += q[i];
+        qa += std::fabs(q[i]);
+    }
+    if (pl->bc != HSMA_BC_METALLIC && std::fabs(qs) > 1e-12 * qa)
+        return fail(HSMA_E_NOT_NEUTRAL, "periodic/slab system is not neutral");
+    HSMA_HIP(hipSetDevice(pl->device));
+    const Layout ly = make_layout(pl, N, false);
+    char* base = nullptr;
+    const size_t nx = sizeof(double) * 3 * (size_t)N, nq = sizeof(double) * (size_t)N;
+    const size_t off_x = 0, off_q = (nx + 255) & ~(size_t)255,
+                 off_phi = off_q + ((nq + 255) & ~(size_t)255),
+                 off_f = off_phi + ((nq + 255) & ~(size_t)255),
+                 off_ws = off_f + ((nx + 255) & ~(size_t)255);
+    if (hipMalloc((void**)&base, off_ws + ly.total) != hipSuccess)
+        return fail(HSMA_E_NOMEM, "device allocation failed");
+    hipStream_t s = nullptr;
+    auto done = [&](hsma_status r) { hipFree(base); return r; };
+    if (hipMemcpy(base + off_x, x, nx, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + off_q, q, nq, hipMemcpyHostToDevice) != hipSuccess)
+        return done(fail(HSMA_E_DEVICE, "host to device copy failed"));
+    st = forward(pl, ly, (double*)(base + off_x), (double*)(base + off_q), base + off_ws, s,
+                 (double*)(base + off_phi), (double*)(base + off_f), nullptr);
+    if (st != HSMA_OK) return done(st);
+    st = read_result(ly, base + off_ws, s, energy);
+    if (st != HSMA_OK) return done(st);
+    if (phi && hipMemcpy(phi, base + off_phi, nq, hipMemcpyDeviceToHost) != hipSuccess)
+        return done(fail(HSMA_E_DEVICE, "device to host copy failed"));
+    if (forces && hipMemcpy(forces, base + off_f, nx, hipMemcpyDeviceToHost) != hipSuccess)
+        return done(fail(HSMA_E_DEVICE, "device to host copy failed"));
+    return done(HSMA_OK);
+}
+
+hsma_status hsma_timing_enable(int enable) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = enable != 0;
+    return HSMA_OK;
+}
+
+hsma_status hsma_timing_read(double* ms, int64_t* launches) {
+    if (ms == nullptr || launches == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (int c = 0; c < 3; ++c) { ms[c] = 0.0; launches[c] = 0; }
+    for (auto& r : g_trecs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(HSMA_E_DEVICE, "event wait failed");
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            ms[r.cls] += t;
+            launches[r.cls] += 1;
+        }
+        g_tpool.push_back(r.a);
+        g_tpool.push_back(r.b);
+    }
+    g_trecs.clear();
+    return HSMA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal declarations of the HSMA library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hsma.h"
+
+namespace hsma {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+hsma_status fail(hsma_status st, const std::string& msg);
+#define HSMA_HIP(call)                                                               \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::hsma::fail(HSMA_E_DEVICE, std::string(#call) + ": " +          \
+                                               hipGetErrorString(e_));               \
+    } while (0)
+
+// ---------------------------------------------------------------- geometry modes
+// Image maps of the 3x3x3 near block (k in {-1,0,1}^3), applied to a source r:
+//   IMG_PERIODIC: r + kL,                  charge q           (periodic sum)
+//   IMG_METALLIC: (-1)^k o r + kL,         charge (-1)^|k| q  (Eq. (diel), gamma = -1)
+//   IMG_FREE    : r only (no images)
+enum { IMG_PERIODIC = 0, IMG_METALLIC = 1, IMG_FREE = 2 };
+
+// Single-precision record of a point (target or source): the centred
+// coordinate c, and the shifted coordinates c - L/2 and c + L/2, each split
+// into a float pair hi + lo, plus the charge.  Differences of hi parts of
+// nearby points are exact (Sterbenz), so image distances keep their relative
+// accuracy for close pairs and near walls.
+//   v[0]  = (h0x, h0y, h0z, q)
+//   v[1]  = (l0x, l0y, l0z, 0)
+//   v[2]  = (hpx, hpy, hpz, hmx)      p: c - L/2, m: c + L/2
+//   v[3]  = (hmy, hmz, lpx, lpy)
+//   v[4]  = (lpz, lmx, lmy, lmz)
+struct Rec32 {
+    float4 v[5];
+};
+
+// Workspace / launch geometry of a pair-kernel launch.
+struct PairGeom {
+    int nt = 0;       // targets
+    int ns = 0;       // sources
+    int tpl = 1;      // targets per lane
+    int ntb = 0;      // target blocks (grid.x)
+    int nt_pad = 0;   // ntb * 256 * tpl
+    int S = 1;        // source chunks (grid.y)
+    int chunk = 0;    // sources per chunk
+};
+PairGeom pair_geometry(int nt, int ns, int tpl, int ncu);
+
+// ---------------------------------------------------------------- plan
+struct hsma_plan_impl;
+}  // namespace hsma
+
+struct hsma_plan_s {
+    hsma_plan_desc desc{};
+    int device = 0;
+    int ncu = 256;
+    int bc = 0;
+    int img = 0;          // image mode of the near block (periodic also for slab)
+    int p = 0, nb = 0, nu = 0, K = 0, nchk = 0, M = 0, F1 = 0, F2 = 0;
+    double L = 1.0, R0 = 0.0, Rs = 0.0;
+    int precision = 0;
+    // host geometry (centred)
+    std::vector<double> chk;    // nchk x 3: monitoring points then twins
+    std::vector<double> spts;   // M x 3
+    std::vector<double> swts;   // M
+    // device-resident matrices (row-major)
+    double* d_P = nullptr;      // nu x K   pseudo-inverse R^-1 Q^T
+    double* d_Wq = nullptr;     // M x nb   charge rows  (w_j / (4 pi Rs)) n B_k(R_j)
+    double* d_Wp = nullptr;     // M x nb   dipole rows  -(w_j / (4 pi)) B_k(R_j)
+    double* d_spos = nullptr;   // M x 4    surface points (X, Y, Z, 0)
+    double4* d_chk64 = nullptr; // nchk     check points (x, y, z, 0)
+    hsma::Rec32* d_chk32 = nullptr;  // nchk single-precision records
+    size_t bytes = 0;
+};
+
+namespace hsma {
+
+// ---------------------------------------------------------------- kernels
+// Pair sums (pairs.hip).  out layout: out[(c * ncomp + comp) * nt_pad + t],
+// comp 0 = potential, 1..3 = field E = -grad phi; c = source chunk.
+hipError_t launch_pair_f64(int img, bool field, bool self, const double4* tgt, const double4* src,
+                           const PairGeom& g, double L, double* out, hipStream_t s);
+hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, const Rec32* src,
+                           const PairGeom& g, float L, double* out, hipStream_t s);
+// Surface images (X, Y, Z, Q, px, py, pz, 0) at targets (x, y, z, q).
+hipError_t launch_surface_f64(const double4* tgt, const double* surf, const PairGeom& g,
+                              double* out, hipStream_t s);
+// Sum the chunks of a pair-kernel output: res[comp * ld + t] = sum_c out[...].
+hipError_t launch_chunk_reduce(const double* out, const PairGeom& g, int ncomp, double* res, int ld,
+                               hipStream_t s);
+// Records from centred double positions.
+hipError_t launch_make_rec32(const double4* p, int n, double L, Rec32* out, hipStream_t s);
+
+// Plan kernels (plan.hip).
+hipError_t launch_basis(const double* pts, int npts, int P, double invR0, double* out, int ld_pt,
+                        int ld_k, int k0, hipStream_t s);
+
+// Timing hooks (api.hip).
+void timing_begin(int cls, hipStream_t s);
+void timing_end(int cls, hipStream_t s);
+
+}  // namespace hsma

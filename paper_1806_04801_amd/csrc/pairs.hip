@@ -1,0 +1,470 @@
+// Pair-sum kernels of the HSMA hot path (gfx950, wave64).
+//
+// One kernel family evaluates, for a set of targets, the Coulomb potential and
+// field of a set of sources together with their 27 images in the 3x3x3 block
+// of boxes around the central box (the charges inside the auxiliary sphere,
+// Sec. II.A; periodic images of Sec. II and the reflected images of Eq. (diel)
+// with gamma = -1).  It serves the near-field sum at the particles (Sec. II.C,
+// update step), the right-hand side at the monitoring points (Sec. II.A) and
+// the two adjoint sums.
+//
+// Layout of the work: a workgroup of 256 lanes owns 256*T targets (T per
+// lane, kept in registers) and one chunk of sources (grid.y).  Sources are
+// read at wave-uniform addresses, so they stream through scalar loads into
+// SGPRs and feed the vector ALUs directly: no LDS staging and no barriers.
+// Images are applied to the per-axis differences: each axis has three
+// differences (k = -1, 0, +1) and their squares, so an image costs one add
+// for r^2, one rsqrt, and the potential/field updates.  Per-chunk results go to
+// a partial buffer that a second kernel sums in a fixed order, so results do
+// not depend on scheduling.
+#include "hsma_internal.h"
+
+namespace hsma {
+
+constexpr int WG = 256;
+
+// 1/sqrt(x) in double: hardware estimate (about 2^-24 relative) refined by one
+// third-order Newton step, y <- y + y e (1/2 + 3/8 e), e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double t = x * y;
+    double e = __builtin_fma(-t, y, 1.0);
+    double c = __builtin_fma(e, 0.375, 0.5);
+    return __builtin_fma(y * e, c, y);
+}
+
+// Per-axis target-minus-image differences for k = -1, 0, +1 (index k + 1).
+template <int IMG>
+__device__ __forceinline__ void diffs_f64(double t, double s, double L, double (&d)[3]) {
+    double d0 = t - s;
+    d[1] = d0;
+    if (IMG == IMG_PERIODIC) {          // image s + kL
+        d[0] = d0 + L;
+        d[2] = d0 - L;
+    } else if (IMG == IMG_METALLIC) {   // image -s + kL
+        double sm = t + s;
+        d[0] = sm + L;
+        d[2] = sm - L;
+    } else {
+        d[0] = d[2] = 0.0;
+    }
+}
+
+// Sum over the images of one source: pot = sum s_k / |d|, f = sum s_k d / |d|^3.
+template <int IMG, bool FIELD, bool SELF>
+__device__ __forceinline__ void images_f64(const double (&dx)[3], const double (&dy)[3],
+                                           const double (&dz)[3], double& pot, double& fx,
+                                           double& fy, double& fz) {
+    constexpr int lo = (IMG == IMG_FREE) ? 1 : 0;
+    constexpr int hi = (IMG == IMG_FREE) ? 2 : 3;
+    double sx[3], sy[3], sz[3];
+#pragma unroll
+    for (int a = lo; a < hi; ++a) {
+        sx[a] = dx[a] * dx[a];
+        sy[a] = dy[a] * dy[a];
+        sz[a] = dz[a] * dz[a];
+    }
+    pot = fx = fy = fz = 0.0;
+#pragma unroll
+    for (int a = lo; a < hi; ++a) {
+#pragma unroll
+        for (int b = lo; b < hi; ++b) {
+            const double sxy = sx[a] + sy[b];
+#pragma unroll
+            for (int c = lo; c < hi; ++c) {
+                const double r2 = sxy + sz[c];
+                double y = rsqrt_f64(r2);
+                if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > 0.0) ? y : 0.0;
+                const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
+                pot = neg ? pot - y : pot + y;
+                if (FIELD) {
+                    double y3 = y * y * y;
+                    y3 = neg ? -y3 : y3;
+                    fx = __builtin_fma(y3, dx[a], fx);
+                    fy = __builtin_fma(y3, dy[b], fy);
+                    fz = __builtin_fma(y3, dz[c], fz);
+                }
+            }
+        }
+    }
+}
+
+template <int IMG, bool FIELD, bool SELF, int T>
+__global__ void __launch_bounds__(WG)
+k_pair_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ src, int ns,
+           int chunk, double L, double* __restrict__ out, int nt_pad) {
+    const int c = blockIdx.y;
+    const int j0 = c * chunk;
+    const int j1 = min(j0 + chunk, ns);
+    double tx[T], ty[T], tz[T], ap[T], ax[T], ay[T], az[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const double4 r = tgt[min(t, nt - 1)];
+        tx[u] = r.x; ty[u] = r.y; tz[u] = r.z;
+        ap[u] = ax[u] = ay[u] = az[u] = 0.0;
+    }
+    for (int j = j0; j < j1; ++j) {
+        const double4 s = src[j];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            double dx[3], dy[3], dz[3];
+            diffs_f64<IMG>(tx[u], s.x, L, dx);
+            diffs_f64<IMG>(ty[u], s.y, L, dy);
+            diffs_f64<IMG>(tz[u], s.z, L, dz);
+            double pot, fx, fy, fz;
+            images_f64<IMG, FIELD, SELF>(dx, dy, dz, pot, fx, fy, fz);
+            ap[u] = __builtin_fma(s.w, pot, ap[u]);
+            if (FIELD) {
+                ax[u] = __builtin_fma(s.w, fx, ax[u]);
+                ay[u] = __builtin_fma(s.w, fy, ay[u]);
+                az[u] = __builtin_fma(s.w, fz, az[u]);
+            }
+        }
+    }
+    constexpr int ncomp = FIELD ? 4 : 1;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        double* o = out + (size_t)c * ncomp * nt_pad + t;
+        o[0] = ap[u];
+        if (FIELD) {
+            o[(size_t)nt_pad] = ax[u];
+            o[(size_t)2 * nt_pad] = ay[u];
+            o[(size_t)3 * nt_pad] = az[u];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- single precision
+// Error-free sum (Knuth's TwoSum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float b) {
+    const float s = hi + b;
+    const float bb = s - hi;
+    const float e = (hi - (s - bb)) + (b - bb);
+    hi = s;
+    lo += e;
+}
+
+struct Pt32 {
+    float h0[3], l0[3], hp[3], lp[3], hm[3], lm[3];
+};
+
+__device__ __forceinline__ Pt32 load_pt32(const Rec32& r) {
+    Pt32 p;
+    p.h0[0] = r.v[0].x; p.h0[1] = r.v[0].y; p.h0[2] = r.v[0].z;
+    p.l0[0] = r.v[1].x; p.l0[1] = r.v[1].y; p.l0[2] = r.v[1].z;
+    p.hp[0] = r.v[2].x; p.hp[1] = r.v[2].y; p.hp[2] = r.v[2].z;
+    p.hm[0] = r.v[2].w; p.hm[1] = r.v[3].x; p.hm[2] = r.v[3].y;
+    p.lp[0] = r.v[3].z; p.lp[1] = r.v[3].w; p.lp[2] = r.v[4].x;
+    p.lm[0] = r.v[4].y; p.lm[1] = r.v[4].z; p.lm[2] = r.v[4].w;
+    return p;
+}
+
+// Differences along axis a for k = -1, 0, +1, from the split coordinates.
+//   periodic: c_t - c_s - kL;  k=+1: (c_t - L/2) - (c_s + L/2),  k=-1: (c_t + L/2) - (c_s - L/2)
+//   metallic: c_t + c_s - kL;  k=+1: (c_t - L/2) + (c_s - L/2),  k=-1: (c_t + L/2) + (c_s + L/2)
+template <int IMG>
+__device__ __forceinline__ void diffs_f32(const Pt32& t, const Pt32& s, int a, float (&d)[3]) {
+    d[1] = (t.h0[a] - s.h0[a]) + (t.l0[a] - s.l0[a]);
+    if (IMG == IMG_PERIODIC) {
+        d[2] = (t.hp[a] - s.hm[a]) + (t.lp[a] - s.lm[a]);
+        d[0] = (t.hm[a] - s.hp[a]) + (t.lm[a] - s.lp[a]);
+    } else if (IMG == IMG_METALLIC) {
+        d[2] = (t.hp[a] + s.hp[a]) + (t.lp[a] + s.lp[a]);
+        d[0] = (t.hm[a] + s.hm[a]) + (t.lm[a] + s.lm[a]);
+    } else {
+        d[0] = d[2] = 0.0f;
+    }
+}
+
+template <int IMG, bool FIELD, bool SELF>
+__device__ __forceinline__ void images_f32(const float (&dx)[3], const float (&dy)[3],
+                                           const float (&dz)[3], float& pot, float& fx,
+                                           float& fy, float& fz) {
+    constexpr int lo = (IMG == IMG_FREE) ? 1 : 0;
+    constexpr int hi = (IMG == IMG_FREE) ? 2 : 3;
+    float sx[3], sy[3], sz[3];
+#pragma unroll
+    for (int a = lo; a < hi; ++a) {
+        sx[a] = dx[a] * dx[a];
+        sy[a] = dy[a] * dy[a];
+        sz[a] = dz[a] * dz[a];
+    }
+    pot = fx = fy = fz = 0.0f;
+#pragma unroll
+    for (int a = lo; a < hi; ++a) {
+#pragma unroll
+        for (int b = lo; b < hi; ++b) {
+            const float sxy = sx[a] + sy[b];
+#pragma unroll
+            for (int c = lo; c < hi; ++c) {
+                const float r2 = sxy + sz[c];
+                float y = __builtin_amdgcn_rsqf(r2);
+                if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > 0.0f) ? y : 0.0f;
+                const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
+                pot = neg ? pot - y : pot + y;
+                if (FIELD) {
+                    float y3 = y * y * y;
+                    y3 = neg ? -y3 : y3;
+                    fx = __builtin_fmaf(y3, dx[a], fx);
+                    fy = __builtin_fmaf(y3, dy[b], fy);
+                    fz = __builtin_fmaf(y3, dz[c], fz);
+                }
+            }
+        }
+    }
+}
+
+template <int IMG, bool FIELD, bool SELF, int T>
+__global__ void __launch_bounds__(WG)
+k_pair_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src, int ns,
+           int chunk, double* __restrict__ out, int nt_pad) {
+    const int c = blockIdx.y;
+    const int j0 = c * chunk;
+    const int j1 = min(j0 + chunk, ns);
+    Pt32 tp[T];
+    float ph[T], pl[T], xh[T], xl[T], yh[T], yl[T], zh[T], zl[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        tp[u] = load_pt32(tgt[min(t, nt - 1)]);
+        ph[u] = pl[u] = xh[u] = xl[u] = yh[u] = yl[u] = zh[u] = zl[u] = 0.0f;
+    }
+    for (int j = j0; j < j1; ++j) {
+        const Rec32 rs = src[j];
+        const Pt32 sp = load_pt32(rs);
+        const float q = rs.v[0].w;
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            float dx[3], dy[3], dz[3];
+            diffs_f32<IMG>(tp[u], sp, 0, dx);
+            diffs_f32<IMG>(tp[u], sp, 1, dy);
+            diffs_f32<IMG>(tp[u], sp, 2, dz);
+            float pot, fx, fy, fz;
+            images_f32<IMG, FIELD, SELF>(dx, dy, dz, pot, fx, fy, fz);
+            two_sum_acc(ph[u], pl[u], q * pot);
+            if (FIELD) {
+                two_sum_acc(xh[u], xl[u], q * fx);
+                two_sum_acc(yh[u], yl[u], q * fy);
+                two_sum_acc(zh[u], zl[u], q * fz);
+            }
+        }
+    }
+    constexpr int ncomp = FIELD ? 4 : 1;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        double* o = out + (size_t)c * ncomp * nt_pad + t;
+        o[0] = (double)ph[u] + (double)pl[u];
+        if (FIELD) {
+            o[(size_t)nt_pad] = (double)xh[u] + (double)xl[u];
+            o[(size_t)2 * nt_pad] = (double)yh[u] + (double)yl[u];
+            o[(size_t)3 * nt_pad] = (double)zh[u] + (double)zl[u];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- surface images
+// Potential and field at targets of M surface points carrying a charge Q_j and
+// a point dipole p_j (Sec. II.B; the dipole is the exact limit of the central
+// difference of Eq. (cd)):
+//   phi = sum Q/|d| + p.d/|d|^3,  E = sum d (Q/|d|^3 + 3 p.d/|d|^5) - p/|d|^3.
+template <int T>
+__global__ void __launch_bounds__(WG)
+k_surface_f64(const double4* __restrict__ tgt, int nt, const double* __restrict__ surf, int ns,
+              int chunk, double* __restrict__ out, int nt_pad) {
+    const int c = blockIdx.y;
+    const int j0 = c * chunk;
+    const int j1 = min(j0 + chunk, ns);
+    double tx[T], ty[T], tz[T], ap[T], ax[T], ay[T], az[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const double4 r = tgt[min(t, nt - 1)];
+        tx[u] = r.x; ty[u] = r.y; tz[u] = r.z;
+        ap[u] = ax[u] = ay[u] = az[u] = 0.0;
+    }
+    for (int j = j0; j < j1; ++j) {
+        const double* s = surf + 8 * (size_t)j;
+        const double X = s[0], Y = s[1], Z = s[2], Q = s[3], px = s[4], py = s[5], pz = s[6];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double dx = tx[u] - X, dy = ty[u] - Y, dz = tz[u] - Z;
+            const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+            const double y = rsqrt_f64(r2);
+            const double y2 = y * y;
+            const double y3 = y2 * y;
+            const double pd = __builtin_fma(px, dx, __builtin_fma(py, dy, pz * dz));
+            ap[u] += __builtin_fma(Q, y, pd * y3);
+            const double g = y3 * __builtin_fma(3.0 * pd, y2, Q);
+            ax[u] += __builtin_fma(g, dx, -px * y3);
+            ay[u] += __builtin_fma(g, dy, -py * y3);
+            az[u] += __builtin_fma(g, dz, -pz * y3);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        double* o = out + (size_t)c * 4 * nt_pad + t;
+        o[0] = ap[u];
+        o[(size_t)nt_pad] = ax[u];
+        o[(size_t)2 * nt_pad] = ay[u];
+        o[(size_t)3 * nt_pad] = az[u];
+    }
+}
+
+// ---------------------------------------------------------------- helpers
+__global__ void k_chunk_reduce(const double* __restrict__ out, int S, int nt, int nt_pad, int ncomp,
+                               double* __restrict__ res, int ld) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nt * ncomp) return;
+    const int comp = idx / nt, t = idx - comp * nt;
+    double acc = 0.0;
+    for (int c = 0; c < S; ++c) acc += out[((size_t)c * ncomp + comp) * nt_pad + t];
+    res[(size_t)comp * ld + t] = acc;
+}
+
+__device__ __forceinline__ void split2(double v, float& h, float& l) {
+    h = (float)v;
+    l = (float)(v - (double)h);
+}
+
+__global__ void k_make_rec32(const double4* __restrict__ p, int n, double L, Rec32* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 r = p[i];
+    const double c[3] = {r.x, r.y, r.z};
+    float h0[3], l0[3], hp[3], lp[3], hm[3], lm[3];
+    for (int a = 0; a < 3; ++a) {
+        split2(c[a], h0[a], l0[a]);
+        split2(c[a] - 0.5 * L, hp[a], lp[a]);
+        split2(c[a] + 0.5 * L, hm[a], lm[a]);
+    }
+    Rec32 o;
+    o.v[0] = make_float4(h0[0], h0[1], h0[2], (float)r.w);
+    o.v[1] = make_float4(l0[0], l0[1], l0[2], 0.0f);
+    o.v[2] = make_float4(hp[0], hp[1], hp[2], hm[0]);
+    o.v[3] = make_float4(hm[1], hm[2], lp[0], lp[1]);
+    o.v[4] = make_float4(lp[2], lm[0], lm[1], lm[2]);
+    out[i] = o;
+}
+
+// ---------------------------------------------------------------- launch
+PairGeom pair_geometry(int nt, int ns, int tpl, int ncu) {
+    PairGeom g;
+    g.nt = nt;
+    g.ns = ns;
+    g.tpl = tpl;
+    g.ntb = (nt + WG * tpl - 1) / (WG * tpl);
+    g.nt_pad = g.ntb * WG * tpl;
+    if (ns <= 0 || nt <= 0) {
+        g.S = 1;
+        g.chunk = 0;
+        return g;
+    }
+    // aim at about 20 resident waves per CU times 4 rounds, chunks of >= 64 sources
+    const long want_wg = 20L * ncu;
+    long S = (want_wg + g.ntb - 1) / g.ntb;
+    long maxS = (ns + 63) / 64;
+    if (S > maxS) S = maxS;
+    if (S < 1) S = 1;
+    g.chunk = (int)((ns + S - 1) / S);
+    g.S = (ns + g.chunk - 1) / g.chunk;
+    return g;
+}
+
+template <int IMG, bool FIELD, bool SELF>
+static hipError_t pair64(const double4* tgt, const double4* src, const PairGeom& g, double L,
+                         double* out, hipStream_t s) {
+    dim3 grid(g.ntb, g.S);
+    if (g.tpl == 2)
+        hipLaunchKernelGGL((k_pair_f64<IMG, FIELD, SELF, 2>), grid, dim3(WG), 0, s, tgt, g.nt, src,
+                           g.ns, g.chunk, L, out, g.nt_pad);
+    else
+        hipLaunchKernelGGL((k_pair_f64<IMG, FIELD, SELF, 1>), grid, dim3(WG), 0, s, tgt, g.nt, src,
+                           g.ns, g.chunk, L, out, g.nt_pad);
+    return hipGetLastError();
+}
+
+template <int IMG, bool FIELD, bool SELF>
+static hipError_t pair32(const Rec32* tgt, const Rec32* src, const PairGeom& g, double* out,
+                         hipStream_t s) {
+    dim3 grid(g.ntb, g.S);
+    if (g.tpl == 2)
+        hipLaunchKernelGGL((k_pair_f32<IMG, FIELD, SELF, 2>), grid, dim3(WG), 0, s, tgt, g.nt, src,
+                           g.ns, g.chunk, out, g.nt_pad);
+    else
+        hipLaunchKernelGGL((k_pair_f32<IMG, FIELD, SELF, 1>), grid, dim3(WG), 0, s, tgt, g.nt, src,
+                           g.ns, g.chunk, out, g.nt_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_f64(int img, bool field, bool self, const double4* tgt, const double4* src,
+                           const PairGeom& g, double L, double* out, hipStream_t s) {
+    if (g.nt <= 0) return hipSuccess;
+    if (g.tpl != 1 && g.tpl != 2) return hipErrorInvalidValue;
+    if (img == IMG_PERIODIC) {
+        if (field) return self ? pair64<IMG_PERIODIC, true, true>(tgt, src, g, L, out, s)
+                               : pair64<IMG_PERIODIC, true, false>(tgt, src, g, L, out, s);
+        return pair64<IMG_PERIODIC, false, false>(tgt, src, g, L, out, s);
+    }
+    if (img == IMG_METALLIC) {
+        if (field) return self ? pair64<IMG_METALLIC, true, true>(tgt, src, g, L, out, s)
+                               : pair64<IMG_METALLIC, true, false>(tgt, src, g, L, out, s);
+        return pair64<IMG_METALLIC, false, false>(tgt, src, g, L, out, s);
+    }
+    if (img == IMG_FREE && field && !self) return pair64<IMG_FREE, true, false>(tgt, src, g, L, out, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, const Rec32* src,
+                           const PairGeom& g, float L, double* out, hipStream_t s) {
+    (void)L;
+    if (g.nt <= 0) return hipSuccess;
+    if (g.tpl != 1 && g.tpl != 2) return hipErrorInvalidValue;
+    if (img == IMG_PERIODIC) {
+        if (field) return self ? pair32<IMG_PERIODIC, true, true>(tgt, src, g, out, s)
+                               : pair32<IMG_PERIODIC, true, false>(tgt, src, g, out, s);
+        return pair32<IMG_PERIODIC, false, false>(tgt, src, g, out, s);
+    }
+    if (img == IMG_METALLIC) {
+        if (field) return self ? pair32<IMG_METALLIC, true, true>(tgt, src, g, out, s)
+                               : pair32<IMG_METALLIC, true, false>(tgt, src, g, out, s);
+        return pair32<IMG_METALLIC, false, false>(tgt, src, g, out, s);
+    }
+    if (img == IMG_FREE && field && !self) return pair32<IMG_FREE, true, false>(tgt, src, g, out, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_surface_f64(const double4* tgt, const double* surf, const PairGeom& g,
+                              double* out, hipStream_t s) {
+    if (g.nt <= 0) return hipSuccess;
+    dim3 grid(g.ntb, g.S);
+    if (g.tpl == 2)
+        hipLaunchKernelGGL((k_surface_f64<2>), grid, dim3(WG), 0, s, tgt, g.nt, surf, g.ns, g.chunk,
+                           out, g.nt_pad);
+    else if (g.tpl == 1)
+        hipLaunchKernelGGL((k_surface_f64<1>), grid, dim3(WG), 0, s, tgt, g.nt, surf, g.ns, g.chunk,
+                           out, g.nt_pad);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_reduce(const double* out, const PairGeom& g, int ncomp, double* res, int ld,
+                               hipStream_t s) {
+    const int n = g.nt * ncomp;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((n + 255) / 256), dim3(256), 0, s, out, g.S, g.nt,
+                       g.nt_pad, ncomp, res, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_rec32(const double4* p, int n, double L, Rec32* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_make_rec32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, L, out);
+    return hipGetLastError();
+}
+
+}  // namespace hsma

@@ -1,0 +1,38 @@
+// Workspace layout and pipeline entry points of the update step.
+#pragma once
+
+#include "hsma_internal.h"
+
+namespace hsma {
+
+struct Result {
+    double energy;
+    double qsum;
+    double qabs;
+    int status;   // bit 0 non-finite input, bit 1 outside the walls, bit 2 not neutral
+    int pad;
+};
+
+struct Layout {
+    int N = 0;     // real particles
+    int ns = 0;    // sources (2N for the slab: real + mirror)
+    PairGeom g_rhs, g_near, g_surf, g_u, g_G;
+    size_t off_src64 = 0, off_src32 = 0, off_rhs_part = 0, off_b = 0, off_A = 0, off_surf = 0;
+    size_t off_near_part = 0, off_surf_part = 0, off_eblk = 0, off_result = 0;
+    size_t off_u_part = 0, off_tw = 0, off_lam64 = 0, off_lam32 = 0, off_G_part = 0,
+           off_real32 = 0, off_ud = 0;
+    int n_eblk = 1;
+    size_t total = 0;
+};
+
+Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad);
+hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, const double* q,
+                    char* ws, hipStream_t s, double* phi, double* forces,
+                    const hsma_intermediates* dbg);
+hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStream_t s,
+                     double* dEdx, double* dEdq);
+hsma_status read_result(const Layout& ly, char* ws, hipStream_t s, double* energy);
+hsma_status build_plan(hsma_plan_s* pl);
+void free_plan(hsma_plan_s* pl);
+
+}  // namespace hsma

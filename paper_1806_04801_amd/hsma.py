@@ -1,0 +1,258 @@
+"""Python binding of libhsma (argument marshalling only).
+
+Every step of the HSMA update step runs in the library's HIP kernels; this
+module converts arguments, owns device buffers through PyTorch (device memory
+and streams only) and raises on every non-OK status.  Names follow the C ABI
+in include/hsma.h.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libhsma.so")
+
+BC_PERIODIC = 0
+BC_METALLIC = 1
+BC_SLAB = 2
+FP64 = 0
+FP32_COMP = 1
+DEFAULT_SEED = 12345
+
+_lib = None
+
+
+class HsmaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("HSMA status %d: %s" % (status, msg))
+        self.status = status
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("bc", ctypes.c_int), ("p", ctypes.c_int),
+                ("M", ctypes.c_int), ("K", ctypes.c_int), ("R", ctypes.c_double),
+                ("precision", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int), ("n_unknowns", ctypes.c_int), ("K", ctypes.c_int),
+                ("n_check", ctypes.c_int), ("M_eff", ctypes.c_int), ("F1", ctypes.c_int),
+                ("F2", ctypes.c_int), ("R0", ctypes.c_double), ("Rs", ctypes.c_double),
+                ("precision", ctypes.c_int), ("bc", ctypes.c_int),
+                ("bytes_resident", ctypes.c_size_t)]
+
+
+class Intermediates(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("b", "A", "surf", "phi_near", "field_near", "phi_out", "field_out")]
+
+
+EXPORTS = {
+    "hsma_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "hsma_last_error": (ctypes.c_char_p, []),
+    "hsma_version": (ctypes.c_int, []),
+    "hsma_plan_create": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)]),
+    "hsma_plan_create_ex": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "hsma_plan_destroy": (None, [ctypes.c_void_p]),
+    "hsma_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
+    "hsma_plan_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "hsma_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
+    "hsma_energy_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "hsma_energy_forces_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                                 ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.POINTER(Intermediates)]),
+    "hsma_energy_grad_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "hsma_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "hsma_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+}
+
+
+def load():
+    """Load libhsma.so; raise if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhsma.so not built: run paper_1806_04801_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != 0:
+        lib = load()
+        raise HsmaError(st, "%s: %s" % (lib.hsma_status_string(st).decode(),
+                                        lib.hsma_last_error().decode()))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_handle(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """An HSMA plan (preparation step) resident on the current GPU."""
+
+    def __init__(self, L, bc, p, M, K, R, precision=FP64, seed=DEFAULT_SEED):
+        lib = load()
+        d = PlanDesc(L=float(L), bc=int(bc), p=int(p), M=int(M), K=int(K), R=float(R),
+                     precision=int(precision), seed=int(seed))
+        h = ctypes.c_void_p()
+        _check(lib.hsma_plan_create_ex(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.L, self.bc, self.p, self.M, self.K, self.R = float(L), int(bc), int(p), int(M), int(K), float(R)
+        self.precision = int(precision)
+        inf = PlanInfo()
+        _check(lib.hsma_plan_info(h, ctypes.byref(inf)))
+        self.info = {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hsma_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def points(self, which):
+        """Host copies of the plan geometry (centred): 0 monitoring points,
+        1 twins, 2 surface points (returns (xyz, weights))."""
+        n = self.info["M_eff"] if which == 2 else self.info["K"]
+        xyz = np.zeros((n, 3))
+        w = np.zeros(n) if which == 2 else None
+        _check(load().hsma_plan_points(self._h, which, xyz.ctypes.data_as(ctypes.c_void_p),
+                                       w.ctypes.data_as(ctypes.c_void_p) if w is not None else None))
+        return (xyz, w) if which == 2 else xyz
+
+    def workspace_bytes(self, n):
+        return int(load().hsma_workspace_bytes(self._h, int(n)))
+
+    def workspace(self, n, device):
+        import torch
+        need = self.workspace_bytes(n)
+        if self._ws is None or self._ws.numel() < need or self._ws.device != device:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device)
+        return self._ws
+
+    # ------------------------------------------------------------ host path
+    def energy_forces_host(self, x, q):
+        """Host arrays in, host arrays out (the library copies over PCIe)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        n = len(q)
+        e = ctypes.c_double()
+        phi = np.zeros(n)
+        F = np.zeros((n, 3))
+        _check(load().hsma_energy_forces(self._h, x.ctypes.data_as(ctypes.c_void_p),
+                                         q.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(e),
+                                         phi.ctypes.data_as(ctypes.c_void_p),
+                                         F.ctypes.data_as(ctypes.c_void_p)))
+        return e.value, phi, F
+
+    # ------------------------------------------------------------ device path
+    def energy_forces(self, x, q, phi=None, forces=None, intermediates=False):
+        """x (N x 3), q (N): float64 CUDA tensors.  Returns (energy, phi, forces)
+        and, if intermediates, a dict of the stage outputs."""
+        import torch
+        assert x.is_cuda and q.is_cuda and x.dtype == torch.float64 and q.dtype == torch.float64
+        x = x.contiguous()
+        q = q.contiguous()
+        n = q.numel()
+        dev = x.device
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float64, device=dev)
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        ws = self.workspace(n, dev)
+        dbg = None
+        inter = None
+        if intermediates:
+            inter = {
+                "b": torch.empty(self.info["K"], dtype=torch.float64, device=dev),
+                "A": torch.empty(self.info["n_basis"], dtype=torch.float64, device=dev),
+                "surf": torch.empty((self.info["M_eff"], 8), dtype=torch.float64, device=dev),
+                "phi_near": torch.empty(n, dtype=torch.float64, device=dev),
+                "field_near": torch.empty((n, 3), dtype=torch.float64, device=dev),
+                "phi_out": torch.empty(n, dtype=torch.float64, device=dev),
+                "field_out": torch.empty((n, 3), dtype=torch.float64, device=dev),
+            }
+            dbg = Intermediates(**{k: v.data_ptr() for k, v in inter.items()})
+        e = ctypes.c_double()
+        _check(load().hsma_energy_forces_device(
+            self._h, _ptr(x), _ptr(q), n, _stream_handle(torch, dev), _ptr(ws), ws.numel(),
+            ctypes.byref(e), _ptr(phi), _ptr(forces), ctypes.byref(dbg) if dbg is not None else None))
+        if intermediates:
+            return e.value, phi, forces, inter
+        return e.value, phi, forces
+
+    def energy_grad(self, x, q):
+        """Exact gradient of the computed energy: (energy, dE/dx, dE/dq)."""
+        import torch
+        x = x.contiguous()
+        q = q.contiguous()
+        n = q.numel()
+        dev = x.device
+        dx = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        dq = torch.empty(n, dtype=torch.float64, device=dev)
+        ws = self.workspace(n, dev)
+        e = ctypes.c_double()
+        _check(load().hsma_energy_grad_device(self._h, _ptr(x), _ptr(q), n, _stream_handle(torch, dev),
+                                              _ptr(ws), ws.numel(), ctypes.byref(e), _ptr(dx), _ptr(dq)))
+        return e.value, dx, dq
+
+
+def timing_enable(flag=True):
+    _check(load().hsma_timing_enable(1 if flag else 0))
+
+
+def timing_read():
+    ms = (ctypes.c_double * 3)()
+    n = (ctypes.c_int64 * 3)()
+    _check(load().hsma_timing_read(ms, n))
+    return {"near": (ms[0], n[0]), "rhs": (ms[1], n[1]), "surface": (ms[2], n[2])}
+
+
+def make_energy_function():
+    """torch.autograd.Function whose forward returns the HSMA energy of (x, q)
+    and whose backward applies the library's adjoint kernels."""
+    import torch
+
+    class HsmaEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, q, plan):
+            e, dx, dq = plan.energy_grad(x.detach(), q.detach())
+            ctx.save_for_backward(dx, dq)
+            return torch.tensor(e, dtype=torch.float64, device=x.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            dx, dq = ctx.saved_tensors
+            return g * dx, g * dq, None
+
+    return HsmaEnergy
