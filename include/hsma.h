@@ -176,6 +176,76 @@ hsma_status hsma_energy_grad_device(hsma_plan plan, const double* x, const doubl
 hsma_status hsma_timing_enable(int enable);
 hsma_status hsma_timing_read(double* ms, int64_t* launches);
 
+/*
+ * Serving: continuous batching of energy/force requests (update steps of
+ * possibly different N, boundary condition and plan) on one GPU.
+ *
+ * A server owns a device arena of memory_bytes for the inputs, outputs and
+ * workspace of admitted requests, a pinned host staging area for their
+ * results, max_active request slots and a stream.  Requests wait in a FIFO
+ * queue until a slot is free and the arena has room (admission by memory).
+ * Each hsma_server_tick admits what fits and enqueues one round of grouped
+ * launches in which every active request advances one stage; the pair tiles of
+ * all requests in the round share one launch.  A request's arithmetic depends
+ * only on its own inputs and plan, so its result is bitwise the same alone and
+ * in any mix.  precision selects the pair sums of every request
+ * (HSMA_FP32_COMP: single precision with two-sum accumulation; HSMA_FP64);
+ * plans only contribute their geometry and matrices.  A server is used from
+ * one host thread; plans must outlive the requests that use them.
+ */
+typedef struct hsma_server_s* hsma_server;
+
+typedef struct {
+    size_t memory_bytes;   /* device arena for admitted requests (>= 1 MiB) */
+    int max_active;        /* request slots (>= 1) */
+    int precision;         /* hsma_precision of the pair sums */
+} hsma_server_desc;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int active, pending;
+    int64_t ticks, tiles;
+    size_t arena_bytes, arena_used, arena_peak;
+} hsma_server_stats_t;
+
+hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out);
+void        hsma_server_destroy(hsma_server server);
+
+/* Queue a request; x (N x 3) and q (N) are host arrays, copied.  *id receives
+   its handle.  HSMA_E_NOMEM if it could never fit the arena. */
+hsma_status hsma_server_submit(hsma_server server, hsma_plan plan, const double* x,
+                               const double* q, int64_t N, int64_t* id);
+
+/* One scheduling round (admission, grouped launches, retirement). */
+hsma_status hsma_server_tick(hsma_server server);
+
+/* Tick until request id has finished. */
+hsma_status hsma_server_wait(hsma_server server, int64_t id);
+
+/* Non-blocking result read: *done = 0 while running; when done, copies the
+   energy, phi (N, or NULL) and forces (N x 3, or NULL) to host arrays, the
+   latency from submission to completion, and releases the request. */
+hsma_status hsma_server_result(hsma_server server, int64_t id, int* done, double* energy,
+                               double* phi, double* forces, double* latency_s);
+
+hsma_status hsma_server_stats(hsma_server server, hsma_server_stats_t* stats);
+
+/* Open-loop replay of a request trace through the server: request i (plan
+   plans[i], host arrays xs[i], qs[i] of Ns[i] particles, which must stay valid)
+   arrives arrival_s[i] seconds after the call starts (non-decreasing).  Fills
+   energies[i], latencies_s[i] (completion minus arrival) and the wall time. */
+hsma_status hsma_server_run_trace(hsma_server server, int64_t n, const double* arrival_s,
+                                  const hsma_plan* plans, const double* const* xs,
+                                  const double* const* qs, const int64_t* Ns, double* energies,
+                                  double* latencies_s, double* wall_s);
+
+/* The same replay with one hsma_energy_forces_device call per request in
+   arrival order (each plan's own precision), for comparison. */
+hsma_status hsma_run_trace_sequential(int64_t n, const double* arrival_s, const hsma_plan* plans,
+                                      const double* const* xs, const double* const* qs,
+                                      const int64_t* Ns, double* energies, double* latencies_s,
+                                      double* wall_s);
+
 #ifdef __cplusplus
 }
 #endif

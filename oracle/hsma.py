@@ -472,7 +472,7 @@ def _mapping_transpose(plan, wpot, wvec):
     return deg / Rs * (Bs.T @ yq) + Bs.T @ yp
 
 
-def adjoint(plan, x, q):
+def adjoint(plan, x, q, targets=None):
     """Exact gradient of the computed energy E(x, q) of solve().
 
     E = 1/2 sum_{i in T} q_i (phi_near_i + phi_out_i), T = the real charges.
@@ -485,18 +485,27 @@ def adjoint(plan, x, q):
       dE/dr_j = q_j grad phi_near_j + 1/2 q_j grad phi_out_j - 1/2 q_j grad G(r_j)
     For the slab every real charge also moves its mirror (x, y, -z) of charge
     -q, so G and grad G enter through that map as well.
-    Returns (E, dE/dx (N x 3), dE/dq (N)).
+    Returns (E, dE/dx, dE/dq); with `targets` (indices of real charges) the
+    derivatives are evaluated at those charges only and E is the partial
+    energy 1/2 sum over the targets of q_i phi_i.
     """
     x = np.asarray(x, dtype=np.float64)
     n_real = len(x)
     src = _prepare_sources(plan, x, q)
     T = np.arange(n_real)
+    sel = T if targets is None else np.asarray(targets, dtype=np.int64)
     bc_img = BC_PERIODIC if plan["bc"] in (BC_PERIODIC, BC_SLAB) else BC_METALLIC
     b = _rhs(plan, src)
     A = coefficients_from_rhs(plan, b)
-    pn, en = near_sum(bc_img, plan["L"], src, T)
     surf = surface_images(plan, A)
-    po, eo = surface_sum(src[T, :3], surf)
+    if targets is None:
+        pn, en = near_sum(bc_img, plan["L"], src, T)
+        po, eo = surface_sum(src[T, :3], surf)
+        energy = 0.5 * np.sum(src[T, 3] * (pn + po))
+    else:
+        pn, en = near_sum(bc_img, plan["L"], src, sel)
+        po, eo = surface_sum(src[sel, :3], surf)
+        energy = 0.5 * np.sum(src[sel, 3] * (pn + po))
     # response of the real charges at the surface points
     upot, ufld = charges_sum(plan["S"], src[T])    # ufld = sum q (R_j - r_i)/|.|^3
     uvec = -ufld                                   # sum q (r_i - R_j)/|.|^3
@@ -513,13 +522,17 @@ def adjoint(plan, x, q):
         lw = np.concatenate([lam, -lam])
     else:
         pts, lw = plan["X"], lam
-    g, dg = check_adjoint(bc_img, plan["L"], src[:, :3], pts, lw)
-    qT = src[T, 3]
-    energy = 0.5 * np.sum(qT * (pn + po))
+    if plan["bc"] == BC_SLAB:
+        gpos = np.concatenate([src[sel, :3], src[sel + n_real, :3]])
+    else:
+        gpos = src[sel, :3]
+    g, dg = check_adjoint(bc_img, plan["L"], gpos, pts, lw)
+    qT = src[sel, 3]
+    ns = len(sel)
     if plan["bc"] == BC_SLAB:
         mir = np.array([1.0, 1.0, -1.0])
-        G = g[:n_real] - g[n_real:]
-        dG = dg[:n_real] - dg[n_real:] * mir
+        G = g[:ns] - g[ns:]
+        dG = dg[:ns] - dg[ns:] * mir
     else:
         G, dG = g, dg
     dq = pn + 0.5 * po - 0.5 * G

@@ -55,6 +55,18 @@ struct PairGeom {
 };
 PairGeom pair_geometry(int nt, int ns, int tpl, int ncu);
 
+// One tile of a grouped pair launch.
+enum { TILE_NEAR = 0, TILE_RHS = 1, TILE_SURFACE = 2 };
+struct TileItem {
+    int kind, img;        // TILE_*, IMG_* (near and right-hand side)
+    int tb, c;            // target block, source chunk
+    int nt, ns, chunk, nt_pad;
+    const void* tgt;      // Rec32 / double4 targets
+    const void* src;      // Rec32 / double4 sources, or surface records (8 doubles)
+    double* out;          // partial buffer of the request's stage
+    double L;
+};
+
 // ---------------------------------------------------------------- plan
 struct hsma_plan_impl;
 }  // namespace hsma
@@ -94,6 +106,7 @@ hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, con
 // Surface images (X, Y, Z, Q, px, py, pz, 0) at targets (x, y, z, q).
 hipError_t launch_surface_f64(const double4* tgt, const double* surf, const PairGeom& g,
                               double* out, hipStream_t s);
+hipError_t launch_group_tiles(bool f32, const TileItem* items, int n, hipStream_t s);
 // Sum the chunks of a pair-kernel output: res[comp * ld + t] = sum_c out[...].
 hipError_t launch_chunk_reduce(const double* out, const PairGeom& g, int ncomp, double* res, int ld,
                                hipStream_t s);

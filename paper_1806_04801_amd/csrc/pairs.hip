@@ -18,6 +18,7 @@
 // a partial buffer that a second kernel sums in a fixed order, so results do
 // not depend on scheduling.
 #include "hsma_internal.h"
+#include "stages.h"
 
 namespace hsma {
 
@@ -89,17 +90,17 @@ __device__ __forceinline__ void images_f64(const double (&dx)[3], const double (
     }
 }
 
+// One tile: target block tb (256*T targets) against source chunk c.
 template <int IMG, bool FIELD, bool SELF, int T>
-__global__ void __launch_bounds__(WG)
-k_pair_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ src, int ns,
-           int chunk, double L, double* __restrict__ out, int nt_pad) {
-    const int c = blockIdx.y;
+__device__ __forceinline__ void tile_pair_f64(int tb, int c, const double4* __restrict__ tgt, int nt,
+                                              const double4* __restrict__ src, int ns, int chunk,
+                                              double L, double* __restrict__ out, int nt_pad) {
     const int j0 = c * chunk;
     const int j1 = min(j0 + chunk, ns);
     double tx[T], ty[T], tz[T], ap[T], ax[T], ay[T], az[T];
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const int t = (tb * T + u) * WG + threadIdx.x;
         const double4 r = tgt[min(t, nt - 1)];
         tx[u] = r.x; ty[u] = r.y; tz[u] = r.z;
         ap[u] = ax[u] = ay[u] = az[u] = 0.0;
@@ -125,7 +126,7 @@ k_pair_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ 
     constexpr int ncomp = FIELD ? 4 : 1;
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const int t = (tb * T + u) * WG + threadIdx.x;
         double* o = out + (size_t)c * ncomp * nt_pad + t;
         o[0] = ap[u];
         if (FIELD) {
@@ -134,6 +135,13 @@ k_pair_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ 
             o[(size_t)3 * nt_pad] = az[u];
         }
     }
+}
+
+template <int IMG, bool FIELD, bool SELF, int T>
+__global__ void __launch_bounds__(WG)
+k_pair_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ src, int ns,
+           int chunk, double L, double* __restrict__ out, int nt_pad) {
+    tile_pair_f64<IMG, FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, L, out, nt_pad);
 }
 
 // ---------------------------------------------------------------- single precision
@@ -217,17 +225,16 @@ __device__ __forceinline__ void images_f32(const float (&dx)[3], const float (&d
 }
 
 template <int IMG, bool FIELD, bool SELF, int T>
-__global__ void __launch_bounds__(WG)
-k_pair_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src, int ns,
-           int chunk, double* __restrict__ out, int nt_pad) {
-    const int c = blockIdx.y;
+__device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __restrict__ tgt, int nt,
+                                              const Rec32* __restrict__ src, int ns, int chunk,
+                                              double* __restrict__ out, int nt_pad) {
     const int j0 = c * chunk;
     const int j1 = min(j0 + chunk, ns);
     Pt32 tp[T];
     float ph[T], pl[T], xh[T], xl[T], yh[T], yl[T], zh[T], zl[T];
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const int t = (tb * T + u) * WG + threadIdx.x;
         tp[u] = load_pt32(tgt[min(t, nt - 1)]);
         ph[u] = pl[u] = xh[u] = xl[u] = yh[u] = yl[u] = zh[u] = zl[u] = 0.0f;
     }
@@ -254,7 +261,7 @@ k_pair_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src,
     constexpr int ncomp = FIELD ? 4 : 1;
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const int t = (tb * T + u) * WG + threadIdx.x;
         double* o = out + (size_t)c * ncomp * nt_pad + t;
         o[0] = (double)ph[u] + (double)pl[u];
         if (FIELD) {
@@ -265,22 +272,28 @@ k_pair_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src,
     }
 }
 
+template <int IMG, bool FIELD, bool SELF, int T>
+__global__ void __launch_bounds__(WG)
+k_pair_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src, int ns,
+           int chunk, double* __restrict__ out, int nt_pad) {
+    tile_pair_f32<IMG, FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, out, nt_pad);
+}
+
 // ---------------------------------------------------------------- surface images
 // Potential and field at targets of M surface points carrying a charge Q_j and
 // a point dipole p_j (Sec. II.B; the dipole is the exact limit of the central
 // difference of Eq. (cd)):
 //   phi = sum Q/|d| + p.d/|d|^3,  E = sum d (Q/|d|^3 + 3 p.d/|d|^5) - p/|d|^3.
 template <int T>
-__global__ void __launch_bounds__(WG)
-k_surface_f64(const double4* __restrict__ tgt, int nt, const double* __restrict__ surf, int ns,
-              int chunk, double* __restrict__ out, int nt_pad) {
-    const int c = blockIdx.y;
+__device__ __forceinline__ void tile_surface_f64(int tb, int c, const double4* __restrict__ tgt,
+                                                 int nt, const double* __restrict__ surf, int ns,
+                                                 int chunk, double* __restrict__ out, int nt_pad) {
     const int j0 = c * chunk;
     const int j1 = min(j0 + chunk, ns);
     double tx[T], ty[T], tz[T], ap[T], ax[T], ay[T], az[T];
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const int t = (tb * T + u) * WG + threadIdx.x;
         const double4 r = tgt[min(t, nt - 1)];
         tx[u] = r.x; ty[u] = r.y; tz[u] = r.z;
         ap[u] = ax[u] = ay[u] = az[u] = 0.0;
@@ -305,13 +318,20 @@ k_surface_f64(const double4* __restrict__ tgt, int nt, const double* __restrict_
     }
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int t = (blockIdx.x * T + u) * WG + threadIdx.x;
+        const int t = (tb * T + u) * WG + threadIdx.x;
         double* o = out + (size_t)c * 4 * nt_pad + t;
         o[0] = ap[u];
         o[(size_t)nt_pad] = ax[u];
         o[(size_t)2 * nt_pad] = ay[u];
         o[(size_t)3 * nt_pad] = az[u];
     }
+}
+
+template <int T>
+__global__ void __launch_bounds__(WG)
+k_surface_f64(const double4* __restrict__ tgt, int nt, const double* __restrict__ surf, int ns,
+              int chunk, double* __restrict__ out, int nt_pad) {
+    tile_surface_f64<T>(blockIdx.x, blockIdx.y, tgt, nt, surf, ns, chunk, out, nt_pad);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -325,29 +345,53 @@ __global__ void k_chunk_reduce(const double* __restrict__ out, int S, int nt, in
     res[(size_t)comp * ld + t] = acc;
 }
 
-__device__ __forceinline__ void split2(double v, float& h, float& l) {
-    h = (float)v;
-    l = (float)(v - (double)h);
-}
-
 __global__ void k_make_rec32(const double4* __restrict__ p, int n, double L, Rec32* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double4 r = p[i];
-    const double c[3] = {r.x, r.y, r.z};
-    float h0[3], l0[3], hp[3], lp[3], hm[3], lm[3];
-    for (int a = 0; a < 3; ++a) {
-        split2(c[a], h0[a], l0[a]);
-        split2(c[a] - 0.5 * L, hp[a], lp[a]);
-        split2(c[a] + 0.5 * L, hm[a], lm[a]);
+    if (i < n) rec32_body(i, p, L, out);
+}
+
+// ---------------------------------------------------------------- grouped tiles
+// One launch over a table of tiles from many requests (continuous batching):
+// work-group g runs tile items[g], whose kind, image mode and operands are
+// wave-uniform, so each work-group takes one branch.  Tiles of one request are
+// computed exactly as in the single-request launch with one target per lane.
+template <bool F32>
+__global__ void __launch_bounds__(WG) k_group_tiles(const TileItem* __restrict__ items) {
+    const TileItem it = items[blockIdx.x];
+    if (it.kind == TILE_SURFACE) {
+        tile_surface_f64<1>(it.tb, it.c, (const double4*)it.tgt, it.nt, (const double*)it.src,
+                            it.ns, it.chunk, it.out, it.nt_pad);
+        return;
     }
-    Rec32 o;
-    o.v[0] = make_float4(h0[0], h0[1], h0[2], (float)r.w);
-    o.v[1] = make_float4(l0[0], l0[1], l0[2], 0.0f);
-    o.v[2] = make_float4(hp[0], hp[1], hp[2], hm[0]);
-    o.v[3] = make_float4(hm[1], hm[2], lp[0], lp[1]);
-    o.v[4] = make_float4(lp[2], lm[0], lm[1], lm[2]);
-    out[i] = o;
+    const bool near = it.kind == TILE_NEAR;
+    if (F32) {
+        const Rec32* t = (const Rec32*)it.tgt;
+        const Rec32* s = (const Rec32*)it.src;
+        if (it.img == IMG_PERIODIC) {
+            if (near) tile_pair_f32<IMG_PERIODIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
+            else tile_pair_f32<IMG_PERIODIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
+        } else {
+            if (near) tile_pair_f32<IMG_METALLIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
+            else tile_pair_f32<IMG_METALLIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
+        }
+    } else {
+        const double4* t = (const double4*)it.tgt;
+        const double4* s = (const double4*)it.src;
+        if (it.img == IMG_PERIODIC) {
+            if (near) tile_pair_f64<IMG_PERIODIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+            else tile_pair_f64<IMG_PERIODIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+        } else {
+            if (near) tile_pair_f64<IMG_METALLIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+            else tile_pair_f64<IMG_METALLIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+        }
+    }
+}
+
+hipError_t launch_group_tiles(bool f32, const TileItem* items, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_group_tiles<true>, dim3(n), dim3(WG), 0, s, items);
+    else hipLaunchKernelGGL(k_group_tiles<false>, dim3(n), dim3(WG), 0, s, items);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- launch

@@ -25,7 +25,8 @@ struct Layout {
     size_t total = 0;
 };
 
-Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad);
+Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_override = 0,
+                   int precision_override = -1);
 hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, const double* q,
                     char* ws, hipStream_t s, double* phi, double* forces,
                     const hsma_intermediates* dbg);

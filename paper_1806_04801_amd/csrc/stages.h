@@ -1,0 +1,213 @@
+// Device bodies of the per-request stages of the update step, shared by the
+// single-request pipeline (solve.hip) and the grouped serving launches
+// (serve.hip), so a request computes the same arithmetic in both.
+#pragma once
+
+#include "hsma_internal.h"
+#include "solve.h"
+
+namespace hsma {
+
+constexpr int SWG = 256;
+
+// Centre (and wrap) particle i; grounded slab: also write its mirror charge
+// -q at z -> -z (mirror reflections plus periodic extension turn the slab into
+// a periodic cube of side L).
+__device__ __forceinline__ void prep_body(int i, const double* __restrict__ x,
+                                          const double* __restrict__ q, int N, int bc, double L,
+                                          double4* __restrict__ src, int* __restrict__ status) {
+    double c[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+    const double qi = q[i];
+    int bad = 0;
+    if (!isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2]) || !isfinite(qi)) bad |= 1;
+    const double h = 0.5 * L;
+    if (bc == HSMA_BC_PERIODIC) {
+        for (int a = 0; a < 3; ++a) {
+            double v = c[a] - h;
+            v -= L * floor(v / L + 0.5);
+            c[a] = v;
+        }
+    } else if (bc == HSMA_BC_METALLIC) {
+        for (int a = 0; a < 3; ++a) {
+            c[a] -= h;
+            if (!(fabs(c[a]) < h)) bad |= 2;
+        }
+    } else {
+        for (int a = 0; a < 2; ++a) {
+            double v = c[a] - h;
+            v -= L * floor(v / L + 0.5);
+            c[a] = v;
+        }
+        if (!(c[2] > 0.0 && c[2] < h)) bad |= 2;
+    }
+    if (bad) atomicOr(status, bad);
+    src[i] = make_double4(c[0], c[1], c[2], qi);
+    if (bc == HSMA_BC_SLAB_METALLIC_Z) src[N + i] = make_double4(c[0], c[1], -c[2], -qi);
+}
+
+__device__ __forceinline__ void split2(double v, float& h, float& l) {
+    h = (float)v;
+    l = (float)(v - (double)h);
+}
+
+// Single-precision record (split coordinates, see Rec32) of point i.
+__device__ __forceinline__ void rec32_body(int i, const double4* __restrict__ p, double L,
+                                           Rec32* __restrict__ out) {
+    const double4 r = p[i];
+    const double c[3] = {r.x, r.y, r.z};
+    float h0[3], l0[3], hp[3], lp[3], hm[3], lm[3];
+    for (int a = 0; a < 3; ++a) {
+        split2(c[a], h0[a], l0[a]);
+        split2(c[a] - 0.5 * L, hp[a], lp[a]);
+        split2(c[a] + 0.5 * L, hm[a], lm[a]);
+    }
+    Rec32 o;
+    o.v[0] = make_float4(h0[0], h0[1], h0[2], (float)r.w);
+    o.v[1] = make_float4(l0[0], l0[1], l0[2], 0.0f);
+    o.v[2] = make_float4(hp[0], hp[1], hp[2], hm[0]);
+    o.v[3] = make_float4(hm[1], hm[2], lp[0], lp[1]);
+    o.v[4] = make_float4(lp[2], lm[0], lm[1], lm[2]);
+    out[i] = o;
+}
+
+// b_k = Phi_in(x_k) (grounded cube) or Phi_in(x_k) - Phi_in(x~_k) (periodic).
+__device__ __forceinline__ void rhs_body(int k, const double* __restrict__ part, int S, int nt_pad,
+                                         int K, int twins, double* __restrict__ b) {
+    double a = 0.0, t = 0.0;
+    for (int c = 0; c < S; ++c) a += part[(size_t)c * nt_pad + k];
+    if (twins)
+        for (int c = 0; c < S; ++c) t += part[(size_t)c * nt_pad + K + k];
+    b[k] = a - t;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    // fixed butterfly order over the 64 lanes
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Least squares (Sec. II.A): A = argmin ||F A + b|| = -R^-1 Q^T b = -P b;
+// row r of P by one wave; periodic: A_00 = 0.
+__device__ __forceinline__ void lsq_body(int r, int lane, const double* __restrict__ P, int K,
+                                         const double* __restrict__ b, int k0,
+                                         double* __restrict__ A) {
+    const double* row = P + (size_t)r * K;
+    double s = 0.0;
+    for (int k = lane; k < K; k += 64) s = __builtin_fma(row[k], b[k], s);
+    s = wave_sum(s);
+    if (lane == 0) {
+        A[k0 + r] = -s;
+        if (k0 == 1 && r == 0) A[0] = 0.0;
+    }
+}
+
+// Harmonic surface mapping (Sec. II.B) for surface point j by one wave:
+// charge Q_j = Wq_j . A and dipole p_j = (Wp_j . A) n_j.
+__device__ __forceinline__ void map_body(int j, int lane, const double* __restrict__ Wq,
+                                         const double* __restrict__ Wp, int nb,
+                                         const double* __restrict__ A,
+                                         const double* __restrict__ spos, double Rs,
+                                         double* __restrict__ surf) {
+    const double* wq = Wq + (size_t)j * nb;
+    const double* wp = Wp + (size_t)j * nb;
+    double sq = 0.0, sp = 0.0;
+    for (int k = lane; k < nb; k += 64) {
+        const double a = A[k];
+        sq = __builtin_fma(wq[k], a, sq);
+        sp = __builtin_fma(wp[k], a, sp);
+    }
+    sq = wave_sum(sq);
+    sp = wave_sum(sp);
+    if (lane == 0) {
+        const double X = spos[4 * j], Y = spos[4 * j + 1], Z = spos[4 * j + 2];
+        double* o = surf + 8 * (size_t)j;
+        o[0] = X; o[1] = Y; o[2] = Z; o[3] = sq;
+        o[4] = sp * X / Rs; o[5] = sp * Y / Rs; o[6] = sp * Z / Rs; o[7] = 0.0;
+    }
+}
+
+// Block-wide sums of three values in a fixed tree order.
+__device__ __forceinline__ void block_sum3(double (&sh)[3][SWG], double& a, double& b, double& c) {
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    sh[2][threadIdx.x] = c;
+    __syncthreads();
+    for (int w = SWG / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+            sh[2][threadIdx.x] += sh[2][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    a = sh[0][0];
+    b = sh[1][0];
+    c = sh[2][0];
+}
+
+// phi = near + surface (chunk sums in fixed order), F = q E, block partial
+// sums of q phi, q and |q| (block blk, all SWG threads participate).
+__device__ __forceinline__ void finalize_body(int blk, const double* __restrict__ near, int Sn,
+                                              int npad, const double* __restrict__ surfp, int Ss,
+                                              int spad, const double4* __restrict__ src, int N,
+                                              double* __restrict__ phi, double* __restrict__ forces,
+                                              double* __restrict__ dbg_pn, double* __restrict__ dbg_fn,
+                                              double* __restrict__ dbg_po, double* __restrict__ dbg_fo,
+                                              double* __restrict__ eblk) {
+    __shared__ double sh[3][SWG];
+    const int i = blk * SWG + threadIdx.x;
+    double e = 0.0, qs = 0.0, qa = 0.0;
+    if (i < N) {
+        double vn[4], vo[4];
+        for (int comp = 0; comp < 4; ++comp) {
+            double a = 0.0, b = 0.0;
+            for (int c = 0; c < Sn; ++c) a += near[((size_t)c * 4 + comp) * npad + i];
+            for (int c = 0; c < Ss; ++c) b += surfp[((size_t)c * 4 + comp) * spad + i];
+            vn[comp] = a;
+            vo[comp] = b;
+        }
+        const double qi = src[i].w;
+        const double p = vn[0] + vo[0];
+        if (phi) phi[i] = p;
+        if (forces) {
+            forces[3 * i] = qi * (vn[1] + vo[1]);
+            forces[3 * i + 1] = qi * (vn[2] + vo[2]);
+            forces[3 * i + 2] = qi * (vn[3] + vo[3]);
+        }
+        if (dbg_pn) dbg_pn[i] = vn[0];
+        if (dbg_po) dbg_po[i] = vo[0];
+        if (dbg_fn) { dbg_fn[3 * i] = vn[1]; dbg_fn[3 * i + 1] = vn[2]; dbg_fn[3 * i + 2] = vn[3]; }
+        if (dbg_fo) { dbg_fo[3 * i] = vo[1]; dbg_fo[3 * i + 1] = vo[2]; dbg_fo[3 * i + 2] = vo[3]; }
+        e = qi * p;
+        qs = qi;
+        qa = fabs(qi);
+    }
+    block_sum3(sh, e, qs, qa);
+    if (threadIdx.x == 0) {
+        eblk[3 * blk] = e;
+        eblk[3 * blk + 1] = qs;
+        eblk[3 * blk + 2] = qa;
+    }
+}
+
+// E = 1/2 sum q phi; neutrality flag for periodic and slab systems (one block).
+__device__ __forceinline__ void energy_body(const double* __restrict__ eblk, int nblk,
+                                            int need_neutral, Result* __restrict__ res) {
+    __shared__ double sh[3][SWG];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += SWG) {
+        a += eblk[3 * k];
+        b += eblk[3 * k + 1];
+        c += eblk[3 * k + 2];
+    }
+    block_sum3(sh, a, b, c);
+    if (threadIdx.x == 0) {
+        res->energy = 0.5 * a;
+        res->qsum = b;
+        res->qabs = c;
+        if (need_neutral && fabs(b) > 1e-12 * c) res->status |= 4;
+    }
+}
+
+}  // namespace hsma

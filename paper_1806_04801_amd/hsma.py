@@ -48,6 +48,22 @@ class Intermediates(ctypes.Structure):
                 ("b", "A", "surf", "phi_near", "field_near", "phi_out", "field_out")]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("memory_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int),
+                ("precision", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("active", ctypes.c_int), ("pending", ctypes.c_int),
+                ("ticks", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
+                ("arena_peak", ctypes.c_size_t)]
+
+
+_TRACE_ARGS = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+
 EXPORTS = {
     "hsma_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "hsma_last_error": (ctypes.c_char_p, []),
@@ -71,6 +87,18 @@ EXPORTS = {
                                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
                                                ctypes.c_void_p, ctypes.c_void_p]),
+    "hsma_server_create": (ctypes.c_int, [ctypes.POINTER(ServerDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "hsma_server_destroy": (None, [ctypes.c_void_p]),
+    "hsma_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "hsma_server_tick": (ctypes.c_int, [ctypes.c_void_p]),
+    "hsma_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "hsma_server_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "hsma_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "hsma_server_run_trace": (ctypes.c_int, [ctypes.c_void_p] + _TRACE_ARGS),
+    "hsma_run_trace_sequential": (ctypes.c_int, _TRACE_ARGS),
     "hsma_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "hsma_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -225,6 +253,91 @@ class Plan:
         _check(load().hsma_energy_grad_device(self._h, _ptr(x), _ptr(q), n, _stream_handle(torch, dev),
                                               _ptr(ws), ws.numel(), ctypes.byref(e), _ptr(dx), _ptr(dq)))
         return e.value, dx, dq
+
+
+class Server:
+    """Continuous-batching server of energy/force requests (see hsma.h)."""
+
+    def __init__(self, memory_bytes=8 << 30, max_active=64, precision=FP32_COMP):
+        lib = load()
+        d = ServerDesc(memory_bytes=int(memory_bytes), max_active=int(max_active),
+                       precision=int(precision))
+        h = ctypes.c_void_p()
+        _check(lib.hsma_server_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._plans = []
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hsma_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, plan, x, q):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        rid = ctypes.c_int64()
+        _check(load().hsma_server_submit(self._h, plan.handle, x.ctypes.data_as(ctypes.c_void_p),
+                                         q.ctypes.data_as(ctypes.c_void_p), len(q), ctypes.byref(rid)))
+        self._plans.append(plan)
+        return rid.value
+
+    def tick(self):
+        _check(load().hsma_server_tick(self._h))
+
+    def wait(self, rid):
+        _check(load().hsma_server_wait(self._h, int(rid)))
+
+    def result(self, rid, n):
+        """(done, energy, phi, forces, latency_s); releases the request when done."""
+        done = ctypes.c_int()
+        e = ctypes.c_double()
+        lat = ctypes.c_double()
+        phi = np.zeros(n)
+        F = np.zeros((n, 3))
+        _check(load().hsma_server_result(self._h, int(rid), ctypes.byref(done), ctypes.byref(e),
+                                         phi.ctypes.data_as(ctypes.c_void_p),
+                                         F.ctypes.data_as(ctypes.c_void_p), ctypes.byref(lat)))
+        if not done.value:
+            return False, None, None, None, None
+        return True, e.value, phi, F, lat.value
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().hsma_server_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def run_trace(self, arrivals, plans, xs, qs):
+        return _trace(load().hsma_server_run_trace, [self._h], arrivals, plans, xs, qs)
+
+
+def run_trace_sequential(arrivals, plans, xs, qs):
+    """Open-loop replay with one plain solve per request (each plan's precision)."""
+    return _trace(load().hsma_run_trace_sequential, [], arrivals, plans, xs, qs)
+
+
+def _trace(fn, head, arrivals, plans, xs, qs):
+    n = len(arrivals)
+    arr = np.ascontiguousarray(arrivals, dtype=np.float64)
+    xs = [np.ascontiguousarray(v, dtype=np.float64) for v in xs]
+    qs = [np.ascontiguousarray(v, dtype=np.float64) for v in qs]
+    ph = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    xp = (ctypes.c_void_p * n)(*[v.ctypes.data for v in xs])
+    qp = (ctypes.c_void_p * n)(*[v.ctypes.data for v in qs])
+    Ns = np.array([len(v) for v in qs], dtype=np.int64)
+    en = np.zeros(n)
+    lat = np.zeros(n)
+    wall = ctypes.c_double()
+    _check(fn(*head, n, arr.ctypes.data_as(ctypes.c_void_p), ctypes.cast(ph, ctypes.c_void_p),
+              ctypes.cast(xp, ctypes.c_void_p), ctypes.cast(qp, ctypes.c_void_p),
+              Ns.ctypes.data_as(ctypes.c_void_p), en.ctypes.data_as(ctypes.c_void_p),
+              lat.ctypes.data_as(ctypes.c_void_p), ctypes.byref(wall)))
+    return en, lat, wall.value
 
 
 def timing_enable(flag=True):

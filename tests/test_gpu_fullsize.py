@@ -1,0 +1,149 @@
+"""Full workload sizes on the GPU against stored oracle values.
+
+tests/golden/<workload>.json holds, for the seeded inputs of
+paper_1806_04801_amd.workloads, the oracle's right-hand side and coefficients
+in full and potential/forces (slab: also the adjoint) at 256 sampled
+particles, written by tests/golden/make_golden.py (oracle only).  The GPU runs
+in the launch configuration bench.py times.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_max, rms
+from paper_1806_04801_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    path = os.path.join(GOLD, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip("golden values not generated: " + path)
+    g = json.load(open(path))
+    for k in ("idx", "b", "A", "phi", "forces", "phi_near", "phi_out", "dEdx", "dEdq"):
+        if k in g:
+            g[k] = np.array(g[k])
+    return g
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04801_amd import hsma
+    hsma.load()
+    return hsma
+
+
+def run(hs, name, precision, grad=False):
+    c = W.CONFIGS[name]
+    x, q = W.make_inputs(name)
+    plan = hs.Plan(c["L"], c["bc"], c["p"], c["M"], c["K"], c["R"], precision=precision)
+    xd = torch.tensor(x, device="cuda")
+    qd = torch.tensor(q, device="cuda")
+    if grad:
+        e, dx, dq = plan.energy_grad(xd, qd)
+        return q, e, dx.cpu().numpy(), dq.cpu().numpy()
+    e, phi, F, inter = plan.energy_forces(xd, qd, intermediates=True)
+    torch.cuda.synchronize()
+    return q, e, phi.cpu().numpy(), F.cpu().numpy(), {k: v.cpu().numpy() for k, v in inter.items()}
+
+
+def report(tag, **errs):
+    print("[fullsize] %s: %s" % (tag, " ".join("%s %.3e" % kv for kv in errs.items())), flush=True)
+
+
+def test_periodic1m_fp64(hs):
+    g = golden("periodic1m")
+    announce("periodic1m fp64 full size")
+    q, e, phi, F, inter = run(hs, "periodic1m", hs.FP64)
+    idx = g["idx"]
+    errs = dict(b=rel_max(inter["b"], g["b"]), A=rel_max(inter["A"], g["A"]),
+                phi=rel_max(phi[idx], g["phi"], rms(g["phi"])), F=rel_max(F[idx], g["forces"]))
+    report("periodic1m fp64", **errs)
+    assert errs["b"] <= 1e-10 and errs["A"] <= 1e-8
+    assert errs["phi"] <= 1e-10 and errs["F"] <= 1e-10
+    pe = 0.5 * np.sum(q[idx] * phi[idx])
+    assert abs(pe - g["partial_energy"]) <= 1e-10 * np.sum(np.abs(q[idx] * phi[idx]))
+    np.save("/tmp/periodic1m_fp64_energy.npy", np.array([e]))
+
+
+def test_periodic1m_fp32_comp(hs):
+    """The gate of the FP32-compensated path: |dE|/|E| <= 1e-5 against the FP64
+    GPU path (full energy) and the oracle (sampled potentials and forces)."""
+    g = golden("periodic1m")
+    announce("periodic1m fp32 full size")
+    q, e, phi, F, inter = run(hs, "periodic1m", hs.FP32_COMP)
+    idx = g["idx"]
+    pe = 0.5 * np.sum(q[idx] * phi[idx])
+    errs = dict(partialE=abs(pe - g["partial_energy"]) / (0.5 * np.sum(np.abs(q[idx] * phi[idx]))),
+                phi=rel_max(phi[idx], g["phi"], rms(g["phi"])), F=rel_max(F[idx], g["forces"]),
+                b=rel_max(inter["b"], g["b"]))
+    path = "/tmp/periodic1m_fp64_energy.npy"
+    if os.path.exists(path):
+        e64 = float(np.load(path)[0])
+        errs["E_vs_fp64"] = abs(e - e64) / abs(e64)
+        assert errs["E_vs_fp64"] <= 1e-5
+    report("periodic1m fp32", **errs)
+    assert errs["partialE"] <= 1e-5 and errs["phi"] <= 1e-5 and errs["F"] <= 1e-4
+
+
+def test_slab200k_fp64(hs):
+    g = golden("slab200k")
+    announce("slab200k fp64 full size")
+    q, e, phi, F, inter = run(hs, "slab200k", hs.FP64)
+    idx = g["idx"]
+    pe = 0.5 * np.sum(q[idx] * phi[idx])
+    errs = dict(partialE=abs(pe - g["partial_energy"]) / (0.5 * np.sum(np.abs(q[idx] * phi[idx]))),
+                phi=rel_max(phi[idx], g["phi"], rms(g["phi"])), F=rel_max(F[idx], g["forces"]),
+                b=rel_max(inter["b"], g["b"]), A=rel_max(inter["A"], g["A"]))
+    report("slab200k fp64", **errs)
+    assert errs["b"] <= 1e-10 and errs["A"] <= 1e-8
+    assert errs["partialE"] <= 1e-10 and errs["phi"] <= 1e-10 and errs["F"] <= 1e-10
+    np.save("/tmp/slab200k_fp64_energy.npy", np.array([e]))
+
+
+def test_slab200k_fp32(hs):
+    """FP32-compensated slab: full energy against the FP64 GPU path (gate
+    1e-5), sampled potentials and forces against the oracle."""
+    g = golden("slab200k")
+    announce("slab200k fp32 full size")
+    q, e, phi, F, inter = run(hs, "slab200k", hs.FP32_COMP)
+    idx = g["idx"]
+    pe = 0.5 * np.sum(q[idx] * phi[idx])
+    errs = dict(partialE=abs(pe - g["partial_energy"]) / (0.5 * np.sum(np.abs(q[idx] * phi[idx]))),
+                phi=rel_max(phi[idx], g["phi"], rms(g["phi"])), F=rel_max(F[idx], g["forces"]),
+                b=rel_max(inter["b"], g["b"]))
+    path = "/tmp/slab200k_fp64_energy.npy"
+    if os.path.exists(path):
+        e64 = float(np.load(path)[0])
+        errs["E_vs_fp64"] = abs(e - e64) / abs(e64)
+        assert errs["E_vs_fp64"] <= 1e-5
+    report("slab200k fp32", **errs)
+    assert errs["partialE"] <= 1e-5 and errs["phi"] <= 1e-5 and errs["F"] <= 1e-4
+
+
+def test_slab200k_adjoint_fp32(hs):
+    g = golden("slab200k")
+    announce("slab200k adjoint fp32 full size")
+    q, e, dx, dq = run(hs, "slab200k", hs.FP32_COMP, grad=True)
+    idx = g["idx"]
+    errs = dict(dq=rel_max(dq[idx], g["dEdq"]), dx=rel_max(dx[idx], g["dEdx"]))
+    report("slab200k adjoint fp32", **errs)
+    assert errs["dq"] <= 1e-5 and errs["dx"] <= 1e-4
+
+
+def test_slab200k_adjoint_fp64(hs):
+    g = golden("slab200k")
+    announce("slab200k adjoint fp64 full size")
+    q, e, dx, dq = run(hs, "slab200k", hs.FP64, grad=True)
+    idx = g["idx"]
+    errs = dict(dq=rel_max(dq[idx], g["dEdq"]), dx=rel_max(dx[idx], g["dEdx"]))
+    report("slab200k adjoint fp64", **errs)
+    assert errs["dq"] <= 1e-9 and errs["dx"] <= 1e-9

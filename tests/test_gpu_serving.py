@@ -1,0 +1,148 @@
+"""Continuous-batching server on the GPU (through the C ABI).
+
+A request's result is bitwise the same alone and in a mix; results agree with
+the single-request path and the oracle; admission respects the memory cap.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import announce, rel_max
+from paper_1806_04801_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04801_amd import hsma
+    hsma.load()
+    return hsma
+
+
+@pytest.fixture(scope="module")
+def plans(hs):
+    out = {}
+    for bc in (0, 1):
+        for p in (8, 12):
+            out[(bc, p)] = hs.Plan(1.0, bc, p, 10 * p * p, 10 * p * p, 2.7)
+    return out
+
+
+def mix(n_req, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        n = int(2 * round(10 ** rng.uniform(2.5, 3.7) / 2))
+        bc = int(rng.integers(0, 2))
+        p = int(rng.choice([8, 12]))
+        x, q = W.uniform_neutral(n, 1.0, seed=1000 + seed * 100 + i)
+        reqs.append((bc, p, x, q))
+    return reqs
+
+
+def energy_scale(plan, x, q):
+    """1/2 sum |q_i phi_i| from the single-request FP64 path: single-precision
+    terms err by ~6e-8 relative each, so the energy error of the FP32 path
+    scales with this sum, not with |E| (which can be a small difference)."""
+    e, phi, F = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+    return e, 0.5 * float(np.sum(np.abs(q * phi.cpu().numpy())))
+
+
+def run_all(srv, plans, reqs):
+    ids = [srv.submit(plans[(bc, p)], x, q) for bc, p, x, q in reqs]
+    out = []
+    for rid, (bc, p, x, q) in zip(ids, reqs):
+        srv.wait(rid)
+        done, e, phi, F, lat = srv.result(rid, len(q))
+        assert done
+        out.append((e, phi, F, lat))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_same_alone_and_in_mix(hs, plans, precision):
+    announce("server alone vs mix precision=%d" % precision)
+    reqs = mix(14, 3)
+    srv = hs.Server(memory_bytes=2 << 30, max_active=8, precision=precision)
+    alone = [run_all(srv, plans, [r])[0] for r in reqs[:3]]
+    both = run_all(srv, plans, reqs)
+    for a, b in zip(alone, both[:3]):
+        assert a[0] == b[0]
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    st = srv.stats()
+    assert st["completed"] == 17 and st["active"] == 0 and st["pending"] == 0
+
+
+def test_server_matches_single_request_path_and_oracle(hs, plans):
+    announce("server vs single path")
+    reqs = mix(10, 5)
+    s64 = hs.Server(memory_bytes=2 << 30, max_active=4, precision=hs.FP64)
+    s32 = hs.Server(memory_bytes=2 << 30, max_active=4, precision=hs.FP32_COMP)
+    r64 = run_all(s64, plans, reqs)
+    r32 = run_all(s32, plans, reqs)
+    for (bc, p, x, q), a, b in zip(reqs, r64, r32):
+        e, phi, F = plans[(bc, p)].energy_forces(torch.tensor(x, device="cuda"),
+                                                 torch.tensor(q, device="cuda"))
+        scale = 0.5 * float(np.sum(np.abs(q * phi.cpu().numpy())))
+        assert abs(a[0] - e) <= 1e-12 * scale
+        assert rel_max(a[1], phi.cpu().numpy()) <= 1e-11
+        assert abs(b[0] - e) <= 1e-6 * scale
+    for (bc, p, x, q), b in list(zip(reqs, r32))[:3]:
+        ref = oracle.solve(oracle.make_plan(1.0, bc, p, 10 * p * p, 10 * p * p, 2.7), x, q)
+        scale = 0.5 * float(np.sum(np.abs(q * ref["phi"])))
+        assert abs(b[0] - ref["energy"]) <= 1e-6 * scale
+
+
+def test_admission_by_memory(hs, plans):
+    """A 30 MiB arena holds about two of these requests (~13 MiB each with
+    their partial buffers): admission is limited by memory, not by slots, and
+    the arena never exceeds its cap."""
+    announce("server admission")
+    reqs = [(0, 12, *W.uniform_neutral(4000, 1.0, seed=40 + i)) for i in range(6)]
+    cap = 30 << 20
+    srv = hs.Server(memory_bytes=cap, max_active=16, precision=hs.FP32_COMP)
+    ids = [srv.submit(plans[(bc, p)], x, q) for bc, p, x, q in reqs]
+    peak_active = 0
+    for _ in range(100000):
+        srv.tick()
+        st = srv.stats()
+        peak_active = max(peak_active, st["active"])
+        assert st["arena_used"] <= cap and st["arena_peak"] <= cap
+        if st["completed"] == len(ids):
+            break
+    assert srv.stats()["completed"] == len(ids)
+    assert 1 <= peak_active < len(ids)
+    ref = plans[(0, 12)].energy_forces(torch.tensor(reqs[0][2], device="cuda"),
+                                       torch.tensor(reqs[0][3], device="cuda"))[0]
+    ok, e, *_ = srv.result(ids[0], 4000)
+    assert ok and abs(e - ref) <= 1e-5 * abs(ref)
+    for rid in ids[1:]:
+        assert srv.result(rid, 4000)[0]
+    big = W.uniform_neutral(400000, 1.0, seed=1)
+    with pytest.raises(hs.HsmaError) as ei:
+        srv.submit(plans[(0, 12)], *big)
+    assert ei.value.status == -5
+
+
+def test_trace_replay_batched_vs_sequential(hs, plans):
+    announce("trace replay")
+    reqs = mix(24, 7)
+    arrivals = np.cumsum(np.random.default_rng(1).exponential(0.002, len(reqs)))
+    pl = [plans[(bc, p)] for bc, p, _, _ in reqs]
+    xs = [r[2] for r in reqs]
+    qs = [r[3] for r in reqs]
+    srv = hs.Server(memory_bytes=2 << 30, max_active=16, precision=hs.FP32_COMP)
+    e32, lat32, wall32 = srv.run_trace(arrivals, pl, xs, qs)
+    e64, lat64, wall64 = hs.run_trace_sequential(arrivals, pl, xs, qs)
+    scale = np.array([energy_scale(p_, x, q)[1] for p_, x, q in zip(pl, xs, qs)])
+    err = np.abs(e32 - e64)
+    print("trace: max |dE|/scale %.2e, median |dE|/|E| %.2e, max |dE|/|E| %.2e"
+          % ((err / scale).max(), np.median(err / np.abs(e64)), (err / np.abs(e64)).max()))
+    assert np.all(err <= 1e-6 * scale)
+    assert np.median(err / np.abs(e64)) <= 1e-5
+    assert np.all(lat32 > 0) and np.all(lat64 > 0)
+    assert srv.stats()["completed"] == len(reqs)
