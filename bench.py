@@ -35,7 +35,36 @@ def parse():
     ap.add_argument("--precision", default=None, help="fp64 or fp32 (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=1024, help="serving: trace length")
+    ap.add_argument("--grad", action="store_true", help="time energy + exact gradient (adjoint)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 1 GiB device buffer (reference kernel for HBM counters)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1806_04801_amd", "csrc", "pairs.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def profiled_traffic(workload, precision_tag):
+    """HBM bytes per launch of the near kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "near_%s_%s_pmc.md" % (precision_tag, workload))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().split()[0]
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(x, q, cfg, n_targets):
@@ -60,12 +89,128 @@ def cpu_baseline(x, q, cfg, n_targets):
                       % (n_targets, len(q), pairs, dt)}
 
 
+def serving(args):
+    """Serving stream: requests with N log-uniform in [1e3, 1e5] (even), periodic or
+    grounded cube with probability 1/2, p in {12, 16, 20}, K = M = 10 p^2,
+    R = 2.7L.  Closed loop (all arrivals at t = 0) gives solves/s; open loop
+    (Poisson arrivals at 0.8 of each path's closed-loop rate) gives p50/p99
+    latency.  Batched FP32-compensated server vs one FP64 solve per request."""
+    import numpy as np
+    import torch
+
+    from paper_1806_04801_amd import hsma, workloads
+
+    torch.cuda.set_device(0)
+    trace = workloads.serving_trace(args.requests, seed=4)
+    plans = {}
+    for bc in (0, 1):
+        for p in (12, 16, 20):
+            plans[(bc, p)] = hsma.Plan(1.0, bc, p, 10 * p * p, 10 * p * p, 2.7)
+    pl, xs, qs = [], [], []
+    for r in trace:
+        x, q = workloads.uniform_neutral(r["n"], 1.0, seed=r["seed"])
+        pl.append(plans[(r["bc"], r["p"])])
+        xs.append(x)
+        qs.append(q)
+    n = len(trace)
+    pairs = 0.0
+    for r in trace:
+        nchk = (2 if r["bc"] == 0 else 1) * 10 * r["p"] ** 2
+        pairs += 27.0 * r["n"] * r["n"] + 27.0 * nchk * r["n"]
+    srv = hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP)
+    zero = np.zeros(n)
+    # warm-up of both paths on a few requests
+    srv.run_trace(zero[:8], pl[:8], xs[:8], qs[:8])
+    hsma.run_trace_sequential(zero[:8], pl[:8], xs[:8], qs[:8])
+    print("serving: closed loop, batched fp32", file=sys.stderr, flush=True)
+    e32, lat32c, wall32 = srv.run_trace(zero, pl, xs, qs)
+    print("serving: closed loop, sequential fp64 (%.1f s batched)" % wall32, file=sys.stderr, flush=True)
+    e64, lat64c, wall64 = hsma.run_trace_sequential(zero, pl, xs, qs)
+    mu32, mu64 = n / wall32, n / wall64
+    rng = np.random.default_rng(44)
+    gaps = rng.exponential(1.0, n)
+    print("serving: open loop (%.1f s sequential)" % wall64, file=sys.stderr, flush=True)
+    arr32 = np.cumsum(gaps) / (0.8 * mu32)
+    _, lat32, _ = srv.run_trace(arr32, pl, xs, qs)
+    arr64 = np.cumsum(gaps) / (0.8 * mu64)
+    _, lat64, _ = hsma.run_trace_sequential(arr64, pl, xs, qs)
+    _, lat32s, _ = srv.run_trace(arr64, pl, xs, qs)      # batched at the sequential path's load
+    rel = np.abs(e32 - e64) / np.abs(e64)
+    pct = lambda a, q_: float(np.percentile(a, q_)) * 1e3
+    rec = {
+        "metric": "solves/s", "value": mu32, "unit": "solves/s", "n_gpus": 1,
+        "steps": n, "warmup": 8, "ms_per_step": 1e3 / mu32, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": "serving", "requests": n,
+            "desc": "N log-uniform [1e3,1e5] even, bc periodic/grounded 1/2, p in {12,16,20}, "
+                    "K=M=10p^2, R=2.7L; FP32-comp batched server vs FP64 per-request",
+            "pair_interactions": pairs,
+            "batched_fp32": {"solves_per_s": mu32, "pairs_per_s": pairs / wall32,
+                             "p50_ms_at_0.8mu": pct(lat32, 50), "p99_ms_at_0.8mu": pct(lat32, 99),
+                             "p50_ms_at_0.8mu64": pct(lat32s, 50), "p99_ms_at_0.8mu64": pct(lat32s, 99)},
+            "sequential_fp64": {"solves_per_s": mu64, "pairs_per_s": pairs / wall64,
+                                "p50_ms_at_0.8mu": pct(lat64, 50), "p99_ms_at_0.8mu": pct(lat64, 99)},
+            "speedup_solves_per_s": mu32 / mu64,
+            "rel_energy_err_fp32_vs_fp64": {"p50": float(np.median(rel)),
+                                            "p99": float(np.percentile(rel, 99)),
+                                            "max": float(rel.max()),
+                                            "frac_le_1e-5": float(np.mean(rel <= 1e-5))},
+        },
+    }
+    print(json.dumps(rec))
+
+
+def adjoint_bench(args, cfg, x, q, prec):
+    """Energy plus exact gradient (forward + adjoint kernels) per step."""
+    import torch
+
+    from paper_1806_04801_amd import hsma
+    dev = torch.device("cuda:0")
+    plan = hsma.Plan(cfg["L"], cfg["bc"], cfg["p"], cfg["M"], cfg["K"], cfg["R"], precision=prec)
+    xd = torch.tensor(x, device=dev)
+    qd = torch.tensor(q, device=dev)
+    for _ in range(args.warmup):
+        plan.energy_grad(xd, qd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e, dx, dq = plan.energy_grad(xd, qd)
+        print("grad step %d done: energy %.10e" % (i, e), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    n = len(q)
+    ns = 2 * n if cfg["bc"] == 2 else n
+    info = plan.info
+    pairs = n * 27.0 * ns + info["n_check"] * 27.0 * ns * 2 + 2.0 * n * info["M_eff"]
+    rec = {
+        "metric": "pair interactions/s", "value": pairs / dt, "unit": "pair interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == hsma.FP32_COMP else "f64", "data": "synthetic",
+        "config": {"workload": args.workload + "+grad", "desc": cfg["desc"] + "; energy + dE/dx + dE/dq",
+                   "N": n, "pairs_per_step": pairs, "energy": e},
+    }
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied %d bytes device to device" % (src.numel() * 8), file=sys.stderr, flush=True)
+        del src, dst
+    if args.workload == "serving":
+        return serving(args)
     import numpy as np
     import torch
 
@@ -78,6 +223,8 @@ def main():
     n = len(q)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.grad:
+        return adjoint_bench(args, cfg, x, q, prec)
     plan = hsma.Plan(cfg["L"], cfg["bc"], cfg["p"], cfg["M"], cfg["K"], cfg["R"], precision=prec)
     info = plan.info
     xd = torch.tensor(x, dtype=torch.float64, device=dev)
@@ -141,7 +288,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": profiled_traffic(args.workload, "f32" if prec == hsma.FP32_COMP else "f64"),
         },
     }
     if not args.no_cpu_baseline:
