@@ -136,7 +136,7 @@ hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStrea
     // G and its field at every source (real and mirror)
     if (f32) {
         CK(launch_make_rec32(lam64, pl->nchk, pl->L, lam32, s));
-        CK(launch_pair_f32(pl->img, true, false, src32, lam32, ly.g_G, (float)pl->L, G_part, s));
+        CK(launch_pair_f32(pl->img, true, false, src32, lam32, ly.g_G, pl->L, G_part, s));
     } else {
         CK(launch_pair_f64(pl->img, true, false, src64, lam64, ly.g_G, pl->L, G_part, s));
     }

@@ -29,18 +29,17 @@ hsma_status fail(hsma_status st, const std::string& msg);
 //   IMG_FREE    : r only (no images)
 enum { IMG_PERIODIC = 0, IMG_METALLIC = 1, IMG_FREE = 2 };
 
-// Single-precision record of a point (target or source): the centred
-// coordinate c, and the shifted coordinates c - L/2 and c + L/2, each split
-// into a float pair hi + lo, plus the charge.  Differences of hi parts of
-// nearby points are exact (Sterbenz), so image distances keep their relative
-// accuracy for close pairs and near walls.
-//   v[0]  = (h0x, h0y, h0z, q)
-//   v[1]  = (l0x, l0y, l0z, 0)
-//   v[2]  = (hpx, hpy, hpz, hmx)      p: c - L/2, m: c + L/2
-//   v[3]  = (hmy, hmz, lpx, lpy)
-//   v[4]  = (lpz, lmx, lmy, lmz)
+// Single-precision record of a point (target or source), in units of the box
+// side L (so the box is [-1/2, 1/2]^3): the centred coordinate c = h0 + l with
+// h0 a multiple of 2^-24 and |l| <= 2^-25, so that h0 - 1/2 and h0 + 1/2 are
+// exact in float and every image difference keeps its leading part exact
+// for close pairs and near walls (Sterbenz); plus the charge.
+//   v[0] = (h0x, h0y, h0z, q)
+//   v[1] = (hpx, hpy, hpz, lx)      hp = h0 - 1/2
+//   v[2] = (hmx, hmy, hmz, ly)      hm = h0 + 1/2
+//   v[3] = (lz, 0, 0, 0)
 struct Rec32 {
-    float4 v[5];
+    float4 v[4];
 };
 
 // Workspace / launch geometry of a pair-kernel launch.
@@ -64,7 +63,7 @@ struct TileItem {
     const void* tgt;      // Rec32 / double4 targets
     const void* src;      // Rec32 / double4 sources, or surface records (8 doubles)
     double* out;          // partial buffer of the request's stage
-    double L;
+    double L;             // box side (physical units)
 };
 
 // ---------------------------------------------------------------- plan
@@ -101,8 +100,10 @@ namespace hsma {
 // comp 0 = potential, 1..3 = field E = -grad phi; c = source chunk.
 hipError_t launch_pair_f64(int img, bool field, bool self, const double4* tgt, const double4* src,
                            const PairGeom& g, double L, double* out, hipStream_t s);
+// Single precision: records in units of L; outputs scaled back to physical
+// units (potential / L, field / L^2).
 hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, const Rec32* src,
-                           const PairGeom& g, float L, double* out, hipStream_t s);
+                           const PairGeom& g, double L, double* out, hipStream_t s);
 // Surface images (X, Y, Z, Q, px, py, pz, 0) at targets (x, y, z, q).
 hipError_t launch_surface_f64(const double4* tgt, const double* surf, const PairGeom& g,
                               double* out, hipStream_t s);

@@ -52,6 +52,8 @@ __device__ __forceinline__ void diffs_f64(double t, double s, double L, double (
 }
 
 // Sum over the images of one source: pot = sum s_k / |d|, f = sum s_k d / |d|^3.
+// The field goes through the marginals of w = s/|d|^3 over the image cube:
+// f_x = sum_a dx_a X_a with X_a = sum_bc w_abc, and likewise for y and z.
 template <int IMG, bool FIELD, bool SELF>
 __device__ __forceinline__ void images_f64(const double (&dx)[3], const double (&dy)[3],
                                            const double (&dz)[3], double& pot, double& fx,
@@ -65,7 +67,8 @@ __device__ __forceinline__ void images_f64(const double (&dx)[3], const double (
         sy[a] = dy[a] * dy[a];
         sz[a] = dz[a] * dz[a];
     }
-    pot = fx = fy = fz = 0.0;
+    double S[3][3], Tz[3][3];
+    pot = 0.0;
 #pragma unroll
     for (int a = lo; a < hi; ++a) {
 #pragma unroll
@@ -77,16 +80,48 @@ __device__ __forceinline__ void images_f64(const double (&dx)[3], const double (
                 double y = rsqrt_f64(r2);
                 if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > 0.0) ? y : 0.0;
                 const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
-                pot = neg ? pot - y : pot + y;
+                if (a == lo && b == lo && c == lo) pot = neg ? -y : y;
+                else pot = neg ? pot - y : pot + y;
                 if (FIELD) {
-                    double y3 = y * y * y;
-                    y3 = neg ? -y3 : y3;
-                    fx = __builtin_fma(y3, dx[a], fx);
-                    fy = __builtin_fma(y3, dy[b], fy);
-                    fz = __builtin_fma(y3, dz[c], fz);
+                    double w = y * y * y;
+                    w = neg ? -w : w;
+                    S[a][b] = (c == lo) ? w : S[a][b] + w;
+                    Tz[a][c] = (b == lo) ? w : Tz[a][c] + w;
                 }
             }
         }
+    }
+    if (FIELD) {
+        double X[3], Y[3], Z[3];
+#pragma unroll
+        for (int a = lo; a < hi; ++a) {
+            double x = S[a][lo], z = Tz[lo][a];
+#pragma unroll
+            for (int b = lo + 1; b < hi; ++b) {
+                x += S[a][b];
+                z += Tz[b][a];
+            }
+            X[a] = x;
+            Z[a] = z;
+        }
+#pragma unroll
+        for (int b = lo; b < hi; ++b) {
+            double yv = S[lo][b];
+#pragma unroll
+            for (int a = lo + 1; a < hi; ++a) yv += S[a][b];
+            Y[b] = yv;
+        }
+        fx = dx[lo] * X[lo];
+        fy = dy[lo] * Y[lo];
+        fz = dz[lo] * Z[lo];
+#pragma unroll
+        for (int a = lo + 1; a < hi; ++a) {
+            fx = __builtin_fma(dx[a], X[a], fx);
+            fy = __builtin_fma(dy[a], Y[a], fy);
+            fz = __builtin_fma(dz[a], Z[a], fz);
+        }
+    } else {
+        fx = fy = fz = 0.0;
     }
 }
 
@@ -155,37 +190,41 @@ __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float b) {
 }
 
 struct Pt32 {
-    float h0[3], l0[3], hp[3], lp[3], hm[3], lm[3];
+    float h0[3], hp[3], hm[3], l[3];
 };
 
 __device__ __forceinline__ Pt32 load_pt32(const Rec32& r) {
     Pt32 p;
     p.h0[0] = r.v[0].x; p.h0[1] = r.v[0].y; p.h0[2] = r.v[0].z;
-    p.l0[0] = r.v[1].x; p.l0[1] = r.v[1].y; p.l0[2] = r.v[1].z;
-    p.hp[0] = r.v[2].x; p.hp[1] = r.v[2].y; p.hp[2] = r.v[2].z;
-    p.hm[0] = r.v[2].w; p.hm[1] = r.v[3].x; p.hm[2] = r.v[3].y;
-    p.lp[0] = r.v[3].z; p.lp[1] = r.v[3].w; p.lp[2] = r.v[4].x;
-    p.lm[0] = r.v[4].y; p.lm[1] = r.v[4].z; p.lm[2] = r.v[4].w;
+    p.hp[0] = r.v[1].x; p.hp[1] = r.v[1].y; p.hp[2] = r.v[1].z;
+    p.hm[0] = r.v[2].x; p.hm[1] = r.v[2].y; p.hm[2] = r.v[2].z;
+    p.l[0] = r.v[1].w; p.l[1] = r.v[2].w; p.l[2] = r.v[3].x;
     return p;
 }
 
-// Differences along axis a for k = -1, 0, +1, from the split coordinates.
-//   periodic: c_t - c_s - kL;  k=+1: (c_t - L/2) - (c_s + L/2),  k=-1: (c_t + L/2) - (c_s - L/2)
-//   metallic: c_t + c_s - kL;  k=+1: (c_t - L/2) + (c_s - L/2),  k=-1: (c_t + L/2) + (c_s + L/2)
+// Differences along axis a for k = -1, 0, +1 (box side 1), leading parts exact
+// for small results:
+//   periodic c_t - c_s - k:  k=+1: (hp_t - hm_s) + (l_t - l_s),  k=-1: (hm_t - hp_s) + (l_t - l_s)
+//   metallic c_t + c_s - k:  k=+1: (hp_t + hp_s) + (l_t + l_s),  k=-1: (hm_t + hm_s) + (l_t + l_s)
 template <int IMG>
 __device__ __forceinline__ void diffs_f32(const Pt32& t, const Pt32& s, int a, float (&d)[3]) {
-    d[1] = (t.h0[a] - s.h0[a]) + (t.l0[a] - s.l0[a]);
+    const float dl = t.l[a] - s.l[a];
+    d[1] = (t.h0[a] - s.h0[a]) + dl;
     if (IMG == IMG_PERIODIC) {
-        d[2] = (t.hp[a] - s.hm[a]) + (t.lp[a] - s.lm[a]);
-        d[0] = (t.hm[a] - s.hp[a]) + (t.lm[a] - s.lp[a]);
+        d[2] = (t.hp[a] - s.hm[a]) + dl;
+        d[0] = (t.hm[a] - s.hp[a]) + dl;
     } else if (IMG == IMG_METALLIC) {
-        d[2] = (t.hp[a] + s.hp[a]) + (t.lp[a] + s.lp[a]);
-        d[0] = (t.hm[a] + s.hm[a]) + (t.lm[a] + s.lm[a]);
+        const float sl = t.l[a] + s.l[a];
+        d[2] = (t.hp[a] + s.hp[a]) + sl;
+        d[0] = (t.hm[a] + s.hm[a]) + sl;
     } else {
         d[0] = d[2] = 0.0f;
     }
 }
 
+// Sum over the 27 images of one source.  The field sum_abc w_abc (dx_a, dy_b,
+// dz_c) with w = s / r^3 is taken through the marginals of w over the image
+// cube: E_x = sum_a dx_a X_a with X_a = sum_bc w_abc, and likewise for y, z.
 template <int IMG, bool FIELD, bool SELF>
 __device__ __forceinline__ void images_f32(const float (&dx)[3], const float (&dy)[3],
                                            const float (&dz)[3], float& pot, float& fx,
@@ -199,7 +238,8 @@ __device__ __forceinline__ void images_f32(const float (&dx)[3], const float (&d
         sy[a] = dy[a] * dy[a];
         sz[a] = dz[a] * dz[a];
     }
-    pot = fx = fy = fz = 0.0f;
+    float S[3][3], Tz[3][3];   // S[a][b] = sum_c w, Tz[a][c] = sum_b w
+    pot = 0.0f;
 #pragma unroll
     for (int a = lo; a < hi; ++a) {
 #pragma unroll
@@ -211,23 +251,58 @@ __device__ __forceinline__ void images_f32(const float (&dx)[3], const float (&d
                 float y = __builtin_amdgcn_rsqf(r2);
                 if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > 0.0f) ? y : 0.0f;
                 const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
-                pot = neg ? pot - y : pot + y;
+                if (a == lo && b == lo && c == lo) pot = neg ? -y : y;
+                else pot = neg ? pot - y : pot + y;
                 if (FIELD) {
-                    float y3 = y * y * y;
-                    y3 = neg ? -y3 : y3;
-                    fx = __builtin_fmaf(y3, dx[a], fx);
-                    fy = __builtin_fmaf(y3, dy[b], fy);
-                    fz = __builtin_fmaf(y3, dz[c], fz);
+                    float w = y * y * y;
+                    w = neg ? -w : w;
+                    S[a][b] = (c == lo) ? w : S[a][b] + w;
+                    Tz[a][c] = (b == lo) ? w : Tz[a][c] + w;
                 }
             }
         }
     }
+    if (FIELD) {
+        float X[3], Y[3], Z[3];
+#pragma unroll
+        for (int a = lo; a < hi; ++a) {
+            float x = S[a][lo], z = Tz[lo][a];
+#pragma unroll
+            for (int b = lo + 1; b < hi; ++b) {
+                x += S[a][b];
+                z += Tz[b][a];
+            }
+            X[a] = x;
+            Z[a] = z;
+        }
+#pragma unroll
+        for (int b = lo; b < hi; ++b) {
+            float yv = S[lo][b];
+#pragma unroll
+            for (int a = lo + 1; a < hi; ++a) yv += S[a][b];
+            Y[b] = yv;
+        }
+        fx = dx[lo] * X[lo];
+        fy = dy[lo] * Y[lo];
+        fz = dz[lo] * Z[lo];
+#pragma unroll
+        for (int a = lo + 1; a < hi; ++a) {
+            fx = __builtin_fmaf(dx[a], X[a], fx);
+            fy = __builtin_fmaf(dy[a], Y[a], fy);
+            fz = __builtin_fmaf(dz[a], Z[a], fz);
+        }
+    } else {
+        fx = fy = fz = 0.0f;
+    }
 }
 
+// One tile in single precision.  Sources are taken two at a time: their two
+// (plain float) contributions are combined and folded into (hi, lo)
+// accumulators by one two-sum.  Outputs are scaled back to physical units.
 template <int IMG, bool FIELD, bool SELF, int T>
 __device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __restrict__ tgt, int nt,
                                               const Rec32* __restrict__ src, int ns, int chunk,
-                                              double* __restrict__ out, int nt_pad) {
+                                              double* __restrict__ out, int nt_pad, double invL) {
     const int j0 = c * chunk;
     const int j1 = min(j0 + chunk, ns);
     Pt32 tp[T];
@@ -238,36 +313,63 @@ __device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __rest
         tp[u] = load_pt32(tgt[min(t, nt - 1)]);
         ph[u] = pl[u] = xh[u] = xl[u] = yh[u] = yl[u] = zh[u] = zl[u] = 0.0f;
     }
-    for (int j = j0; j < j1; ++j) {
-        const Rec32 rs = src[j];
-        const Pt32 sp = load_pt32(rs);
-        const float q = rs.v[0].w;
+    int j = j0;
+    for (; j + 1 < j1; j += 2) {
+        const Rec32 r0 = src[j];
+        const Rec32 r1 = src[j + 1];
+        const Pt32 s0 = load_pt32(r0), s1 = load_pt32(r1);
+        const float q0 = r0.v[0].w, q1 = r1.v[0].w;
 #pragma unroll
         for (int u = 0; u < T; ++u) {
             float dx[3], dy[3], dz[3];
-            diffs_f32<IMG>(tp[u], sp, 0, dx);
-            diffs_f32<IMG>(tp[u], sp, 1, dy);
-            diffs_f32<IMG>(tp[u], sp, 2, dz);
-            float pot, fx, fy, fz;
-            images_f32<IMG, FIELD, SELF>(dx, dy, dz, pot, fx, fy, fz);
-            two_sum_acc(ph[u], pl[u], q * pot);
+            float p0, fx0, fy0, fz0, p1, fx1, fy1, fz1;
+            diffs_f32<IMG>(tp[u], s0, 0, dx);
+            diffs_f32<IMG>(tp[u], s0, 1, dy);
+            diffs_f32<IMG>(tp[u], s0, 2, dz);
+            images_f32<IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
+            diffs_f32<IMG>(tp[u], s1, 0, dx);
+            diffs_f32<IMG>(tp[u], s1, 1, dy);
+            diffs_f32<IMG>(tp[u], s1, 2, dz);
+            images_f32<IMG, FIELD, SELF>(dx, dy, dz, p1, fx1, fy1, fz1);
+            two_sum_acc(ph[u], pl[u], __builtin_fmaf(q1, p1, q0 * p0));
             if (FIELD) {
-                two_sum_acc(xh[u], xl[u], q * fx);
-                two_sum_acc(yh[u], yl[u], q * fy);
-                two_sum_acc(zh[u], zl[u], q * fz);
+                two_sum_acc(xh[u], xl[u], __builtin_fmaf(q1, fx1, q0 * fx0));
+                two_sum_acc(yh[u], yl[u], __builtin_fmaf(q1, fy1, q0 * fy0));
+                two_sum_acc(zh[u], zl[u], __builtin_fmaf(q1, fz1, q0 * fz0));
+            }
+        }
+    }
+    if (j < j1) {
+        const Rec32 r0 = src[j];
+        const Pt32 s0 = load_pt32(r0);
+        const float q0 = r0.v[0].w;
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            float dx[3], dy[3], dz[3];
+            float p0, fx0, fy0, fz0;
+            diffs_f32<IMG>(tp[u], s0, 0, dx);
+            diffs_f32<IMG>(tp[u], s0, 1, dy);
+            diffs_f32<IMG>(tp[u], s0, 2, dz);
+            images_f32<IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
+            two_sum_acc(ph[u], pl[u], q0 * p0);
+            if (FIELD) {
+                two_sum_acc(xh[u], xl[u], q0 * fx0);
+                two_sum_acc(yh[u], yl[u], q0 * fy0);
+                two_sum_acc(zh[u], zl[u], q0 * fz0);
             }
         }
     }
     constexpr int ncomp = FIELD ? 4 : 1;
+    const double invL2 = invL * invL;
 #pragma unroll
     for (int u = 0; u < T; ++u) {
         const int t = (tb * T + u) * WG + threadIdx.x;
         double* o = out + (size_t)c * ncomp * nt_pad + t;
-        o[0] = (double)ph[u] + (double)pl[u];
+        o[0] = ((double)ph[u] + (double)pl[u]) * invL;
         if (FIELD) {
-            o[(size_t)nt_pad] = (double)xh[u] + (double)xl[u];
-            o[(size_t)2 * nt_pad] = (double)yh[u] + (double)yl[u];
-            o[(size_t)3 * nt_pad] = (double)zh[u] + (double)zl[u];
+            o[(size_t)nt_pad] = ((double)xh[u] + (double)xl[u]) * invL2;
+            o[(size_t)2 * nt_pad] = ((double)yh[u] + (double)yl[u]) * invL2;
+            o[(size_t)3 * nt_pad] = ((double)zh[u] + (double)zl[u]) * invL2;
         }
     }
 }
@@ -275,8 +377,9 @@ __device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __rest
 template <int IMG, bool FIELD, bool SELF, int T>
 __global__ void __launch_bounds__(WG)
 k_pair_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src, int ns,
-           int chunk, double* __restrict__ out, int nt_pad) {
-    tile_pair_f32<IMG, FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, out, nt_pad);
+           int chunk, double* __restrict__ out, int nt_pad, double invL) {
+    tile_pair_f32<IMG, FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, out, nt_pad,
+                                       invL);
 }
 
 // ---------------------------------------------------------------- surface images
@@ -368,11 +471,11 @@ __global__ void __launch_bounds__(WG) k_group_tiles(const TileItem* __restrict__
         const Rec32* t = (const Rec32*)it.tgt;
         const Rec32* s = (const Rec32*)it.src;
         if (it.img == IMG_PERIODIC) {
-            if (near) tile_pair_f32<IMG_PERIODIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
-            else tile_pair_f32<IMG_PERIODIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
+            if (near) tile_pair_f32<IMG_PERIODIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
+            else tile_pair_f32<IMG_PERIODIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
         } else {
-            if (near) tile_pair_f32<IMG_METALLIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
-            else tile_pair_f32<IMG_METALLIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad);
+            if (near) tile_pair_f32<IMG_METALLIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
+            else tile_pair_f32<IMG_METALLIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
         }
     } else {
         const double4* t = (const double4*)it.tgt;
@@ -433,14 +536,14 @@ static hipError_t pair64(const double4* tgt, const double4* src, const PairGeom&
 
 template <int IMG, bool FIELD, bool SELF>
 static hipError_t pair32(const Rec32* tgt, const Rec32* src, const PairGeom& g, double* out,
-                         hipStream_t s) {
+                         double invL, hipStream_t s) {
     dim3 grid(g.ntb, g.S);
     if (g.tpl == 2)
         hipLaunchKernelGGL((k_pair_f32<IMG, FIELD, SELF, 2>), grid, dim3(WG), 0, s, tgt, g.nt, src,
-                           g.ns, g.chunk, out, g.nt_pad);
+                           g.ns, g.chunk, out, g.nt_pad, invL);
     else
         hipLaunchKernelGGL((k_pair_f32<IMG, FIELD, SELF, 1>), grid, dim3(WG), 0, s, tgt, g.nt, src,
-                           g.ns, g.chunk, out, g.nt_pad);
+                           g.ns, g.chunk, out, g.nt_pad, invL);
     return hipGetLastError();
 }
 
@@ -463,21 +566,21 @@ hipError_t launch_pair_f64(int img, bool field, bool self, const double4* tgt, c
 }
 
 hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, const Rec32* src,
-                           const PairGeom& g, float L, double* out, hipStream_t s) {
-    (void)L;
+                           const PairGeom& g, double L, double* out, hipStream_t s) {
     if (g.nt <= 0) return hipSuccess;
     if (g.tpl != 1 && g.tpl != 2) return hipErrorInvalidValue;
+    const double iL = 1.0 / L;
     if (img == IMG_PERIODIC) {
-        if (field) return self ? pair32<IMG_PERIODIC, true, true>(tgt, src, g, out, s)
-                               : pair32<IMG_PERIODIC, true, false>(tgt, src, g, out, s);
-        return pair32<IMG_PERIODIC, false, false>(tgt, src, g, out, s);
+        if (field) return self ? pair32<IMG_PERIODIC, true, true>(tgt, src, g, out, iL, s)
+                               : pair32<IMG_PERIODIC, true, false>(tgt, src, g, out, iL, s);
+        return pair32<IMG_PERIODIC, false, false>(tgt, src, g, out, iL, s);
     }
     if (img == IMG_METALLIC) {
-        if (field) return self ? pair32<IMG_METALLIC, true, true>(tgt, src, g, out, s)
-                               : pair32<IMG_METALLIC, true, false>(tgt, src, g, out, s);
-        return pair32<IMG_METALLIC, false, false>(tgt, src, g, out, s);
+        if (field) return self ? pair32<IMG_METALLIC, true, true>(tgt, src, g, out, iL, s)
+                               : pair32<IMG_METALLIC, true, false>(tgt, src, g, out, iL, s);
+        return pair32<IMG_METALLIC, false, false>(tgt, src, g, out, iL, s);
     }
-    if (img == IMG_FREE && field && !self) return pair32<IMG_FREE, true, false>(tgt, src, g, out, s);
+    if (img == IMG_FREE && field && !self) return pair32<IMG_FREE, true, false>(tgt, src, g, out, iL, s);
     return hipErrorInvalidValue;
 }
 

@@ -30,63 +30,12 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.h"
 #include "hsma_internal.h"
 #include "solve.h"
 #include "stages.h"
 
 namespace hsma {
-
-// ---------------------------------------------------------------- allocator
-// First-fit allocator over [0, cap) with coalescing of free neighbours.
-class Arena {
-   public:
-    explicit Arena(size_t cap) : cap_(cap) { free_[0] = cap; }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t noff = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[noff] = rest;
-                used_ += bytes;
-                peak_ = std::max(peak_, used_);
-                sizes_[*off] = bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off) {
-        auto s = sizes_.find(off);
-        if (s == sizes_.end()) return;
-        size_t bytes = s->second;
-        sizes_.erase(s);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-    size_t cap() const { return cap_; }
-
-   private:
-    size_t cap_, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;
-    std::unordered_map<size_t, size_t> sizes_;
-};
 
 // Device descriptor of one request (grouped small kernels read an array).
 struct ReqDesc {
@@ -534,7 +483,7 @@ hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out) {
     if (hipMalloc((void**)&sv->arena_base, desc->memory_bytes) != hipSuccess)
         return bail(HSMA_E_NOMEM, "device arena allocation failed");
     // pinned staging for results: sized for the arena's worth of particles
-    const size_t host_cap = desc->memory_bytes / 2 + ((size_t)1 << 20);
+    const size_t host_cap = std::min(desc->memory_bytes / 4, (size_t)1 << 30) + ((size_t)1 << 20);
     if (hipHostMalloc((void**)&sv->host_base, host_cap, hipHostMallocDefault) != hipSuccess)
         return bail(HSMA_E_NOMEM, "pinned host allocation failed");
     sv->arena.reset(new Arena(desc->memory_bytes));

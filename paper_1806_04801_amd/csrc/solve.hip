@@ -144,7 +144,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     // right-hand side at the monitoring points (and twins)
     timing_begin(1, s);
     if (f32)
-        CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, ly.g_rhs, (float)pl->L,
+        CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, ly.g_rhs, pl->L,
                            rhs_part, s));
     else
         CK(launch_pair_f64(pl->img, false, false, pl->d_chk64, src64, ly.g_rhs, pl->L, rhs_part, s));
@@ -159,7 +159,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     // near field at the particles: the sources and their 27 images, self excluded
     timing_begin(0, s);
     if (f32)
-        CK(launch_pair_f32(pl->img, true, true, src32, src32, ly.g_near, (float)pl->L, near_part, s));
+        CK(launch_pair_f32(pl->img, true, true, src32, src32, ly.g_near, pl->L, near_part, s));
     else
         CK(launch_pair_f64(pl->img, true, true, src64, src64, ly.g_near, pl->L, near_part, s));
     timing_end(0, s);

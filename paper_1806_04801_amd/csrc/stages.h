@@ -45,28 +45,24 @@ __device__ __forceinline__ void prep_body(int i, const double* __restrict__ x,
     if (bc == HSMA_BC_SLAB_METALLIC_Z) src[N + i] = make_double4(c[0], c[1], -c[2], -qi);
 }
 
-__device__ __forceinline__ void split2(double v, float& h, float& l) {
-    h = (float)v;
-    l = (float)(v - (double)h);
-}
-
-// Single-precision record (split coordinates, see Rec32) of point i.
+// Single-precision record (see Rec32) of point i: coordinates in units of L,
+// hi part rounded to a multiple of 2^-24, lo part the float remainder.
 __device__ __forceinline__ void rec32_body(int i, const double4* __restrict__ p, double L,
                                            Rec32* __restrict__ out) {
     const double4 r = p[i];
-    const double c[3] = {r.x, r.y, r.z};
-    float h0[3], l0[3], hp[3], lp[3], hm[3], lm[3];
+    const double inv = 1.0 / L;
+    const double c[3] = {r.x * inv, r.y * inv, r.z * inv};
+    float h[3], l[3];
     for (int a = 0; a < 3; ++a) {
-        split2(c[a], h0[a], l0[a]);
-        split2(c[a] - 0.5 * L, hp[a], lp[a]);
-        split2(c[a] + 0.5 * L, hm[a], lm[a]);
+        const double hq = rint(c[a] * 16777216.0) * (1.0 / 16777216.0);
+        h[a] = (float)hq;
+        l[a] = (float)(c[a] - hq);
     }
     Rec32 o;
-    o.v[0] = make_float4(h0[0], h0[1], h0[2], (float)r.w);
-    o.v[1] = make_float4(l0[0], l0[1], l0[2], 0.0f);
-    o.v[2] = make_float4(hp[0], hp[1], hp[2], hm[0]);
-    o.v[3] = make_float4(hm[1], hm[2], lp[0], lp[1]);
-    o.v[4] = make_float4(lp[2], lm[0], lm[1], lm[2]);
+    o.v[0] = make_float4(h[0], h[1], h[2], (float)r.w);
+    o.v[1] = make_float4(h[0] - 0.5f, h[1] - 0.5f, h[2] - 0.5f, l[0]);
+    o.v[2] = make_float4(h[0] + 0.5f, h[1] + 0.5f, h[2] + 0.5f, l[1]);
+    o.v[3] = make_float4(l[2], 0.0f, 0.0f, 0.0f);
     out[i] = o;
 }
 

@@ -1,0 +1,109 @@
+"""Edge and degenerate cases of the HIP path against the oracle (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import announce, rel_max, rms
+from paper_1806_04801_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04801_amd import hsma
+    hsma.load()
+    return hsma
+
+
+def both(hs, bc, p, M, K, x, q, precision=0, L=1.0, R=2.7):
+    ref = oracle.solve(oracle.make_plan(L, bc, p, M, K, R), x, q)
+    plan = hs.Plan(L, bc, p, M, K, R, precision=precision)
+    e, phi, F = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+    return ref, e, phi.cpu().numpy(), F.cpu().numpy()
+
+
+def test_single_charge_in_grounded_cube(hs):
+    """One charge: the energy is its interaction with its own images."""
+    announce("edge single charge")
+    x = np.array([[0.3, 0.6, 0.45]])
+    q = np.array([1.5])
+    ref, e, phi, F = both(hs, 1, 12, 1000, 600, x, q)
+    assert abs(e - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+    assert rel_max(F, ref["forces"]) <= 1e-10
+    assert e < 0   # attracted by its images
+
+
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_minimum_degree(hs, bc):
+    announce("edge p=1 bc=%d" % bc)
+    x, q = (W.slab_charges(20, 1.0, 3) if bc == 2 else W.uniform_neutral(20, 1.0, 3))
+    ref, e, phi, F = both(hs, bc, 1, 100, 20, x, q)
+    assert abs(e - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+    assert rel_max(phi, ref["phi"], rms(ref["phi"])) <= 1e-10
+
+
+def test_square_least_squares(hs):
+    """K equal to the number of unknowns (the fit interpolates)."""
+    announce("edge K = unknowns")
+    x, q = W.uniform_neutral(40, 1.0, 4)
+    ref, e, phi, F = both(hs, 1, 4, 200, 25, x, q)
+    assert abs(e - ref["energy"]) <= 1e-9 * abs(ref["energy"])
+
+
+def test_periodic_wrap_and_boundary_positions(hs):
+    """Positions on the box faces, at L, and outside [0, L) wrap periodically;
+    the same system shifted by lattice vectors gives the same result."""
+    announce("edge periodic wrap")
+    x, q = W.uniform_neutral(64, 1.0, 5)
+    x[0] = [0.0, 0.0, 0.0]
+    x[1] = [0.5, 0.0, 0.999999]
+    plan = hs.Plan(1.0, 0, 10, 1000, 600, 2.7)
+    e0, phi0, F0 = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+    shift = np.random.default_rng(1).integers(-3, 4, size=x.shape).astype(float)
+    e1, phi1, F1 = plan.energy_forces(torch.tensor(x + shift, device="cuda"), torch.tensor(q, device="cuda"))
+    assert abs(e1 - e0) <= 1e-12 * abs(e0)
+    assert rel_max(F1.cpu().numpy(), F0.cpu().numpy()) <= 1e-10
+    ref = oracle.solve(oracle.make_plan(1.0, 0, 10, 1000, 600, 2.7), x, q)
+    assert abs(e0 - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_zero_charges(hs, precision):
+    """Uncharged particles feel no force and carry no energy; all-zero input gives 0."""
+    announce("edge zero charges")
+    x, q = W.uniform_neutral(100, 1.0, 6)
+    q[::3] = 0.0
+    q[1] -= q.sum()     # restore neutrality
+    ref, e, phi, F = both(hs, 0, 8, 1000, 600, x, q, precision)
+    assert np.all(F[q == 0] == 0.0)
+    tol = 1e-10 if precision == 0 else 1e-6
+    assert abs(e - ref["energy"]) <= tol * abs(ref["energy"])
+    plan = hs.Plan(1.0, 0, 8, 1000, 600, 2.7, precision=precision)
+    e0, phi0, F0 = plan.energy_forces(torch.tensor(x, device="cuda"),
+                                      torch.zeros(100, dtype=torch.float64, device="cuda"))
+    assert e0 == 0.0 and torch.all(F0 == 0)
+
+
+def test_empty_input_rejected(hs):
+    announce("edge empty")
+    plan = hs.Plan(1.0, 0, 6, 500, 300, 2.7)
+    with pytest.raises(hs.HsmaError) as ei:
+        plan.energy_forces_host(np.zeros((0, 3)), np.zeros(0))
+    assert ei.value.status == -1
+
+
+def test_plan_reuse_across_sizes_and_streams(hs):
+    """One plan serves calls of different N on different streams."""
+    announce("edge plan reuse")
+    plan = hs.Plan(1.0, 1, 10, 1000, 600, 2.7)
+    s = torch.cuda.Stream()
+    for n in (10, 1000, 37, 2049):
+        x, q = W.uniform_neutral(n + n % 2, 1.0, 100 + n)
+        ref = oracle.solve(oracle.make_plan(1.0, 1, 10, 1000, 600, 2.7), x, q)
+        with torch.cuda.stream(s):
+            e, phi, F = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+        assert abs(e - ref["energy"]) <= 1e-10 * abs(ref["energy"])
