@@ -20,5 +20,6 @@ from .hsma import (  # noqa: F401
     basis, householder_qr, qr_solve_ls, qr_apply_q,
     make_plan, solve, adjoint, splitmix64_uniform,
     near_sum, potential_at, surface_sum, charges_sum, check_adjoint,
-    surface_images_paper_literal,
+    surface_images_paper_literal, sphere_images, near_explicit,
+    basis_gradient, far_field_direct,
 )

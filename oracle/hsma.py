@@ -54,6 +54,7 @@ def _load():
         lib.orc_surface.argtypes = [d, L_, d, L_, d, d]
         lib.orc_charges.argtypes = [d, L_, d, L_, d, d]
         lib.orc_check_adjoint.argtypes = [ctypes.c_int, ctypes.c_double, d, L_, d, d, L_, d, d]
+        lib.orc_near_explicit.argtypes = [d, lg, L_, d, lg, ctypes.POINTER(ctypes.c_int), L_, d, d]
         _lib = lib
     return _lib
 
@@ -113,6 +114,49 @@ def check_adjoint(bc, L, pos, pts, lam):
     dg = np.zeros((len(pos), 3))
     _load().orc_check_adjoint(bc, L, _p(pos), len(pos), _p(pts), _p(lam), len(pts), _p(g), _p(dg))
     return g, dg
+
+
+def sphere_images(bc, L, src, Rs):
+    """The paper's near set (Sec. II.A): every image of every source whose
+    position lies inside the auxiliary sphere |r| < Rs (box centred at 0).
+    Images: r + kL (periodic) or (-1)^k o r + kL with charge (-1)^|k| q
+    (grounded cube), for all integer k with a box that reaches the sphere.
+    Returns (img m x 4, owner m, center m) in the order source-major, then k
+    lexicographic."""
+    kr = int(math.ceil(Rs / L + 0.5))
+    rng = range(-kr, kr + 1)
+    ks = [(a, b, c) for a in rng for b in rng for c in rng]
+    imgs, owner, center = [], [], []
+    for j, (x, y, z, q) in enumerate(np.asarray(src, dtype=np.float64)):
+        for k in ks:
+            if bc == BC_PERIODIC:
+                p = (x + k[0] * L, y + k[1] * L, z + k[2] * L)
+                s = 1.0
+            else:
+                r = [x, y, z]
+                p = tuple((r[a] if k[a] % 2 == 0 else -r[a]) + k[a] * L for a in range(3))
+                s = (-1.0) ** (abs(k[0]) + abs(k[1]) + abs(k[2]))
+            if p[0] * p[0] + p[1] * p[1] + p[2] * p[2] < Rs * Rs:
+                imgs.append((p[0], p[1], p[2], s * q))
+                owner.append(j)
+                center.append(1 if k == (0, 0, 0) else 0)
+    return (np.array(imgs).reshape(-1, 4), np.array(owner, dtype=np.int64),
+            np.array(center, dtype=np.int32))
+
+
+def near_explicit(src, tidx, img, owner, center):
+    """phi and E at source targets from explicit images, bare self term left out."""
+    src, img = _c(src), _c(img)
+    tidx = np.ascontiguousarray(tidx, dtype=np.int64)
+    owner = np.ascontiguousarray(owner, dtype=np.int64)
+    center = np.ascontiguousarray(center, dtype=np.int32)
+    phi = np.zeros(len(tidx))
+    fld = np.zeros((len(tidx), 3))
+    _load().orc_near_explicit(_p(src), tidx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(tidx),
+                              _p(img), owner.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                              center.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(img),
+                              _p(phi), _p(fld))
+    return phi, fld
 
 
 # --------------------------------------------------------------------------
@@ -288,6 +332,49 @@ def basis(pts, P, R0):
     return B
 
 
+def basis_gradient(pts, P, R0):
+    """grad B_k(r) for the basis of basis(), from spherical angles:
+    grad f = df/dr r^ + (1/r) df/dtheta theta^ + (1/(r sin theta)) df/dphi phi^,
+    with dPbar_n^m/dtheta from the identity
+    (1 - x^2) dPbar_n^m/dx = -n x Pbar_n^m + sqrt((2n+1)(n^2-m^2)/(2n-1)) Pbar_{n-1}^m
+    (x = cos theta).
+    Points must avoid the origin and the z axis.  Returns (npts, N_b, 3)."""
+    pts = np.asarray(pts, dtype=np.float64)
+    r = np.sqrt(np.sum(pts * pts, axis=1))
+    x = pts[:, 2] / r
+    st = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    az = np.arctan2(pts[:, 1], pts[:, 0])
+    Pb = _legendre_normalized(P, x, st)
+    rhat = np.stack([st * np.cos(az), st * np.sin(az), x], axis=1)
+    that = np.stack([x * np.cos(az), x * np.sin(az), -st], axis=1)
+    phat = np.stack([-np.sin(az), np.cos(az), np.zeros_like(az)], axis=1)
+    G = np.zeros((len(pts), (P + 1) ** 2, 3))
+    for n in range(P + 1):
+        rn = (r / R0) ** n
+        for m in range(0, n + 1):
+            prev = Pb[(n - 1, m)] if n - 1 >= m else np.zeros_like(x)
+            dPdth = (n * x * Pb[(n, m)] - math.sqrt((2.0 * n + 1.0) * (n * n - m * m) / (2.0 * n - 1.0)) * prev
+                     ) / st if n > 0 else np.zeros_like(x)
+            variants = [(n * n + n, 1.0, np.ones_like(az), np.zeros_like(az))] if m == 0 else [
+                (n * n + n + m, math.sqrt(2.0), np.cos(m * az), -m * np.sin(m * az)),
+                (n * n + n - m, math.sqrt(2.0), np.sin(m * az), m * np.cos(m * az))]
+            for k, c, T, dT in variants:
+                f = rn * c * Pb[(n, m)] * T
+                dr_ = n * f / r
+                dth = rn * c * dPdth * T / r
+                dph = rn * c * Pb[(n, m)] * dT / (r * st)
+                G[:, k, :] = dr_[:, None] * rhat + dth[:, None] * that + dph[:, None] * phat
+    return G
+
+
+def far_field_direct(plan, A, pts):
+    """Phi_out and E_out = -grad Phi_out at points straight from the fitted
+    series sum_k A_k B_k (Eq. (harmonic)), without the surface mapping."""
+    phi = basis(pts, plan["p"], plan["R0"]) @ A
+    grad = np.einsum("ikc,k->ic", basis_gradient(pts, plan["p"], plan["R0"]), A)
+    return phi, -grad
+
+
 def degree_of(P):
     """n for each basis index k = n^2 + n + m."""
     return np.array([n for n in range(P + 1) for _ in range(2 * n + 1)], dtype=np.float64)
@@ -380,9 +467,15 @@ def make_plan(L, bc, p, M, K, R, seed=12345):
                 deg=degree_of(p))
 
 
-def _rhs(plan, src):
+def _rhs(plan, src, images=None):
     """Right-hand side: Phi_in at the monitoring points, differenced with the
-    twins for the periodic residual (Sec. II.A)."""
+    twins for the periodic residual (Sec. II.A).  images: explicit near set
+    (sphere mode) instead of the 27-image block."""
+    if images is not None:
+        b = charges_sum(plan["X"], images[0])[0]
+        if plan["Xt"] is not None:
+            b = b - charges_sum(plan["Xt"], images[0])[0]
+        return b
     bc = BC_PERIODIC if plan["bc"] in (BC_PERIODIC, BC_SLAB) else BC_METALLIC
     b = potential_at(bc, plan["L"], src, plan["X"])
     if plan["Xt"] is not None:
@@ -435,10 +528,14 @@ def _prepare_sources(plan, x, q):
     return np.concatenate([c, q[:, None]], axis=1)
 
 
-def solve(plan, x, q, targets=None, dipole="exact", dr=None):
+def solve(plan, x, q, targets=None, dipole="exact", dr=None, near="block", far="surface"):
     """Update step (Sec. II.C): images, least squares, surface images, then
     potential, field, energy and forces at the targets (indices of real
-    sources; default all).  E = 1/2 sum_targets q_i phi_i, F_i = q_i E_i."""
+    sources; default all).  E = 1/2 sum_targets q_i phi_i, F_i = q_i E_i.
+    near: "block" (27 images per source) or "sphere" (every image inside the
+    auxiliary sphere, the paper's literal near set).  far: "surface" (the
+    harmonic surface mapping) or "direct" (the fitted series evaluated at the
+    targets)."""
     x = np.asarray(x, dtype=np.float64)
     n_real = len(x)
     src = _prepare_sources(plan, x, q)
@@ -446,11 +543,18 @@ def solve(plan, x, q, targets=None, dipole="exact", dr=None):
         targets = np.arange(n_real)
     targets = np.asarray(targets, dtype=np.int64)
     bc_img = BC_PERIODIC if plan["bc"] in (BC_PERIODIC, BC_SLAB) else BC_METALLIC
-    b = _rhs(plan, src)
+    images = sphere_images(bc_img, plan["L"], src, plan["Rs"]) if near == "sphere" else None
+    b = _rhs(plan, src, images)
     A = coefficients_from_rhs(plan, b)
-    pn, en = near_sum(bc_img, plan["L"], src, targets)
+    if images is not None:
+        pn, en = near_explicit(src, targets, *images)
+    else:
+        pn, en = near_sum(bc_img, plan["L"], src, targets)
     tpos = src[targets, :3]
-    if dipole == "exact":
+    if far == "direct":
+        surf = None
+        po, eo = far_field_direct(plan, A, tpos)
+    elif dipole == "exact":
         surf = surface_images(plan, A)
         po, eo = surface_sum(tpos, surf)
     else:

@@ -208,3 +208,33 @@ void orc_check_adjoint(int bc, double L, const double *pos, long ns,
         dg[3 * j + 0] = gx; dg[3 * j + 1] = gy; dg[3 * j + 2] = gz;
     }
 }
+
+/*
+ * Near-field potential and field at source targets from an explicit list of
+ * charges (image positions and charges, img: m x 4), where entry j belongs to
+ * source owner[j] and center[j] != 0 marks the unshifted copy of that source.
+ * Only the bare self term (owner == target, center) is left out.  Used for the
+ * paper-literal near set "all charges within the auxiliary sphere"
+ * (Sec. II.A).
+ */
+void orc_near_explicit(const double *src, const long *tidx, long nt, const double *img,
+                       const long *owner, const int *center, long m, double *phi, double *field)
+{
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (long t = 0; t < nt; ++t) {
+        long i = tidx[t];
+        const double *ri = src + 4 * i;
+        double ap = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (long j = 0; j < m; ++j) {
+            if (owner[j] == i && center[j]) continue;
+            const double *s = img + 4 * j;
+            double dx = ri[0] - s[0], dy = ri[1] - s[1], dz = ri[2] - s[2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            ap += s[3] / d;
+            double c = s[3] / (d * d * d);
+            ex += c * dx; ey += c * dy; ez += c * dz;
+        }
+        phi[t] = ap;
+        field[3 * t + 0] = ex; field[3 * t + 1] = ey; field[3 * t + 2] = ez;
+    }
+}

@@ -12,6 +12,7 @@ import pytest
 import ewald
 import oracle
 from oracle import hsma
+from paper_1806_04801_amd import workloads as W
 
 MADELUNG = 1.74756459463318219  # Sec. III, first example
 
@@ -93,6 +94,33 @@ def test_against_ewald(bc, p, tolE, tolP, tolF):
             dphi -= dphi.mean()   # potential gauge: A_00 = 0 vs zero-mean Ewald
         assert np.abs(dphi).max() <= tolP * np.abs(rphi).max()
         assert np.abs(r["field"] - rfld).max() <= tolF * np.abs(rfld).max()
+
+
+@pytest.mark.parametrize("alpha,tols", [(1.3, (1e-3, 1e-4, 2e-5)), (2.0, (1e-4, 1e-6, 1e-8))])
+def test_sphere_near_set_converges_to_ewald(alpha, tols):
+    """The paper's literal near set (every image inside R_s = alpha sqrt3 L/2):
+    the energy converges to tin-foil Ewald as P grows (P = 8, 12, 16), at the
+    rate the truncation bound of Sec. II.A gives (alpha^-P)."""
+    x, q = W.random_sign_lattice(4, 1.0, 3)
+    _, _, E = ewald.ewald(x, q, 1.0)
+    R = alpha * math.sqrt(3.0) / 2.0
+    for p, tol in zip((8, 12, 16), tols):
+        plan = oracle.make_plan(1.0, oracle.BC_PERIODIC, p, 1976, max(2 * p * p, (p + 1) ** 2 + 50), R)
+        r = oracle.solve(plan, x, q, near="sphere")
+        assert abs(r["energy"] - E) <= tol * abs(E)
+
+
+def test_sphere_images_of_grounded_cube():
+    """Sphere images of a grounded cube: reflected positions and alternating
+    signs; the near set at R_s = 2.7L contains the 27-image block."""
+    src = np.array([[0.1, -0.2, 0.3, 1.0]])
+    img, owner, center = oracle.sphere_images(oracle.BC_METALLIC, 1.0, src, 2.7)
+    assert center.sum() == 1 and np.all(owner == 0)
+    for k in ((1, 0, 0), (0, -1, 1), (1, 1, 1)):
+        p = np.array([(src[0, a] if k[a] == 0 else -src[0, a]) + k[a] for a in range(3)])
+        hit = np.where(np.all(np.abs(img[:, :3] - p) < 1e-15, axis=1))[0]
+        assert len(hit) == 1 and img[hit[0], 3] == (-1.0) ** sum(abs(v) for v in k)
+    assert np.all(np.sum(img[:, :3] ** 2, axis=1) < 2.7 ** 2)
 
 
 def test_paper_cavity_example():
@@ -270,6 +298,32 @@ def test_basis_orthonormal_on_unit_sphere():
     B = oracle.basis(pts, P, 1.0)
     G = B.T @ (wts[:, None] * B)
     assert np.allclose(G, np.eye((P + 1) ** 2), atol=1e-12)
+
+
+def test_basis_gradient_matches_finite_differences():
+    """The angular gradient formula of the basis against central differences
+    of the basis itself (n <= 12)."""
+    rng = np.random.default_rng(13)
+    P = rng.random((15, 3)) - 0.5
+    G = oracle.basis_gradient(P, 12, 0.9)
+    h = 1e-5
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd = (oracle.basis(P + e, 12, 0.9) - oracle.basis(P - e, 12, 0.9)) / (2 * h)
+        assert np.allclose(G[:, :, a], fd, rtol=1e-7, atol=1e-8)
+
+
+def test_direct_far_field_equals_surface_mapping():
+    """The fitted series evaluated directly and through its surface charges and
+    dipoles (Green's identity with the Fibonacci quadrature) agree."""
+    rng = np.random.default_rng(14)
+    x, q = _rand_system(rng, 30, oracle.BC_PERIODIC)
+    plan = oracle.make_plan(1.0, oracle.BC_PERIODIC, 12, 2500, 600, 2.7)
+    a = oracle.solve(plan, x, q)
+    b = oracle.solve(plan, x, q, far="direct")
+    assert np.abs(a["phi_out"] - b["phi_out"]).max() < 1e-9 * np.abs(a["phi"]).max()
+    assert np.abs(a["field_out"] - b["field_out"]).max() < 1e-8 * np.abs(a["field"]).max()
 
 
 # ---------------------------------------------------------------- LS + mapping
