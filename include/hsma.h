@@ -54,6 +54,28 @@ typedef enum {
 } hsma_precision;
 
 typedef enum {
+    HSMA_NEAR_BLOCK = 0,   /* near set: the 27 images of every source in the 3x3x3 block of boxes */
+    HSMA_NEAR_SPHERE = 1   /* near set: every image inside the auxiliary sphere |r| < R_s (the
+                              paper's literal near set, Sec. II.A); images generated per call;
+                              no adjoint and no serving in this mode */
+} hsma_near_mode;
+
+typedef enum {
+    HSMA_DIPOLE_EXACT = 0,  /* surface dipole as exact point dipoles (limit of Eq. (cd)) */
+    HSMA_DIPOLE_LAYERS = 1  /* the paper's form: the dipole layer replaced by two charge layers
+                               on the spheres R_s -+ dr/2 (Eq. (cd), Eq. (integrals)), i.e. three
+                               point charges per surface point; double precision; no adjoint and
+                               no serving in this mode */
+} hsma_dipole_mode;
+
+typedef enum {
+    HSMA_FAR_SURFACE = 0,  /* far field through the harmonic surface mapping (Sec. II.B) */
+    HSMA_FAR_DIRECT = 1    /* far field as the fitted series sum_k A_k B_k(r) and its gradient,
+                              evaluated at the particles (double precision); no adjoint and no
+                              serving in this mode */
+} hsma_far_mode;
+
+typedef enum {
     HSMA_OK = 0,
     HSMA_E_INVALID = -1,      /* bad argument (sizes, NULL, non-finite input, K < unknowns, R <= R0) */
     HSMA_E_NOT_NEUTRAL = -2,  /* periodic or slab system with non-zero total charge */
@@ -76,6 +98,10 @@ typedef struct {
     double R;          /* auxiliary sphere radius R_s > sqrt(3) L / 2 (alpha > 1, Sec. III) */
     int precision;     /* hsma_precision */
     uint64_t seed;     /* SplitMix64 seed of the grounded-cube face monitoring points */
+    int near_mode;     /* hsma_near_mode (hsma_plan_create: HSMA_NEAR_BLOCK) */
+    int dipole_mode;   /* hsma_dipole_mode (hsma_plan_create: HSMA_DIPOLE_EXACT) */
+    double dr;         /* layer spacing for HSMA_DIPOLE_LAYERS; <= 0 selects 1e-5 R_s */
+    int far_mode;      /* hsma_far_mode (hsma_plan_create: HSMA_FAR_SURFACE) */
 } hsma_plan_desc;
 
 typedef struct {
@@ -90,13 +116,19 @@ typedef struct {
     int precision;
     int bc;
     size_t bytes_resident;  /* device bytes held by the plan */
+    int near_mode;
+    int max_images_per_source;  /* near images per source: 27, or the sphere-mode bound */
+    int dipole_mode;
+    double dr;
+    int far_mode;
 } hsma_plan_info_t;
 
 /* Optional device outputs of the intermediate stages (any pointer may be NULL). */
 typedef struct {
     double* b;           /* K values of the least-squares right-hand side */
     double* A;           /* N_b coefficients A_nm, index n^2 + n + m */
-    double* surf;        /* M_eff x 8: X, Y, Z, Q, p_x, p_y, p_z, 0 of the surface images */
+    double* surf;        /* M_eff x 8: X, Y, Z, Q, p_x, p_y, p_z, 0 of the surface images
+                            (exact-dipole plans; not written with charge layers) */
     double* phi_near;    /* N near-field potentials */
     double* field_near;  /* N x 3 near fields */
     double* phi_out;     /* N far-field potentials (surface images) */

@@ -1,5 +1,6 @@
 // C ABI of the HSMA library: argument checks, plans, host and device entry
 // points, kernel timing.
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -96,6 +97,16 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     const int nu = (d->bc == HSMA_BC_METALLIC) ? nb : nb - 1;
     if (d->K < nu || d->K > (1 << 24)) return fail(HSMA_E_INVALID, "K must be >= number of unknowns");
     if (d->M < 4 || d->M > (1 << 22)) return fail(HSMA_E_INVALID, "M out of range");
+    if (d->near_mode != HSMA_NEAR_BLOCK && d->near_mode != HSMA_NEAR_SPHERE)
+        return fail(HSMA_E_INVALID, "unknown near mode");
+    if (d->far_mode != HSMA_FAR_SURFACE && d->far_mode != HSMA_FAR_DIRECT)
+        return fail(HSMA_E_INVALID, "unknown far-field mode");
+    if (d->dipole_mode != HSMA_DIPOLE_EXACT && d->dipole_mode != HSMA_DIPOLE_LAYERS)
+        return fail(HSMA_E_INVALID, "unknown dipole mode");
+    if (d->dipole_mode == HSMA_DIPOLE_LAYERS && !(d->dr < 0.5 * (d->R - std::sqrt(3.0) * d->L / 2.0)))
+        return fail(HSMA_E_INVALID, "layer spacing dr too large for R");
+    if (d->near_mode == HSMA_NEAR_SPHERE && d->R > 12.0 * d->L)
+        return fail(HSMA_E_INVALID, "sphere near set limited to R <= 12 L");
     hsma_plan_s* pl = new (std::nothrow) hsma_plan_s();
     if (pl == nullptr) return fail(HSMA_E_NOMEM, "host allocation failed");
     pl->desc = *d;
@@ -109,6 +120,24 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     pl->R0 = R0;
     pl->Rs = d->R;
     pl->precision = d->precision;
+    pl->near_mode = d->near_mode;
+    pl->dipole_mode = d->dipole_mode;
+    pl->far_mode = d->far_mode;
+    pl->dr = d->dr > 0.0 ? d->dr : 1e-5 * d->R;
+    if (pl->near_mode == HSMA_NEAR_SPHERE) {
+        // candidates |k_a| <= kr; a source has at most as many images inside the
+        // sphere as there are shifted boxes that reach it
+        pl->kr = (int)std::ceil(d->R / d->L + 0.5);
+        int cnt = 0;
+        for (int a = -pl->kr; a <= pl->kr; ++a)
+            for (int b = -pl->kr; b <= pl->kr; ++b)
+                for (int c = -pl->kr; c <= pl->kr; ++c) {
+                    auto gap = [&](int k) { double g = std::fabs((double)k) - 0.5; return g > 0 ? g * d->L : 0.0; };
+                    const double d2 = gap(a) * gap(a) + gap(b) * gap(b) + gap(c) * gap(c);
+                    if (d2 < d->R * d->R) ++cnt;
+                }
+        pl->maxper = cnt;
+    }
     hsma_status st = build_plan(pl);
     if (st != HSMA_OK) {
         free_plan(pl);
@@ -135,6 +164,10 @@ hsma_status hsma_plan_create(double L, int bc, int p, int M, int K, double R, hs
     d.R = R;
     d.precision = HSMA_FP64;
     d.seed = 12345;
+    d.near_mode = HSMA_NEAR_BLOCK;
+    d.dipole_mode = HSMA_DIPOLE_EXACT;
+    d.dr = 0.0;
+    d.far_mode = HSMA_FAR_SURFACE;
     return hsma_plan_create_ex(&d, out);
 }
 
@@ -158,6 +191,11 @@ hsma_status hsma_plan_info(hsma_plan pl, hsma_plan_info_t* info) {
     info->precision = pl->precision;
     info->bc = pl->bc;
     info->bytes_resident = pl->bytes;
+    info->near_mode = pl->near_mode;
+    info->max_images_per_source = pl->maxper;
+    info->dipole_mode = pl->dipole_mode;
+    info->dr = pl->dr;
+    info->far_mode = pl->far_mode;
     return HSMA_OK;
 }
 
@@ -187,6 +225,9 @@ static hsma_status check_sizes(hsma_plan pl, int64_t N) {
     if (N < 1 || N > (int64_t)1 << 28) return fail(HSMA_E_INVALID, "N out of range");
     if (pl->bc == HSMA_BC_SLAB_METALLIC_Z && N > (int64_t)1 << 27)
         return fail(HSMA_E_INVALID, "N out of range for the slab");
+    const int64_t ns = (pl->bc == HSMA_BC_SLAB_METALLIC_Z) ? 2 * N : N;
+    if (pl->near_mode == HSMA_NEAR_SPHERE && ns * pl->maxper > (int64_t)INT32_MAX)
+        return fail(HSMA_E_INVALID, "too many sphere images for N");
     return HSMA_OK;
 }
 
@@ -215,6 +256,11 @@ hsma_status hsma_energy_grad_device(hsma_plan pl, const double* x, const double*
     if (x == nullptr || q == nullptr || workspace == nullptr || energy == nullptr ||
         dEdx == nullptr || dEdq == nullptr)
         return fail(HSMA_E_INVALID, "NULL argument");
+    if (pl->near_mode != HSMA_NEAR_BLOCK)
+        return fail(HSMA_E_INVALID, "the adjoint needs the block near set (the sphere set moves "
+                                    "images in and out as charges move)");
+    if (pl->dipole_mode != HSMA_DIPOLE_EXACT || pl->far_mode != HSMA_FAR_SURFACE)
+        return fail(HSMA_E_INVALID, "the adjoint needs the surface mapping with exact dipoles");
     const Layout ly = make_layout(pl, N, true);
     if (workspace_bytes < ly.total) return fail(HSMA_E_NOMEM, "workspace too small");
     HSMA_HIP(hipSetDevice(pl->device));

@@ -79,6 +79,12 @@ struct hsma_plan_s {
     int p = 0, nb = 0, nu = 0, K = 0, nchk = 0, M = 0, F1 = 0, F2 = 0;
     double L = 1.0, R0 = 0.0, Rs = 0.0;
     int precision = 0;
+    int near_mode = 0;
+    int kr = 1;           // sphere mode: images with |k_a| <= kr are candidates
+    int maxper = 27;      // near images per source (upper bound in sphere mode)
+    int dipole_mode = 0;  // HSMA_DIPOLE_EXACT or HSMA_DIPOLE_LAYERS
+    double dr = 0.0;      // layer spacing (charge-layer dipoles)
+    int far_mode = 0;     // HSMA_FAR_SURFACE or HSMA_FAR_DIRECT
     // host geometry (centred)
     std::vector<double> chk;    // nchk x 3: monitoring points then twins
     std::vector<double> spts;   // M x 3
@@ -108,11 +114,19 @@ hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, con
 hipError_t launch_surface_f64(const double4* tgt, const double* surf, const PairGeom& g,
                               double* out, hipStream_t s);
 hipError_t launch_group_tiles(bool f32, const TileItem* items, int n, hipStream_t s);
+// Pair sums over an explicit list of charges (double4 or Rec32 records).
+hipError_t launch_explicit(bool f32, bool field, bool self, const void* tgt, const void* src,
+                           const PairGeom& g, double L, double* out, hipStream_t s);
 // Sum the chunks of a pair-kernel output: res[comp * ld + t] = sum_c out[...].
 hipError_t launch_chunk_reduce(const double* out, const PairGeom& g, int ncomp, double* res, int ld,
                                hipStream_t s);
 // Records from centred double positions.
 hipError_t launch_make_rec32(const double4* p, int n, double L, Rec32* out, hipStream_t s);
+
+// Far field straight from the fitted series (plan.hip): out[comp * nt_pad + t],
+// comp 0 = sum_k A_k B_k(r_t), 1..3 = -grad.
+hipError_t launch_far_direct(const double4* tgt, int nt, int nt_pad, int P, double invR0,
+                             const double* A, double* out, hipStream_t s);
 
 // Plan kernels (plan.hip).
 hipError_t launch_basis(const double* pts, int npts, int P, double invR0, double* out, int ld_pt,

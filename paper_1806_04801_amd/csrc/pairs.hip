@@ -296,13 +296,15 @@ __device__ __forceinline__ void images_f32(const float (&dx)[3], const float (&d
     }
 }
 
-// One tile in single precision.  Sources are taken two at a time: their two
-// (plain float) contributions are combined and folded into (hi, lo)
-// accumulators by one two-sum.  Outputs are scaled back to physical units.
+// One tile in single precision.  Each lane sums the (plain float)
+// contributions of up to 8 sources into partials and folds them into (hi, lo)
+// accumulators with one two-sum per component.  Outputs are scaled back to
+// physical units.
 template <int IMG, bool FIELD, bool SELF, int T>
 __device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __restrict__ tgt, int nt,
                                               const Rec32* __restrict__ src, int ns, int chunk,
                                               double* __restrict__ out, int nt_pad, double invL) {
+    constexpr int G = 8;
     const int j0 = c * chunk;
     const int j1 = min(j0 + chunk, ns);
     Pt32 tp[T];
@@ -313,49 +315,39 @@ __device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __rest
         tp[u] = load_pt32(tgt[min(t, nt - 1)]);
         ph[u] = pl[u] = xh[u] = xl[u] = yh[u] = yl[u] = zh[u] = zl[u] = 0.0f;
     }
-    int j = j0;
-    for (; j + 1 < j1; j += 2) {
-        const Rec32 r0 = src[j];
-        const Rec32 r1 = src[j + 1];
-        const Pt32 s0 = load_pt32(r0), s1 = load_pt32(r1);
-        const float q0 = r0.v[0].w, q1 = r1.v[0].w;
+    for (int g0 = j0; g0 < j1; g0 += G) {
+        const int g1 = min(g0 + G, j1);
+        float sp[T], sx[T], sy[T], sz[T];
 #pragma unroll
-        for (int u = 0; u < T; ++u) {
-            float dx[3], dy[3], dz[3];
-            float p0, fx0, fy0, fz0, p1, fx1, fy1, fz1;
-            diffs_f32<IMG>(tp[u], s0, 0, dx);
-            diffs_f32<IMG>(tp[u], s0, 1, dy);
-            diffs_f32<IMG>(tp[u], s0, 2, dz);
-            images_f32<IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
-            diffs_f32<IMG>(tp[u], s1, 0, dx);
-            diffs_f32<IMG>(tp[u], s1, 1, dy);
-            diffs_f32<IMG>(tp[u], s1, 2, dz);
-            images_f32<IMG, FIELD, SELF>(dx, dy, dz, p1, fx1, fy1, fz1);
-            two_sum_acc(ph[u], pl[u], __builtin_fmaf(q1, p1, q0 * p0));
-            if (FIELD) {
-                two_sum_acc(xh[u], xl[u], __builtin_fmaf(q1, fx1, q0 * fx0));
-                two_sum_acc(yh[u], yl[u], __builtin_fmaf(q1, fy1, q0 * fy0));
-                two_sum_acc(zh[u], zl[u], __builtin_fmaf(q1, fz1, q0 * fz0));
+        for (int u = 0; u < T; ++u) sp[u] = sx[u] = sy[u] = sz[u] = 0.0f;
+#pragma unroll 2
+        for (int j = g0; j < g1; ++j) {
+            const Rec32 r0 = src[j];
+            const Pt32 s0 = load_pt32(r0);
+            const float q0 = r0.v[0].w;
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                float dx[3], dy[3], dz[3];
+                float p0, fx0, fy0, fz0;
+                diffs_f32<IMG>(tp[u], s0, 0, dx);
+                diffs_f32<IMG>(tp[u], s0, 1, dy);
+                diffs_f32<IMG>(tp[u], s0, 2, dz);
+                images_f32<IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
+                sp[u] = __builtin_fmaf(q0, p0, sp[u]);
+                if (FIELD) {
+                    sx[u] = __builtin_fmaf(q0, fx0, sx[u]);
+                    sy[u] = __builtin_fmaf(q0, fy0, sy[u]);
+                    sz[u] = __builtin_fmaf(q0, fz0, sz[u]);
+                }
             }
         }
-    }
-    if (j < j1) {
-        const Rec32 r0 = src[j];
-        const Pt32 s0 = load_pt32(r0);
-        const float q0 = r0.v[0].w;
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-            float dx[3], dy[3], dz[3];
-            float p0, fx0, fy0, fz0;
-            diffs_f32<IMG>(tp[u], s0, 0, dx);
-            diffs_f32<IMG>(tp[u], s0, 1, dy);
-            diffs_f32<IMG>(tp[u], s0, 2, dz);
-            images_f32<IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
-            two_sum_acc(ph[u], pl[u], q0 * p0);
+            two_sum_acc(ph[u], pl[u], sp[u]);
             if (FIELD) {
-                two_sum_acc(xh[u], xl[u], q0 * fx0);
-                two_sum_acc(yh[u], yl[u], q0 * fy0);
-                two_sum_acc(zh[u], zl[u], q0 * fz0);
+                two_sum_acc(xh[u], xl[u], sx[u]);
+                two_sum_acc(yh[u], yl[u], sy[u]);
+                two_sum_acc(zh[u], zl[u], sz[u]);
             }
         }
     }
@@ -380,6 +372,171 @@ k_pair_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src,
            int chunk, double* __restrict__ out, int nt_pad, double invL) {
     tile_pair_f32<IMG, FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, out, nt_pad,
                                        invL);
+}
+
+// ---------------------------------------------------------------- explicit charges
+// Tiles over an explicit list of point charges (the paper's near set "every
+// image inside the auxiliary sphere", generated per source): one pair per
+// (target, charge).  SELF: a charge at exactly the target's position (its own
+// unshifted copy) is skipped.  The single-precision version sums 8 charges in
+// plain float per lane before each two-sum fold.
+template <bool FIELD, bool SELF, int T>
+__device__ __forceinline__ void tile_free_f64(int tb, int c, const double4* __restrict__ tgt, int nt,
+                                              const double4* __restrict__ src, int ns, int chunk,
+                                              double* __restrict__ out, int nt_pad) {
+    const int j0 = c * chunk;
+    const int j1 = min(j0 + chunk, ns);
+    double tx[T], ty[T], tz[T], ap[T], ax[T], ay[T], az[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (tb * T + u) * WG + threadIdx.x;
+        const double4 r = tgt[min(t, nt - 1)];
+        tx[u] = r.x; ty[u] = r.y; tz[u] = r.z;
+        ap[u] = ax[u] = ay[u] = az[u] = 0.0;
+    }
+    for (int j = j0; j < j1; ++j) {
+        const double4 s = src[j];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double dx = tx[u] - s.x, dy = ty[u] - s.y, dz = tz[u] - s.z;
+            const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+            double y = rsqrt_f64(r2);
+            if (SELF) y = (r2 > 0.0) ? y : 0.0;
+            const double qy = s.w * y;
+            ap[u] += qy;
+            if (FIELD) {
+                const double w = qy * y * y;
+                ax[u] = __builtin_fma(w, dx, ax[u]);
+                ay[u] = __builtin_fma(w, dy, ay[u]);
+                az[u] = __builtin_fma(w, dz, az[u]);
+            }
+        }
+    }
+    constexpr int ncomp = FIELD ? 4 : 1;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (tb * T + u) * WG + threadIdx.x;
+        double* o = out + (size_t)c * ncomp * nt_pad + t;
+        o[0] = ap[u];
+        if (FIELD) {
+            o[(size_t)nt_pad] = ax[u];
+            o[(size_t)2 * nt_pad] = ay[u];
+            o[(size_t)3 * nt_pad] = az[u];
+        }
+    }
+}
+
+template <bool FIELD, bool SELF, int T>
+__device__ __forceinline__ void tile_free_f32(int tb, int c, const Rec32* __restrict__ tgt, int nt,
+                                              const Rec32* __restrict__ src, int ns, int chunk,
+                                              double* __restrict__ out, int nt_pad, double invL) {
+    constexpr int G = 8;
+    const int j0 = c * chunk;
+    const int j1 = min(j0 + chunk, ns);
+    float th[T][3], tl[T][3];
+    float ph[T], pl[T], xh[T], xl[T], yh[T], yl[T], zh[T], zl[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (tb * T + u) * WG + threadIdx.x;
+        const Pt32 p = load_pt32(tgt[min(t, nt - 1)]);
+        for (int a = 0; a < 3; ++a) { th[u][a] = p.h0[a]; tl[u][a] = p.l[a]; }
+        ph[u] = pl[u] = xh[u] = xl[u] = yh[u] = yl[u] = zh[u] = zl[u] = 0.0f;
+    }
+    for (int g0 = j0; g0 < j1; g0 += G) {
+        const int g1 = min(g0 + G, j1);
+        float sp[T], sx[T], sy[T], sz[T];
+#pragma unroll
+        for (int u = 0; u < T; ++u) sp[u] = sx[u] = sy[u] = sz[u] = 0.0f;
+        for (int j = g0; j < g1; ++j) {
+            const Pt32 s = load_pt32(src[j]);
+            const float q = src[j].v[0].w;
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                const float dx = (th[u][0] - s.h0[0]) + (tl[u][0] - s.l[0]);
+                const float dy = (th[u][1] - s.h0[1]) + (tl[u][1] - s.l[1]);
+                const float dz = (th[u][2] - s.h0[2]) + (tl[u][2] - s.l[2]);
+                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                float y = __builtin_amdgcn_rsqf(r2);
+                if (SELF) y = (r2 > 0.0f) ? y : 0.0f;
+                const float qy = q * y;
+                sp[u] += qy;
+                if (FIELD) {
+                    const float w = qy * y * y;
+                    sx[u] = __builtin_fmaf(w, dx, sx[u]);
+                    sy[u] = __builtin_fmaf(w, dy, sy[u]);
+                    sz[u] = __builtin_fmaf(w, dz, sz[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            two_sum_acc(ph[u], pl[u], sp[u]);
+            if (FIELD) {
+                two_sum_acc(xh[u], xl[u], sx[u]);
+                two_sum_acc(yh[u], yl[u], sy[u]);
+                two_sum_acc(zh[u], zl[u], sz[u]);
+            }
+        }
+    }
+    constexpr int ncomp = FIELD ? 4 : 1;
+    const double invL2 = invL * invL;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int t = (tb * T + u) * WG + threadIdx.x;
+        double* o = out + (size_t)c * ncomp * nt_pad + t;
+        o[0] = ((double)ph[u] + (double)pl[u]) * invL;
+        if (FIELD) {
+            o[(size_t)nt_pad] = ((double)xh[u] + (double)xl[u]) * invL2;
+            o[(size_t)2 * nt_pad] = ((double)yh[u] + (double)yl[u]) * invL2;
+            o[(size_t)3 * nt_pad] = ((double)zh[u] + (double)zl[u]) * invL2;
+        }
+    }
+}
+
+template <bool FIELD, bool SELF, int T>
+__global__ void __launch_bounds__(WG)
+k_free_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ src, int ns,
+           int chunk, double* __restrict__ out, int nt_pad) {
+    tile_free_f64<FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, out, nt_pad);
+}
+
+template <bool FIELD, bool SELF, int T>
+__global__ void __launch_bounds__(WG)
+k_free_f32(const Rec32* __restrict__ tgt, int nt, const Rec32* __restrict__ src, int ns,
+           int chunk, double* __restrict__ out, int nt_pad, double invL) {
+    tile_free_f32<FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, out, nt_pad, invL);
+}
+
+template <bool FIELD, bool SELF>
+static hipError_t free_launch(bool f32, const void* tgt, const void* src, const PairGeom& g,
+                              double L, double* out, hipStream_t s) {
+    dim3 grid(g.ntb, g.S);
+    if (f32) {
+        if (g.tpl == 2)
+            hipLaunchKernelGGL((k_free_f32<FIELD, SELF, 2>), grid, dim3(WG), 0, s, (const Rec32*)tgt,
+                               g.nt, (const Rec32*)src, g.ns, g.chunk, out, g.nt_pad, 1.0 / L);
+        else
+            hipLaunchKernelGGL((k_free_f32<FIELD, SELF, 1>), grid, dim3(WG), 0, s, (const Rec32*)tgt,
+                               g.nt, (const Rec32*)src, g.ns, g.chunk, out, g.nt_pad, 1.0 / L);
+    } else {
+        if (g.tpl == 2)
+            hipLaunchKernelGGL((k_free_f64<FIELD, SELF, 2>), grid, dim3(WG), 0, s, (const double4*)tgt,
+                               g.nt, (const double4*)src, g.ns, g.chunk, out, g.nt_pad);
+        else
+            hipLaunchKernelGGL((k_free_f64<FIELD, SELF, 1>), grid, dim3(WG), 0, s, (const double4*)tgt,
+                               g.nt, (const double4*)src, g.ns, g.chunk, out, g.nt_pad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_explicit(bool f32, bool field, bool self, const void* tgt, const void* src,
+                           const PairGeom& g, double L, double* out, hipStream_t s) {
+    if (g.nt <= 0) return hipSuccess;
+    if (g.tpl != 1 && g.tpl != 2) return hipErrorInvalidValue;
+    if (field) return self ? free_launch<true, true>(f32, tgt, src, g, L, out, s)
+                           : free_launch<true, false>(f32, tgt, src, g, L, out, s);
+    if (self) return hipErrorInvalidValue;
+    return free_launch<false, false>(f32, tgt, src, g, L, out, s);
 }
 
 // ---------------------------------------------------------------- surface images

@@ -69,6 +69,85 @@ __global__ void k_basis(const double* __restrict__ pts, int npts, int P, double 
     }
 }
 
+// Far field evaluated from the fitted series (Eq. (harmonic)) at targets:
+// phi = sum_k A_k B_k(r), E = -sum_k A_k grad B_k(r).  The recurrence of
+// k_basis is carried with its derivatives: Pi_n^m depends on (u_z, |u|^2), so
+// grad Pi = (2 u_x Pr, 2 u_y Pr, Pz + 2 u_z Pr) with Pz = dPi/du_z and
+// Pr = dPi/d|u|^2 from the differentiated three-term recurrence, and
+// d/du_x (u_x + i u_y)^m = m (u_x + i u_y)^(m-1), d/du_y = i m (u_x + i u_y)^(m-1).
+__global__ void __launch_bounds__(256) k_far_direct(const double4* __restrict__ tgt, int nt,
+                                                   int nt_pad, int P, double invR0,
+                                                   const double* __restrict__ A,
+                                                   double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt_pad) return;
+    const double4 r = tgt[min(t, nt - 1)];
+    const double x = r.x * invR0, y = r.y * invR0, z = r.z * invR0;
+    const double rho = x * x + y * y + z * z;
+    const double sq2 = 1.4142135623730951;
+    double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    double pmm = 0.28209479177387814;
+    double cm = 1.0, sm = 0.0, cm1 = 0.0, sm1 = 0.0;  // (x+iy)^m and (x+iy)^(m-1)
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            pmm *= sqrt((2.0 * m + 1.0) / (2.0 * m));
+            cm1 = cm;
+            sm1 = sm;
+            const double cn = cm * x - sm * y;
+            sm = cm * y + sm * x;
+            cm = cn;
+        }
+        // T = C_m (k = n^2+n+m) and S_m (k = n^2+n-m) with their gradients
+        const double fc = (m == 0) ? 1.0 : sq2;
+        const double dCx = m * cm1, dCy = -m * sm1, dSx = m * sm1, dSy = m * cm1;
+        auto acc = [&](int n, double Pi, double Pz, double Pr) {
+            const double dPx = 2.0 * x * Pr, dPy = 2.0 * y * Pr, dPz = Pz + 2.0 * z * Pr;
+            const int kc = n * n + n + m;
+            const double ac = fc * A[kc];
+            phi += ac * Pi * cm;
+            gx += ac * (dPx * cm + Pi * dCx);
+            gy += ac * (dPy * cm + Pi * dCy);
+            gz += ac * (dPz * cm);
+            if (m > 0) {
+                const double as = sq2 * A[n * n + n - m];
+                phi += as * Pi * sm;
+                gx += as * (dPx * sm + Pi * dSx);
+                gy += as * (dPy * sm + Pi * dSy);
+                gz += as * (dPz * sm);
+            }
+        };
+        double p2 = pmm, z2 = 0.0, r2 = 0.0;          // n = m
+        acc(m, p2, z2, r2);
+        if (m == P) break;
+        const double c1 = sqrt(2.0 * m + 3.0);
+        double p1 = c1 * z * pmm, z1 = c1 * pmm, r1 = 0.0;  // n = m + 1
+        acc(m + 1, p1, z1, r1);
+        for (int n = m + 2; n <= P; ++n) {
+            const double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+            const double b = sqrt((((double)n - 1.0) * (n - 1.0) - (double)m * m) /
+                                  (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+            const double p0 = a * (z * p1 - b * rho * p2);
+            const double z0 = a * (p1 + z * z1 - b * rho * z2);
+            const double r0 = a * (z * r1 - b * p2 - b * rho * r2);
+            acc(n, p0, z0, r0);
+            p2 = p1; z2 = z1; r2 = r1;
+            p1 = p0; z1 = z0; r1 = r0;
+        }
+    }
+    out[t] = phi;
+    out[(size_t)nt_pad + t] = -gx * invR0;
+    out[(size_t)2 * nt_pad + t] = -gy * invR0;
+    out[(size_t)3 * nt_pad + t] = -gz * invR0;
+}
+
+hipError_t launch_far_direct(const double4* tgt, int nt, int nt_pad, int P, double invR0,
+                             const double* A, double* out, hipStream_t s) {
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_far_direct, dim3((nt_pad + 255) / 256), dim3(256), 0, s, tgt, nt, nt_pad, P,
+                       invR0, A, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_basis(const double* pts, int npts, int P, double invR0, double* out, int ld_pt,
                         int ld_k, int k0, hipStream_t s) {
     if (npts <= 0) return hipSuccess;

@@ -521,6 +521,9 @@ static hsma_status submit_impl(hsma_server sv, hsma_plan plan, const double* x, 
     if (sv == nullptr || plan == nullptr || x == nullptr || q == nullptr || id == nullptr)
         return fail(HSMA_E_INVALID, "NULL argument");
     if (N < 1 || N > ((int64_t)1 << 26)) return fail(HSMA_E_INVALID, "N out of range");
+    if (plan->near_mode != HSMA_NEAR_BLOCK || plan->dipole_mode != HSMA_DIPOLE_EXACT ||
+        plan->far_mode != HSMA_FAR_SURFACE)
+        return fail(HSMA_E_INVALID, "the server runs block near-set, exact-dipole plans only");
     Layout ly;
     if (req_device_bytes(plan, (int)N, sv->desc.precision, &ly) > sv->arena->cap() ||
         req_host_bytes((int)N) > sv->host_arena->cap()) {
@@ -690,6 +693,7 @@ hsma_status hsma_run_trace_sequential(int64_t n, const double* arrival_s, const 
     int64_t nmax = 1;
     size_t wsmax = 0;
     for (int64_t i = 0; i < n; ++i) {
+        if (plans[i] == nullptr) return fail(HSMA_E_INVALID, "NULL plan");
         nmax = std::max(nmax, Ns[i]);
         wsmax = std::max(wsmax, make_layout(plans[i], Ns[i], false).total);
     }

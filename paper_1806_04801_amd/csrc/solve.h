@@ -21,6 +21,8 @@ struct Layout {
     size_t off_near_part = 0, off_surf_part = 0, off_eblk = 0, off_result = 0;
     size_t off_u_part = 0, off_tw = 0, off_lam64 = 0, off_lam32 = 0, off_G_part = 0,
            off_real32 = 0, off_ud = 0;
+    size_t off_cnt = 0, off_imgoff = 0, off_img64 = 0, off_img32 = 0;   // sphere near set
+    int64_t img_max = 0;
     int n_eblk = 1;
     size_t total = 0;
 };

@@ -1,6 +1,8 @@
 // Update step of the HSMA (Sec. II.C) on one GPU: sources -> right-hand side
 // at the monitoring points -> least-squares coefficients -> surface images ->
 // near-field and surface sums at the particles -> energy and forces.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "hsma_internal.h"
@@ -29,9 +31,15 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     const bool f32 = prec == HSMA_FP32_COMP;
     const int tpl_near = tpl_near_override > 0 ? tpl_near_override : env_int("HSMA_TPL_NEAR", 2);
     const int tpl_rhs = env_int("HSMA_TPL_RHS", 1);
-    ly.g_rhs = pair_geometry(pl->nchk, ly.ns, tpl_rhs, pl->ncu);
-    ly.g_near = pair_geometry(ly.N, ly.ns, tpl_near, pl->ncu);
-    ly.g_surf = pair_geometry(ly.N, pl->M, 1, pl->ncu);
+    const bool sphere = pl->near_mode == HSMA_NEAR_SPHERE;
+    // sphere mode: sources are the explicit images (at most maxper per source);
+    // partial buffers are sized for that bound
+    ly.img_max = sphere ? (int64_t)ly.ns * pl->maxper : 0;
+    const int ns_pairs = sphere ? (int)std::min<int64_t>(ly.img_max, INT32_MAX) : ly.ns;
+    ly.g_rhs = pair_geometry(pl->nchk, ns_pairs, tpl_rhs, pl->ncu);
+    ly.g_near = pair_geometry(ly.N, ns_pairs, tpl_near, pl->ncu);
+    const int nsurf = pl->dipole_mode == HSMA_DIPOLE_LAYERS ? 3 * pl->M : pl->M;
+    ly.g_surf = pair_geometry(ly.N, nsurf, 1, pl->ncu);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     ly.off_src64 = take(sizeof(double4) * (size_t)ly.ns);
@@ -39,13 +47,19 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.off_rhs_part = take(sizeof(double) * (size_t)ly.g_rhs.S * ly.g_rhs.nt_pad);
     ly.off_b = take(sizeof(double) * (size_t)pl->K);
     ly.off_A = take(sizeof(double) * (size_t)pl->nb);
-    ly.off_surf = take(sizeof(double) * 8 * (size_t)pl->M);
+    ly.off_surf = take(sizeof(double) * 12 * (size_t)pl->M);   // 8 per point, or 3 charges
     ly.off_near_part = take(sizeof(double) * 4 * (size_t)ly.g_near.S * ly.g_near.nt_pad);
     ly.off_surf_part = take(sizeof(double) * 4 * (size_t)ly.g_surf.S * ly.g_surf.nt_pad);
     ly.n_eblk = (ly.N + WG - 1) / WG;
     if (ly.n_eblk < 1) ly.n_eblk = 1;
     ly.off_eblk = take(sizeof(double) * 3 * (size_t)ly.n_eblk);
     ly.off_result = take(sizeof(Result));
+    if (sphere) {
+        ly.off_cnt = take(sizeof(int) * (size_t)ly.ns);
+        ly.off_imgoff = take(sizeof(int) * ((size_t)ly.ns + 1));
+        ly.off_img64 = take(sizeof(double4) * (size_t)ly.img_max);
+        ly.off_img32 = f32 ? take(sizeof(Rec32) * (size_t)ly.img_max) : 0;
+    }
     if (grad) {
         ly.g_u = pair_geometry(pl->M, ly.N, 1, pl->ncu);
         ly.g_G = pair_geometry(ly.ns, pl->nchk, tpl_near, pl->ncu);
@@ -98,6 +112,15 @@ __global__ void __launch_bounds__(WG) k_map(const double* __restrict__ Wq,
     if (j < M) map_body(j, threadIdx.x & 63, Wq, Wp, nb, A, spos, Rs, surf);
 }
 
+__global__ void __launch_bounds__(WG) k_map_layers(const double* __restrict__ Wq,
+                                                  const double* __restrict__ Wp, int M, int nb,
+                                                  const double* __restrict__ A,
+                                                  const double* __restrict__ spos, double Rs,
+                                                  double dr, double4* __restrict__ chg) {
+    const int j = blockIdx.x * (WG / 64) + threadIdx.x / 64;
+    if (j < M) map_layers_body(j, threadIdx.x & 63, M, Wq, Wp, nb, A, spos, Rs, dr, chg);
+}
+
 __global__ void __launch_bounds__(WG)
 k_finalize(const double* __restrict__ near, int Sn, int npad, const double* __restrict__ surfp,
            int Ss, int spad, const double4* __restrict__ src, int N, double* __restrict__ phi,
@@ -110,6 +133,68 @@ k_finalize(const double* __restrict__ near, int Sn, int npad, const double* __re
 __global__ void __launch_bounds__(WG) k_energy(const double* __restrict__ eblk, int nblk,
                                               int need_neutral, Result* __restrict__ res) {
     energy_body(eblk, nblk, need_neutral, res);
+}
+
+// The paper's near set: every image of source i with |image| < Rs, for
+// |k_a| <= kr (periodic r + kL; grounded (-1)^k o r + kL, charge (-1)^|k| q),
+// in lexicographic k order.  count: number of images per source; write: the
+// images at the source's offset.
+template <bool WRITE>
+__global__ void k_sphere_images(const double4* __restrict__ src, int ns, int metallic, double L,
+                                double Rs, int kr, int* __restrict__ cnt,
+                                const int* __restrict__ off, double4* __restrict__ img) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    const double4 c = src[i];
+    const double R2 = Rs * Rs;
+    int n = 0;
+    int o = WRITE ? off[i] : 0;
+    for (int a = -kr; a <= kr; ++a)
+        for (int b = -kr; b <= kr; ++b)
+            for (int k = -kr; k <= kr; ++k) {
+                double px = c.x, py = c.y, pz = c.z, sg = 1.0;
+                if (metallic) {
+                    if (a & 1) { px = -px; sg = -sg; }
+                    if (b & 1) { py = -py; sg = -sg; }
+                    if (k & 1) { pz = -pz; sg = -sg; }
+                }
+                px += a * L;
+                py += b * L;
+                pz += k * L;
+                if (px * px + py * py + pz * pz < R2) {
+                    if (WRITE) img[o + n] = make_double4(px, py, pz, sg * c.w);
+                    ++n;
+                }
+            }
+    if (!WRITE) cnt[i] = n;
+}
+
+// Exclusive prefix sum of cnt[0..n) into off[0..n], off[n] = total (one block).
+__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int n,
+                                              int* __restrict__ off) {
+    __shared__ long long part[1024];
+    const int t = threadIdx.x;
+    const int seg = (n + 1023) / 1024;
+    const int b = t * seg, e = min(b + seg, n);
+    long long s = 0;
+    for (int i = b; i < e; ++i) s += cnt[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        long long acc = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const long long v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        off[n] = (int)acc;
+    }
+    __syncthreads();
+    long long acc = part[t];
+    for (int i = b; i < e; ++i) {
+        off[i] = (int)acc;
+        acc += cnt[i];
+    }
 }
 
 // ---------------------------------------------------------------- pipeline
@@ -141,34 +226,85 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
                        src64, &res->status);
     CK(hipGetLastError());
     if (f32) CK(launch_make_rec32(src64, ly.ns, pl->L, src32, s));
+    PairGeom g_rhs = ly.g_rhs, g_near = ly.g_near;
+    const bool sphere = pl->near_mode == HSMA_NEAR_SPHERE;
+    double4* img64 = nullptr;
+    Rec32* img32 = nullptr;
+    if (sphere) {
+        // explicit near images; their number sets the launch geometry
+        int* cnt = (int*)(ws + ly.off_cnt);
+        int* off = (int*)(ws + ly.off_imgoff);
+        img64 = (double4*)(ws + ly.off_img64);
+        const int metallic = pl->img == IMG_METALLIC ? 1 : 0;
+        hipLaunchKernelGGL(k_sphere_images<false>, dim3((ly.ns + WG - 1) / WG), dim3(WG), 0, s,
+                           src64, ly.ns, metallic, pl->L, pl->Rs, pl->kr, cnt, (const int*)nullptr,
+                           (double4*)nullptr);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, ly.ns, off);
+        hipLaunchKernelGGL(k_sphere_images<true>, dim3((ly.ns + WG - 1) / WG), dim3(WG), 0, s,
+                           src64, ly.ns, metallic, pl->L, pl->Rs, pl->kr, (int*)nullptr,
+                           (const int*)off, img64);
+        CK(hipGetLastError());
+        int n_img = 0;
+        CK(hipMemcpyAsync(&n_img, off + ly.ns, sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        if (n_img < 0 || (int64_t)n_img > ly.img_max)
+            return fail(HSMA_E_DEVICE, "image count out of range");
+        g_rhs = pair_geometry(pl->nchk, n_img, ly.g_rhs.tpl, pl->ncu);
+        g_near = pair_geometry(ly.N, n_img, ly.g_near.tpl, pl->ncu);
+        if (f32) {
+            img32 = (Rec32*)(ws + ly.off_img32);
+            CK(launch_make_rec32(img64, n_img, pl->L, img32, s));
+        }
+    }
     // right-hand side at the monitoring points (and twins)
     timing_begin(1, s);
-    if (f32)
-        CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, ly.g_rhs, pl->L,
-                           rhs_part, s));
+    if (sphere)
+        CK(launch_explicit(f32, false, false, f32 ? (const void*)pl->d_chk32 : (const void*)pl->d_chk64,
+                           f32 ? (const void*)img32 : (const void*)img64, g_rhs, pl->L, rhs_part, s));
+    else if (f32)
+        CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, g_rhs, pl->L, rhs_part, s));
     else
-        CK(launch_pair_f64(pl->img, false, false, pl->d_chk64, src64, ly.g_rhs, pl->L, rhs_part, s));
+        CK(launch_pair_f64(pl->img, false, false, pl->d_chk64, src64, g_rhs, pl->L, rhs_part, s));
     timing_end(1, s);
     hipLaunchKernelGGL(k_rhs_finalize, dim3((pl->K + WG - 1) / WG), dim3(WG), 0, s, rhs_part,
-                       ly.g_rhs.S, ly.g_rhs.nt_pad, pl->K, pl->img == IMG_PERIODIC ? 1 : 0, b);
+                       g_rhs.S, g_rhs.nt_pad, pl->K, pl->img == IMG_PERIODIC ? 1 : 0, b);
     hipLaunchKernelGGL(k_lsq, dim3((pl->nu + 3) / 4), dim3(WG), 0, s, pl->d_P, pl->nu, pl->K, b,
                        pl->nb - pl->nu, A);
-    hipLaunchKernelGGL(k_map, dim3((pl->M + 3) / 4), dim3(WG), 0, s, pl->d_Wq, pl->d_Wp, pl->M,
-                       pl->nb, A, pl->d_spos, pl->Rs, surf);
+    const bool layers = pl->dipole_mode == HSMA_DIPOLE_LAYERS;
+    const bool direct = pl->far_mode == HSMA_FAR_DIRECT;
+    if (direct) {
+        // no mapping: the series is evaluated at the particles below
+    } else if (layers)
+        hipLaunchKernelGGL(k_map_layers, dim3((pl->M + 3) / 4), dim3(WG), 0, s, pl->d_Wq, pl->d_Wp,
+                           pl->M, pl->nb, A, pl->d_spos, pl->Rs, pl->dr, (double4*)surf);
+    else
+        hipLaunchKernelGGL(k_map, dim3((pl->M + 3) / 4), dim3(WG), 0, s, pl->d_Wq, pl->d_Wp, pl->M,
+                           pl->nb, A, pl->d_spos, pl->Rs, surf);
     CK(hipGetLastError());
     // near field at the particles: the sources and their 27 images, self excluded
     timing_begin(0, s);
-    if (f32)
-        CK(launch_pair_f32(pl->img, true, true, src32, src32, ly.g_near, pl->L, near_part, s));
+    if (sphere)
+        CK(launch_explicit(f32, true, true, f32 ? (const void*)src32 : (const void*)src64,
+                           f32 ? (const void*)img32 : (const void*)img64, g_near, pl->L, near_part, s));
+    else if (f32)
+        CK(launch_pair_f32(pl->img, true, true, src32, src32, g_near, pl->L, near_part, s));
     else
-        CK(launch_pair_f64(pl->img, true, true, src64, src64, ly.g_near, pl->L, near_part, s));
+        CK(launch_pair_f64(pl->img, true, true, src64, src64, g_near, pl->L, near_part, s));
     timing_end(0, s);
     // surface images at the particles
+    PairGeom g_surf = ly.g_surf;
     timing_begin(2, s);
-    CK(launch_surface_f64(src64, surf, ly.g_surf, surf_part, s));
+    if (direct) {
+        g_surf.S = 1;
+        CK(launch_far_direct(src64, N, g_surf.nt_pad, pl->p, 1.0 / pl->R0, A, surf_part, s));
+    } else if (layers) {
+        CK(launch_explicit(false, true, false, src64, surf, g_surf, pl->L, surf_part, s));
+    } else {
+        CK(launch_surface_f64(src64, surf, g_surf, surf_part, s));
+    }
     timing_end(2, s);
-    hipLaunchKernelGGL(k_finalize, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, ly.g_near.S,
-                       ly.g_near.nt_pad, surf_part, ly.g_surf.S, ly.g_surf.nt_pad, src64, N, phi,
+    hipLaunchKernelGGL(k_finalize, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, g_near.S,
+                       g_near.nt_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, phi,
                        forces, dbg ? dbg->phi_near : nullptr, dbg ? dbg->field_near : nullptr,
                        dbg ? dbg->phi_out : nullptr, dbg ? dbg->field_out : nullptr, eblk);
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(WG), 0, s, eblk, ly.n_eblk,
@@ -177,7 +313,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     if (dbg) {
         if (dbg->b) CK(hipMemcpyAsync(dbg->b, b, sizeof(double) * pl->K, hipMemcpyDeviceToDevice, s));
         if (dbg->A) CK(hipMemcpyAsync(dbg->A, A, sizeof(double) * pl->nb, hipMemcpyDeviceToDevice, s));
-        if (dbg->surf)
+        if (dbg->surf && !layers && !direct)
             CK(hipMemcpyAsync(dbg->surf, surf, sizeof(double) * 8 * pl->M, hipMemcpyDeviceToDevice, s));
     }
     return HSMA_OK;

@@ -54,9 +54,12 @@ __device__ __forceinline__ void rec32_body(int i, const double4* __restrict__ p,
     const double c[3] = {r.x * inv, r.y * inv, r.z * inv};
     float h[3], l[3];
     for (int a = 0; a < 3; ++a) {
+        // inside the box |c| <= 1/2 the 2^-24 grid value is exact in float;
+        // outside (check points, images) the float may round it, so the lo
+        // part is taken against the stored hi part
         const double hq = rint(c[a] * 16777216.0) * (1.0 / 16777216.0);
         h[a] = (float)hq;
-        l[a] = (float)(c[a] - hq);
+        l[a] = (float)(c[a] - (double)h[a]);
     }
     Rec32 o;
     o.v[0] = make_float4(h[0], h[1], h[2], (float)r.w);
@@ -120,6 +123,35 @@ __device__ __forceinline__ void map_body(int j, int lane, const double* __restri
         double* o = surf + 8 * (size_t)j;
         o[0] = X; o[1] = Y; o[2] = Z; o[3] = sq;
         o[4] = sp * X / Rs; o[5] = sp * Y / Rs; o[6] = sp * Z / Rs; o[7] = 0.0;
+    }
+}
+
+// The paper's form of the mapping (Eq. (cd), Eq. (integrals)) for surface
+// point j: the charge Q_j at R_j and, for the dipole layer, the charges
+// +w_j Phi_out(R_j)/(4 pi dr) at (R_s - dr/2) n_j and -w_j Phi_out(R_j)/(4 pi dr)
+// at (R_s + dr/2) n_j.  Wp_j . A = -w_j Phi_out(R_j)/(4 pi).  One wave.
+__device__ __forceinline__ void map_layers_body(int j, int lane, int M, const double* __restrict__ Wq,
+                                                const double* __restrict__ Wp, int nb,
+                                                const double* __restrict__ A,
+                                                const double* __restrict__ spos, double Rs, double dr,
+                                                double4* __restrict__ chg) {
+    const double* wq = Wq + (size_t)j * nb;
+    const double* wp = Wp + (size_t)j * nb;
+    double sq = 0.0, sp = 0.0;
+    for (int k = lane; k < nb; k += 64) {
+        const double a = A[k];
+        sq = __builtin_fma(wq[k], a, sq);
+        sp = __builtin_fma(wp[k], a, sp);
+    }
+    sq = wave_sum(sq);
+    sp = wave_sum(sp);
+    if (lane == 0) {
+        const double nx = spos[4 * j] / Rs, ny = spos[4 * j + 1] / Rs, nz = spos[4 * j + 2] / Rs;
+        const double ql = -sp / dr;                 // w_j Phi_out(R_j) / (4 pi dr)
+        const double ri = Rs - 0.5 * dr, ro = Rs + 0.5 * dr;
+        chg[j] = make_double4(spos[4 * j], spos[4 * j + 1], spos[4 * j + 2], sq);
+        chg[M + j] = make_double4(ri * nx, ri * ny, ri * nz, ql);
+        chg[2 * M + j] = make_double4(ro * nx, ro * ny, ro * nz, -ql);
     }
 }
 

@@ -18,6 +18,12 @@ BC_METALLIC = 1
 BC_SLAB = 2
 FP64 = 0
 FP32_COMP = 1
+NEAR_BLOCK = 0
+NEAR_SPHERE = 1
+DIPOLE_EXACT = 0
+DIPOLE_LAYERS = 1
+FAR_SURFACE = 0
+FAR_DIRECT = 1
 DEFAULT_SEED = 12345
 
 _lib = None
@@ -32,7 +38,8 @@ class HsmaError(RuntimeError):
 class PlanDesc(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double), ("bc", ctypes.c_int), ("p", ctypes.c_int),
                 ("M", ctypes.c_int), ("K", ctypes.c_int), ("R", ctypes.c_double),
-                ("precision", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("near_mode", ctypes.c_int),
+                ("dipole_mode", ctypes.c_int), ("dr", ctypes.c_double), ("far_mode", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -40,7 +47,9 @@ class PlanInfo(ctypes.Structure):
                 ("n_check", ctypes.c_int), ("M_eff", ctypes.c_int), ("F1", ctypes.c_int),
                 ("F2", ctypes.c_int), ("R0", ctypes.c_double), ("Rs", ctypes.c_double),
                 ("precision", ctypes.c_int), ("bc", ctypes.c_int),
-                ("bytes_resident", ctypes.c_size_t)]
+                ("bytes_resident", ctypes.c_size_t), ("near_mode", ctypes.c_int),
+                ("max_images_per_source", ctypes.c_int), ("dipole_mode", ctypes.c_int),
+                ("dr", ctypes.c_double), ("far_mode", ctypes.c_int)]
 
 
 class Intermediates(ctypes.Structure):
@@ -139,10 +148,12 @@ def _stream_handle(torch, device):
 class Plan:
     """An HSMA plan (preparation step) resident on the current GPU."""
 
-    def __init__(self, L, bc, p, M, K, R, precision=FP64, seed=DEFAULT_SEED):
+    def __init__(self, L, bc, p, M, K, R, precision=FP64, seed=DEFAULT_SEED, near_mode=NEAR_BLOCK,
+                 dipole_mode=DIPOLE_EXACT, dr=0.0, far_mode=FAR_SURFACE):
         lib = load()
         d = PlanDesc(L=float(L), bc=int(bc), p=int(p), M=int(M), K=int(K), R=float(R),
-                     precision=int(precision), seed=int(seed))
+                     precision=int(precision), seed=int(seed), near_mode=int(near_mode),
+                     dipole_mode=int(dipole_mode), dr=float(dr), far_mode=int(far_mode))
         h = ctypes.c_void_p()
         _check(lib.hsma_plan_create_ex(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

@@ -87,6 +87,13 @@ CONFIGS = {
                         desc="grounded cube, 10k uniform +-1 charges, p=16, K=2000, M=2500, FP64"),
     "periodic1m": dict(L=1.0, bc=0, p=20, M=4000, K=4000, R=2.7, n=1_000_000, seed=3,
                        desc="periodic cube, 1e6 uniform +-1 charges, p=20, K=4000, M=4000, FP32-comp"),
+    # The paper's timing system (Sec. III): unit charges of random sign on a
+    # uniform lattice, periodic, alpha = 1.3 (R_s = 1.3 sqrt(3)/2 L), P = 25,
+    # N_m = 2 P^2 monitoring points, N_o = 5928 surface images over three
+    # spheres = 2 x 988 points per sphere.  46^3 = 97,336 sites.
+    "paper100k": dict(L=1.0, bc=0, p=25, M=1976, K=1250, R=1.3 * math.sqrt(3.0) / 2.0, n=46 ** 3,
+                      seed=7, desc="paper timing system: 46^3 random-sign lattice, periodic, alpha=1.3, "
+                                   "P=25, N_m=2P^2=1250, N_o=5928 (1976 per sphere)"),
     "slab200k": dict(L=1.0, bc=2, p=16, M=2500, K=3000, R=2.7, n=200_000, seed=5,
                      desc="grounded slab 1x1x0.5, 2e5 charges {+2,+1,-1}, p=16, K=3000, M=2500, FP32"),
 }
@@ -103,4 +110,7 @@ def make_inputs(name, n=None, seed=None):
         return x, q
     if name == "slab200k":
         return slab_charges(n, c["L"], seed)
+    if name == "paper100k":
+        side = round(n ** (1.0 / 3.0))
+        return random_sign_lattice(side, c["L"], seed)
     return uniform_neutral(n, c["L"], seed)
