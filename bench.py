@@ -41,6 +41,8 @@ def parse():
                     help="near set: 27-image block or every image inside the auxiliary sphere")
     ap.add_argument("--dipole", default="exact", choices=["exact", "layers"],
                     help="surface dipoles exact, or the paper's two charge layers (dr = 1e-5 R_s)")
+    ap.add_argument("--far", default="surface", choices=["surface", "direct"],
+                    help="far field through the surface mapping, or the series evaluated directly")
     ap.add_argument("--paper-time", action="store_true",
                     help="report seconds per update step against the paper's GPU timing")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -262,7 +264,8 @@ def main():
     near_mode = hsma.NEAR_SPHERE if args.near == "sphere" else hsma.NEAR_BLOCK
     plan = hsma.Plan(cfg["L"], cfg["bc"], cfg["p"], cfg["M"], cfg["K"], cfg["R"], precision=prec,
                      near_mode=near_mode,
-                     dipole_mode=hsma.DIPOLE_LAYERS if args.dipole == "layers" else hsma.DIPOLE_EXACT)
+                     dipole_mode=hsma.DIPOLE_LAYERS if args.dipole == "layers" else hsma.DIPOLE_EXACT,
+                     far_mode=hsma.FAR_DIRECT if args.far == "direct" else hsma.FAR_SURFACE)
     info = plan.info
     xd = torch.tensor(x, dtype=torch.float64, device=dev)
     qd = torch.tensor(q, dtype=torch.float64, device=dev)
@@ -295,6 +298,8 @@ def main():
         near_pairs = n * 27.0 * ns - n
         rhs_pairs = info["n_check"] * 27.0 * ns
     surf_pairs = float(n) * info["M_eff"] * (3 if args.dipole == "layers" else 1)
+    if args.far == "direct":
+        surf_pairs = 0.0   # no surface images: the series is evaluated per particle
     pairs_step = near_pairs + rhs_pairs + surf_pairs
     ms_step = 1e3 * dt / args.steps
     near_ms, near_launches = kt["near"]
@@ -318,6 +323,7 @@ def main():
             "workload": args.workload,
             "near_set": args.near,
             "surface_dipole": args.dipole,
+            "far_field": args.far,
             "desc": cfg["desc"],
             "N": n, "bc": cfg["bc"], "p": cfg["p"], "K": cfg["K"], "M_eff": info["M_eff"],
             "R": cfg["R"], "precision": "fp32 pair sums + two-sum accumulation" if prec else "fp64",

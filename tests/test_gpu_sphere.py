@@ -112,6 +112,7 @@ def test_direct_far_field_vs_oracle(hs, bc, p, precision):
     else:
         scale = 0.5 * np.sum(np.abs(q * ref["phi"]))
         assert abs(e - ref["energy"]) <= 1e-6 * scale
-    # and it agrees with the surface mapping to the quadrature error
+    # and it agrees with the surface mapping to the quadrature error (in FP32
+    # mode the coefficients carry the single-precision right-hand side)
     sref = oracle.solve(oracle.make_plan(1.0, bc, p, 2500, K, 2.7), x, q)
-    assert rel_max(po, sref["phi_out"], rms(sref["phi"])) <= 1e-8
+    assert rel_max(po, sref["phi_out"], rms(sref["phi"])) <= (1e-8 if precision == 0 else 1e-5)

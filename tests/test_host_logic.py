@@ -17,3 +17,44 @@ def test_serving_arena_allocator(tmp_path):
     for seed in (1, 2, 3):
         out = subprocess.run([str(exe), str(seed)], capture_output=True, text=True, timeout=120)
         assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
+
+
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_bench_sphere_image_count(bc):
+    """bench.py counts the sphere near set (for its pair totals) exactly as the
+    oracle builds it."""
+    import math
+
+    import numpy as np
+
+    import bench
+    import oracle
+    from oracle import hsma as oh
+    from paper_1806_04801_amd import workloads as W
+    x, q = W.slab_charges(50, 1.0, 2) if bc == 2 else W.uniform_neutral(50, 1.0, 2)
+    R = 1.7 * math.sqrt(3) / 2
+    cfg = dict(L=1.0, R=R, bc=bc)
+    c = oh.normalize(x, 1.0, bc)
+    if bc == 2:
+        c, q = oh.double_slab(c, q)
+    img, _, _ = oracle.sphere_images(oracle.BC_METALLIC if bc == 1 else oracle.BC_PERIODIC, 1.0,
+                                     np.concatenate([c, q[:, None]], axis=1), R)
+    assert bench.sphere_image_count(x, cfg) == len(img)
+
+
+def test_bench_traffic_needs_matching_kernel_source(tmp_path, monkeypatch):
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "near_f32_w_pmc.md").write_text(
+        "- hbm_bytes_per_launch: 123.5\n- kernel_source_sha256_16: %s   (x)\n" % bench.kernel_source_hash())
+    (prof / "near_f32_v_pmc.md").write_text(
+        "- hbm_bytes_per_launch: 123.5\n- kernel_source_sha256_16: 0000000000000000\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "paper_1806_04801_amd" / "csrc").mkdir(parents=True)
+    import shutil
+    shutil.copy(os.path.join(os.path.dirname(HERE), "paper_1806_04801_amd", "csrc", "pairs.hip"),
+                tmp_path / "paper_1806_04801_amd" / "csrc" / "pairs.hip")
+    assert bench.profiled_traffic("w", "f32") == 123.5
+    assert bench.profiled_traffic("v", "f32") is None
+    assert bench.profiled_traffic("missing", "f32") is None
