@@ -24,6 +24,12 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector peak
 NEAR_FLOPS_PER_PAIR = 20     # potential + field, rsqrt counted as one flop
+# Pair-once near kernel: one evaluation (20 flops) serves both directions and
+# adds 8 (4 products and 4 sums for the reverse terms), 28 per unordered pair,
+# i.e. 14 per ordered pair.  Its diagonal blocks are evaluated per ordered pair
+# (20 flops each) and are under 1% of the pairs; they are counted at 14 too,
+# which understates the work.
+NEAR_FLOPS_PER_PAIR_ONCE = 14
 
 
 def parse():
@@ -78,16 +84,28 @@ def sphere_image_count(x, cfg):
     return n_img
 
 
-def kernel_source_hash():
+NEAR_SOURCES = {"tiles": ("pairs.hip", "pair_math.h"), "pair-once": ("sym.hip", "pair_math.h")}
+
+
+def kernel_source_hash(kind="tiles"):
+    """Hash of the sources that define the near kernel of that kind."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1806_04801_amd", "csrc", "pairs.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in NEAR_SOURCES[kind]:
+        h.update(open(os.path.join(ROOT, "paper_1806_04801_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload, precision_tag):
-    """HBM bytes per launch of the near kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "near_%s_%s_pmc.md" % (precision_tag, workload))
+def profile_name(workload, precision_tag, kind="tiles"):
+    stem = "near_pair_once" if kind == "pair-once" else "near"
+    return "%s_%s_%s" % (stem, precision_tag, workload)
+
+
+def profiled_traffic(workload, precision_tag, kind="tiles"):
+    """HBM bytes of one near-field sum (all launches of its kernel) from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source."""
+    path = os.path.join(ROOT, "profiles", profile_name(workload, precision_tag, kind) + "_pmc.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -95,7 +113,7 @@ def profiled_traffic(workload, precision_tag):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().split()[0]
-    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash(kind):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -304,7 +322,9 @@ def main():
     ms_step = 1e3 * dt / args.steps
     near_ms, near_launches = kt["near"]
     near_avg_s = near_ms / max(near_launches, 1) / 1e3
-    achieved = NEAR_FLOPS_PER_PAIR * near_pairs / near_avg_s / 1e12
+    sched = plan.near_schedule(n)
+    flops_pair = NEAR_FLOPS_PER_PAIR_ONCE if sched["kind"] == 1 else NEAR_FLOPS_PER_PAIR
+    achieved = flops_pair * near_pairs / near_avg_s / 1e12
     peak = FP32_PEAK_TFLOPS if prec == hsma.FP32_COMP else FP64_PEAK_TFLOPS
     rec = {
         "metric": "pair interactions/s",
@@ -329,6 +349,9 @@ def main():
             "R": cfg["R"], "precision": "fp32 pair sums + two-sum accumulation" if prec else "fp64",
             "pairs_per_step": {"near": near_pairs, "rhs": rhs_pairs, "surface": surf_pairs},
             "near_pairs_per_s": near_pairs / near_avg_s,
+            "near_kernel": ("pair-once" if sched["kind"] == 1 else "tiles"),
+            "near_schedule": sched,
+            "near_flops_per_pair": flops_pair,
             "kernel_ms_avg": {k: (v[0] / max(v[1], 1)) for k, v in kt.items()},
             "energy": energies[-1],
         },
@@ -338,7 +361,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": profiled_traffic(args.workload, "f32" if prec == hsma.FP32_COMP else "f64"),
+            "traffic": profiled_traffic(args.workload, "f32" if prec == hsma.FP32_COMP else "f64",
+                                        "pair-once" if sched["kind"] == 1 else "tiles"),
         },
     }
     if not args.no_cpu_baseline:

@@ -167,6 +167,37 @@ hsma_status hsma_plan_points(hsma_plan plan, int which, double* xyz, double* w);
 size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
 
 /*
+ * The near-field kernel that an update step with N particles runs, and its
+ * schedule (the near sum of Sec. II.C over the 3x3x3 image block).
+ *   kind 0: per-target tiles; each lane sums every source image for its own
+ *           targets, so each ordered (target, image) pair is evaluated once.
+ *   kind 1: each unordered particle pair is evaluated once and both of its
+ *           directions are accumulated (the image-block sum is symmetric in
+ *           the two particles).  Single precision, periodic or grounded box,
+ *           block near set, N at or above a threshold (262144, or the
+ *           HSMA_SYM_MIN environment variable); HSMA_SYM=0 in the environment
+ *           turns it off and HSMA_SYM=1 forces it.  The particles are cut
+ *           into `blocks` blocks of `block`; block pairs run in blocks - 1
+ *           (+1 if odd) round-robin rounds after one diagonal launch; a block
+ *           pair is split into `slices` row slices of 64 * rows_per_lane rows
+ *           and `parts` column parts, one wave each; `launches` counts every
+ *           kernel launch of the sum.
+ * Fields other than kind are 0 for kind 0.  Returns HSMA_E_INVALID for a NULL
+ * plan or output, or N < 1.
+ */
+typedef struct {
+    int kind;
+    int rows_per_lane;
+    int block;
+    int slices;
+    int parts;
+    int blocks;
+    int launches;
+} hsma_near_schedule_t;
+
+hsma_status hsma_near_schedule(hsma_plan plan, int64_t N, hsma_near_schedule_t* out);
+
+/*
  * Update step (Sec. II.C) on host arrays: x (N x 3), q (N); outputs energy
  * (one double), phi (N or NULL) and forces (N x 3 or NULL).  Allocates its
  * own device buffers and synchronizes before returning.

@@ -141,7 +141,8 @@ hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStrea
         CK(launch_pair_f64(pl->img, true, false, src64, lam64, ly.g_G, pl->L, G_part, s));
     }
     hipLaunchKernelGGL(k_grad_finalize, dim3((ly.N + WG - 1) / WG), dim3(WG), 0, s,
-                       (const double*)(ws + ly.off_near_part), ly.g_near.S, ly.g_near.nt_pad,
+                       (const double*)(ws + ly.off_near_part), ly.sym ? ly.g_sym.C + ly.g_sym.s : ly.g_near.S,
+                       ly.sym ? ly.g_sym.n_pad : ly.g_near.nt_pad,
                        (const double*)(ws + ly.off_surf_part), ly.g_surf.S, ly.g_surf.nt_pad,
                        G_part, ly.g_G.S, ly.g_G.nt_pad, src64, ly.N,
                        pl->bc == HSMA_BC_SLAB_METALLIC_Z ? 1 : 0, dEdx, dEdq);

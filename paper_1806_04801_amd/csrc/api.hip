@@ -220,6 +220,23 @@ size_t hsma_workspace_bytes(hsma_plan pl, int64_t N) {
     return make_layout(pl, N, true).total;
 }
 
+hsma_status hsma_near_schedule(hsma_plan pl, int64_t N, hsma_near_schedule_t* out) {
+    if (pl == nullptr || out == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
+    if (N < 1 || N > (int64_t)1 << 28) return fail(HSMA_E_INVALID, "N out of range");
+    const Layout ly = make_layout(pl, N, false);
+    *out = hsma_near_schedule_t{};
+    if (ly.sym) {
+        out->kind = 1;
+        out->rows_per_lane = ly.g_sym.T;
+        out->block = ly.g_sym.B;
+        out->slices = ly.g_sym.s;
+        out->parts = ly.g_sym.C;
+        out->blocks = ly.g_sym.nb;
+        out->launches = ly.g_sym.P;   // the diagonal launch and P - 1 rounds
+    }
+    return HSMA_OK;
+}
+
 static hsma_status check_sizes(hsma_plan pl, int64_t N) {
     if (pl == nullptr) return fail(HSMA_E_INVALID, "NULL plan");
     if (N < 1 || N > (int64_t)1 << 28) return fail(HSMA_E_INVALID, "N out of range");

@@ -54,12 +54,32 @@ struct PairGeom {
 };
 PairGeom pair_geometry(int nt, int ns, int tpl, int ncu);
 
-// One tile of a grouped pair launch.
+// Geometry of the near sum that visits every unordered particle pair once:
+// blocks of B = 64 * T * s particles, nb blocks (P = nb rounded up to even),
+// accumulators padded to n_pad = nb * B per component.
+struct SymGeom {
+    int n = 0;       // particles
+    int T = 1;       // rows per lane
+    int s = 1;       // row slices per block
+    int C = 1;       // column parts per block (one wave per slice and part)
+    int B = 64;      // block size
+    int nb = 0;      // blocks
+    int P = 0;       // nb rounded up to even: P - 1 rounds
+    int n_pad = 0;   // nb * B
+};
+SymGeom sym_geometry(int n, int T, int ncu);
+
+// One group of tiles of a grouped pair launch: all tiles of one pair stage of
+// one request.  Tile i of the group (0 <= i < ntb * S) is target block
+// i % ntb against source chunk i / ntb; work-group g of the launch runs tile
+// g - first of the group whose range [first, first + ntb * S) holds g.
 enum { TILE_NEAR = 0, TILE_RHS = 1, TILE_SURFACE = 2 };
-struct TileItem {
+struct TileGroup {
     int kind, img;        // TILE_*, IMG_* (near and right-hand side)
-    int tb, c;            // target block, source chunk
+    int first;            // index of the group's first tile in the launch
+    int ntb, S;           // target blocks, source chunks
     int nt, ns, chunk, nt_pad;
+    int pad;
     const void* tgt;      // Rec32 / double4 targets
     const void* src;      // Rec32 / double4 sources, or surface records (8 doubles)
     double* out;          // partial buffer of the request's stage
@@ -113,7 +133,13 @@ hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, con
 // Surface images (X, Y, Z, Q, px, py, pz, 0) at targets (x, y, z, q).
 hipError_t launch_surface_f64(const double4* tgt, const double* surf, const PairGeom& g,
                               double* out, hipStream_t s);
-hipError_t launch_group_tiles(bool f32, const TileItem* items, int n, hipStream_t s);
+hipError_t launch_group_tiles(bool f32, const TileGroup* groups, int ngroups, int ntiles,
+                              hipStream_t s);
+// Near sum at the particles, each unordered pair once (single precision,
+// periodic or grounded images).  acc: (g.C + g.s) copies of 4 x g.n_pad doubles,
+// written completely for the first g.n entries of each component.
+hipError_t launch_sym_f32(int img, const Rec32* pts, const SymGeom& g, double L, double* acc,
+                          hipStream_t s);
 // Pair sums over an explicit list of charges (double4 or Rec32 records).
 hipError_t launch_explicit(bool f32, bool field, bool self, const void* tgt, const void* src,
                            const PairGeom& g, double L, double* out, hipStream_t s);

@@ -18,112 +18,12 @@
 // a partial buffer that a second kernel sums in a fixed order, so results do
 // not depend on scheduling.
 #include "hsma_internal.h"
+#include "pair_math.h"
 #include "stages.h"
 
 namespace hsma {
 
 constexpr int WG = 256;
-
-// 1/sqrt(x) in double: hardware estimate (about 2^-24 relative) refined by one
-// third-order Newton step, y <- y + y e (1/2 + 3/8 e), e = 1 - x y^2.
-__device__ __forceinline__ double rsqrt_f64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double t = x * y;
-    double e = __builtin_fma(-t, y, 1.0);
-    double c = __builtin_fma(e, 0.375, 0.5);
-    return __builtin_fma(y * e, c, y);
-}
-
-// Per-axis target-minus-image differences for k = -1, 0, +1 (index k + 1).
-template <int IMG>
-__device__ __forceinline__ void diffs_f64(double t, double s, double L, double (&d)[3]) {
-    double d0 = t - s;
-    d[1] = d0;
-    if (IMG == IMG_PERIODIC) {          // image s + kL
-        d[0] = d0 + L;
-        d[2] = d0 - L;
-    } else if (IMG == IMG_METALLIC) {   // image -s + kL
-        double sm = t + s;
-        d[0] = sm + L;
-        d[2] = sm - L;
-    } else {
-        d[0] = d[2] = 0.0;
-    }
-}
-
-// Sum over the images of one source: pot = sum s_k / |d|, f = sum s_k d / |d|^3.
-// The field goes through the marginals of w = s/|d|^3 over the image cube:
-// f_x = sum_a dx_a X_a with X_a = sum_bc w_abc, and likewise for y and z.
-template <int IMG, bool FIELD, bool SELF>
-__device__ __forceinline__ void images_f64(const double (&dx)[3], const double (&dy)[3],
-                                           const double (&dz)[3], double& pot, double& fx,
-                                           double& fy, double& fz) {
-    constexpr int lo = (IMG == IMG_FREE) ? 1 : 0;
-    constexpr int hi = (IMG == IMG_FREE) ? 2 : 3;
-    double sx[3], sy[3], sz[3];
-#pragma unroll
-    for (int a = lo; a < hi; ++a) {
-        sx[a] = dx[a] * dx[a];
-        sy[a] = dy[a] * dy[a];
-        sz[a] = dz[a] * dz[a];
-    }
-    double S[3][3], Tz[3][3];
-    pot = 0.0;
-#pragma unroll
-    for (int a = lo; a < hi; ++a) {
-#pragma unroll
-        for (int b = lo; b < hi; ++b) {
-            const double sxy = sx[a] + sy[b];
-#pragma unroll
-            for (int c = lo; c < hi; ++c) {
-                const double r2 = sxy + sz[c];
-                double y = rsqrt_f64(r2);
-                if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > 0.0) ? y : 0.0;
-                const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
-                if (a == lo && b == lo && c == lo) pot = neg ? -y : y;
-                else pot = neg ? pot - y : pot + y;
-                if (FIELD) {
-                    double w = y * y * y;
-                    w = neg ? -w : w;
-                    S[a][b] = (c == lo) ? w : S[a][b] + w;
-                    Tz[a][c] = (b == lo) ? w : Tz[a][c] + w;
-                }
-            }
-        }
-    }
-    if (FIELD) {
-        double X[3], Y[3], Z[3];
-#pragma unroll
-        for (int a = lo; a < hi; ++a) {
-            double x = S[a][lo], z = Tz[lo][a];
-#pragma unroll
-            for (int b = lo + 1; b < hi; ++b) {
-                x += S[a][b];
-                z += Tz[b][a];
-            }
-            X[a] = x;
-            Z[a] = z;
-        }
-#pragma unroll
-        for (int b = lo; b < hi; ++b) {
-            double yv = S[lo][b];
-#pragma unroll
-            for (int a = lo + 1; a < hi; ++a) yv += S[a][b];
-            Y[b] = yv;
-        }
-        fx = dx[lo] * X[lo];
-        fy = dy[lo] * Y[lo];
-        fz = dz[lo] * Z[lo];
-#pragma unroll
-        for (int a = lo + 1; a < hi; ++a) {
-            fx = __builtin_fma(dx[a], X[a], fx);
-            fy = __builtin_fma(dy[a], Y[a], fy);
-            fz = __builtin_fma(dz[a], Z[a], fz);
-        }
-    } else {
-        fx = fy = fz = 0.0;
-    }
-}
 
 // One tile: target block tb (256*T targets) against source chunk c.
 template <int IMG, bool FIELD, bool SELF, int T>
@@ -149,7 +49,7 @@ __device__ __forceinline__ void tile_pair_f64(int tb, int c, const double4* __re
             diffs_f64<IMG>(ty[u], s.y, L, dy);
             diffs_f64<IMG>(tz[u], s.z, L, dz);
             double pot, fx, fy, fz;
-            images_f64<IMG, FIELD, SELF>(dx, dy, dz, pot, fx, fy, fz);
+            images_sum<double, IMG, FIELD, SELF>(dx, dy, dz, pot, fx, fy, fz);
             ap[u] = __builtin_fma(s.w, pot, ap[u]);
             if (FIELD) {
                 ax[u] = __builtin_fma(s.w, fx, ax[u]);
@@ -180,122 +80,6 @@ k_pair_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ 
 }
 
 // ---------------------------------------------------------------- single precision
-// Error-free sum (Knuth's TwoSum): s + e == a + b exactly.
-__device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float b) {
-    const float s = hi + b;
-    const float bb = s - hi;
-    const float e = (hi - (s - bb)) + (b - bb);
-    hi = s;
-    lo += e;
-}
-
-struct Pt32 {
-    float h0[3], hp[3], hm[3], l[3];
-};
-
-__device__ __forceinline__ Pt32 load_pt32(const Rec32& r) {
-    Pt32 p;
-    p.h0[0] = r.v[0].x; p.h0[1] = r.v[0].y; p.h0[2] = r.v[0].z;
-    p.hp[0] = r.v[1].x; p.hp[1] = r.v[1].y; p.hp[2] = r.v[1].z;
-    p.hm[0] = r.v[2].x; p.hm[1] = r.v[2].y; p.hm[2] = r.v[2].z;
-    p.l[0] = r.v[1].w; p.l[1] = r.v[2].w; p.l[2] = r.v[3].x;
-    return p;
-}
-
-// Differences along axis a for k = -1, 0, +1 (box side 1), leading parts exact
-// for small results:
-//   periodic c_t - c_s - k:  k=+1: (hp_t - hm_s) + (l_t - l_s),  k=-1: (hm_t - hp_s) + (l_t - l_s)
-//   metallic c_t + c_s - k:  k=+1: (hp_t + hp_s) + (l_t + l_s),  k=-1: (hm_t + hm_s) + (l_t + l_s)
-template <int IMG>
-__device__ __forceinline__ void diffs_f32(const Pt32& t, const Pt32& s, int a, float (&d)[3]) {
-    const float dl = t.l[a] - s.l[a];
-    d[1] = (t.h0[a] - s.h0[a]) + dl;
-    if (IMG == IMG_PERIODIC) {
-        d[2] = (t.hp[a] - s.hm[a]) + dl;
-        d[0] = (t.hm[a] - s.hp[a]) + dl;
-    } else if (IMG == IMG_METALLIC) {
-        const float sl = t.l[a] + s.l[a];
-        d[2] = (t.hp[a] + s.hp[a]) + sl;
-        d[0] = (t.hm[a] + s.hm[a]) + sl;
-    } else {
-        d[0] = d[2] = 0.0f;
-    }
-}
-
-// Sum over the 27 images of one source.  The field sum_abc w_abc (dx_a, dy_b,
-// dz_c) with w = s / r^3 is taken through the marginals of w over the image
-// cube: E_x = sum_a dx_a X_a with X_a = sum_bc w_abc, and likewise for y, z.
-template <int IMG, bool FIELD, bool SELF>
-__device__ __forceinline__ void images_f32(const float (&dx)[3], const float (&dy)[3],
-                                           const float (&dz)[3], float& pot, float& fx,
-                                           float& fy, float& fz) {
-    constexpr int lo = (IMG == IMG_FREE) ? 1 : 0;
-    constexpr int hi = (IMG == IMG_FREE) ? 2 : 3;
-    float sx[3], sy[3], sz[3];
-#pragma unroll
-    for (int a = lo; a < hi; ++a) {
-        sx[a] = dx[a] * dx[a];
-        sy[a] = dy[a] * dy[a];
-        sz[a] = dz[a] * dz[a];
-    }
-    float S[3][3], Tz[3][3];   // S[a][b] = sum_c w, Tz[a][c] = sum_b w
-    pot = 0.0f;
-#pragma unroll
-    for (int a = lo; a < hi; ++a) {
-#pragma unroll
-        for (int b = lo; b < hi; ++b) {
-            const float sxy = sx[a] + sy[b];
-#pragma unroll
-            for (int c = lo; c < hi; ++c) {
-                const float r2 = sxy + sz[c];
-                float y = __builtin_amdgcn_rsqf(r2);
-                if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > 0.0f) ? y : 0.0f;
-                const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
-                if (a == lo && b == lo && c == lo) pot = neg ? -y : y;
-                else pot = neg ? pot - y : pot + y;
-                if (FIELD) {
-                    float w = y * y * y;
-                    w = neg ? -w : w;
-                    S[a][b] = (c == lo) ? w : S[a][b] + w;
-                    Tz[a][c] = (b == lo) ? w : Tz[a][c] + w;
-                }
-            }
-        }
-    }
-    if (FIELD) {
-        float X[3], Y[3], Z[3];
-#pragma unroll
-        for (int a = lo; a < hi; ++a) {
-            float x = S[a][lo], z = Tz[lo][a];
-#pragma unroll
-            for (int b = lo + 1; b < hi; ++b) {
-                x += S[a][b];
-                z += Tz[b][a];
-            }
-            X[a] = x;
-            Z[a] = z;
-        }
-#pragma unroll
-        for (int b = lo; b < hi; ++b) {
-            float yv = S[lo][b];
-#pragma unroll
-            for (int a = lo + 1; a < hi; ++a) yv += S[a][b];
-            Y[b] = yv;
-        }
-        fx = dx[lo] * X[lo];
-        fy = dy[lo] * Y[lo];
-        fz = dz[lo] * Z[lo];
-#pragma unroll
-        for (int a = lo + 1; a < hi; ++a) {
-            fx = __builtin_fmaf(dx[a], X[a], fx);
-            fy = __builtin_fmaf(dy[a], Y[a], fy);
-            fz = __builtin_fmaf(dz[a], Z[a], fz);
-        }
-    } else {
-        fx = fy = fz = 0.0f;
-    }
-}
-
 // One tile in single precision.  Each lane sums the (plain float)
 // contributions of up to 8 sources into partials and folds them into (hi, lo)
 // accumulators with one two-sum per component.  Outputs are scaled back to
@@ -332,7 +116,7 @@ __device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __rest
                 diffs_f32<IMG>(tp[u], s0, 0, dx);
                 diffs_f32<IMG>(tp[u], s0, 1, dy);
                 diffs_f32<IMG>(tp[u], s0, 2, dz);
-                images_f32<IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
+                images_sum<float, IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
                 sp[u] = __builtin_fmaf(q0, p0, sp[u]);
                 if (FIELD) {
                     sx[u] = __builtin_fmaf(q0, fx0, sx[u]);
@@ -394,7 +178,7 @@ __device__ __forceinline__ void tile_free_f64(int tb, int c, const double4* __re
         tx[u] = r.x; ty[u] = r.y; tz[u] = r.z;
         ap[u] = ax[u] = ay[u] = az[u] = 0.0;
     }
-    for (int j = j0; j < j1; ++j) {
+    auto pair = [&](int j) {
         const double4 s = src[j];
 #pragma unroll
         for (int u = 0; u < T; ++u) {
@@ -405,13 +189,20 @@ __device__ __forceinline__ void tile_free_f64(int tb, int c, const double4* __re
             const double qy = s.w * y;
             ap[u] += qy;
             if (FIELD) {
-                const double w = qy * y * y;
+                const double w = qy * (y * y);
                 ax[u] = __builtin_fma(w, dx, ax[u]);
                 ay[u] = __builtin_fma(w, dy, ay[u]);
                 az[u] = __builtin_fma(w, dz, az[u]);
             }
         }
+    };
+    // groups of four charges are unrolled so that their scalar loads issue together
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pair(j + k);
     }
+    for (; j < j1; ++j) pair(j);
     constexpr int ncomp = FIELD ? 4 : 1;
 #pragma unroll
     for (int u = 0; u < T; ++u) {
@@ -447,7 +238,7 @@ __device__ __forceinline__ void tile_free_f32(int tb, int c, const Rec32* __rest
         float sp[T], sx[T], sy[T], sz[T];
 #pragma unroll
         for (int u = 0; u < T; ++u) sp[u] = sx[u] = sy[u] = sz[u] = 0.0f;
-        for (int j = g0; j < g1; ++j) {
+        auto pair = [&](int j) {
             const Pt32 s = load_pt32(src[j]);
             const float q = src[j].v[0].w;
 #pragma unroll
@@ -461,12 +252,19 @@ __device__ __forceinline__ void tile_free_f32(int tb, int c, const Rec32* __rest
                 const float qy = q * y;
                 sp[u] += qy;
                 if (FIELD) {
-                    const float w = qy * y * y;
+                    const float w = qy * (y * y);
                     sx[u] = __builtin_fmaf(w, dx, sx[u]);
                     sy[u] = __builtin_fmaf(w, dy, sy[u]);
                     sz[u] = __builtin_fmaf(w, dz, sz[u]);
                 }
             }
+        };
+        // a full group is unrolled so that its scalar loads issue together
+        if (g1 - g0 == G) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) pair(g0 + k);
+        } else {
+            for (int j = g0; j < g1; ++j) pair(j);
         }
 #pragma unroll
         for (int u = 0; u < T; ++u) {
@@ -611,46 +409,60 @@ __global__ void k_make_rec32(const double4* __restrict__ p, int n, double L, Rec
 }
 
 // ---------------------------------------------------------------- grouped tiles
-// One launch over a table of tiles from many requests (continuous batching):
-// work-group g runs tile items[g], whose kind, image mode and operands are
-// wave-uniform, so each work-group takes one branch.  Tiles of one request are
-// computed exactly as in the single-request launch with one target per lane.
+// One launch over the tiles of many requests (continuous batching).  Work-group
+// g finds its group by a binary search over the groups' first-tile indices
+// (wave-uniform, so it runs on scalar loads), then runs the same tile function
+// as the single-request kernels with one target per lane.  Kind, image mode and
+// operands are uniform over the work-group, so each takes one branch.
 template <bool F32>
-__global__ void __launch_bounds__(WG) k_group_tiles(const TileItem* __restrict__ items) {
-    const TileItem it = items[blockIdx.x];
+__global__ void __launch_bounds__(WG) k_group_tiles(const TileGroup* __restrict__ groups,
+                                                   int ngroups) {
+    const int g = blockIdx.x;
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (groups[mid].first <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const TileGroup it = groups[lo];
+    const int i = g - it.first;
+    const int c = i / it.ntb;
+    const int tb = i - c * it.ntb;
     if (it.kind == TILE_SURFACE) {
-        tile_surface_f64<1>(it.tb, it.c, (const double4*)it.tgt, it.nt, (const double*)it.src,
-                            it.ns, it.chunk, it.out, it.nt_pad);
+        tile_surface_f64<1>(tb, c, (const double4*)it.tgt, it.nt, (const double*)it.src, it.ns,
+                            it.chunk, it.out, it.nt_pad);
         return;
     }
     const bool near = it.kind == TILE_NEAR;
     if (F32) {
         const Rec32* t = (const Rec32*)it.tgt;
         const Rec32* s = (const Rec32*)it.src;
+        const double iL = 1.0 / it.L;
         if (it.img == IMG_PERIODIC) {
-            if (near) tile_pair_f32<IMG_PERIODIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
-            else tile_pair_f32<IMG_PERIODIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
+            if (near) tile_pair_f32<IMG_PERIODIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
+            else tile_pair_f32<IMG_PERIODIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
         } else {
-            if (near) tile_pair_f32<IMG_METALLIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
-            else tile_pair_f32<IMG_METALLIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, 1.0 / it.L);
+            if (near) tile_pair_f32<IMG_METALLIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
+            else tile_pair_f32<IMG_METALLIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
         }
     } else {
         const double4* t = (const double4*)it.tgt;
         const double4* s = (const double4*)it.src;
         if (it.img == IMG_PERIODIC) {
-            if (near) tile_pair_f64<IMG_PERIODIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
-            else tile_pair_f64<IMG_PERIODIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+            if (near) tile_pair_f64<IMG_PERIODIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+            else tile_pair_f64<IMG_PERIODIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
         } else {
-            if (near) tile_pair_f64<IMG_METALLIC, true, true, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
-            else tile_pair_f64<IMG_METALLIC, false, false, 1>(it.tb, it.c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+            if (near) tile_pair_f64<IMG_METALLIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
+            else tile_pair_f64<IMG_METALLIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
         }
     }
 }
 
-hipError_t launch_group_tiles(bool f32, const TileItem* items, int n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    if (f32) hipLaunchKernelGGL(k_group_tiles<true>, dim3(n), dim3(WG), 0, s, items);
-    else hipLaunchKernelGGL(k_group_tiles<false>, dim3(n), dim3(WG), 0, s, items);
+hipError_t launch_group_tiles(bool f32, const TileGroup* groups, int ngroups, int ntiles,
+                              hipStream_t s) {
+    if (ntiles <= 0 || ngroups <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_group_tiles<true>, dim3(ntiles), dim3(WG), 0, s, groups, ngroups);
+    else hipLaunchKernelGGL(k_group_tiles<false>, dim3(ntiles), dim3(WG), 0, s, groups, ngroups);
     return hipGetLastError();
 }
 

@@ -264,39 +264,40 @@ static bool admit(hsma_server_s* sv, SrvReq* r) {
     return true;
 }
 
-// Tiles of one pair stage of one request (right-hand side, near, or surface).
-static void add_tiles(std::vector<TileItem>& v, int kind, int img, const PairGeom& g,
+// The tiles of one pair stage of one request, as one group of the launch.
+static void add_group(std::vector<TileGroup>& v, int* ntiles, int kind, int img, const PairGeom& g,
                       const void* tgt, const void* src, double* out, double L) {
-    for (int c = 0; c < g.S; ++c)
-        for (int tb = 0; tb < g.ntb; ++tb) {
-            TileItem it;
-            it.kind = kind;
-            it.img = img;
-            it.tb = tb;
-            it.c = c;
-            it.nt = g.nt;
-            it.ns = g.ns;
-            it.chunk = g.chunk;
-            it.nt_pad = g.nt_pad;
-            it.tgt = tgt;
-            it.src = src;
-            it.out = out;
-            it.L = L;
-            v.push_back(it);
-        }
+    if (g.nt <= 0 || g.ntb <= 0 || g.S <= 0) return;
+    TileGroup it;
+    it.kind = kind;
+    it.img = img;
+    it.first = *ntiles;
+    it.ntb = g.ntb;
+    it.S = g.S;
+    it.nt = g.nt;
+    it.ns = g.ns;
+    it.chunk = g.chunk;
+    it.nt_pad = g.nt_pad;
+    it.pad = 0;
+    it.tgt = tgt;
+    it.src = src;
+    it.out = out;
+    it.L = L;
+    v.push_back(it);
+    *ntiles += g.ntb * g.S;
 }
 
 // Copy the tick's tables to the device through a pinned ring slot.
 static hsma_status upload(hsma_server_s* sv, const std::vector<ReqDesc>& da,
-                          const std::vector<ReqDesc>& db, const std::vector<TileItem>& tiles,
-                          ReqDesc** dA, ReqDesc** dB, TileItem** dT) {
+                          const std::vector<ReqDesc>& db, const std::vector<TileGroup>& tiles,
+                          ReqDesc** dA, ReqDesc** dB, TileGroup** dT) {
     const int slot = sv->ring;
     sv->ring = (sv->ring + 1) % hsma_server_s::RING;
     if (sv->tabused[slot]) HSMA_HIP(hipEventSynchronize(sv->tabev[slot]));
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) & ~(a - 1); };
     const size_t na = up(sizeof(ReqDesc) * da.size()), nb = up(sizeof(ReqDesc) * db.size()),
-                 nt = up(sizeof(TileItem) * tiles.size());
+                 nt = up(sizeof(TileGroup) * tiles.size());
     const size_t need = na + nb + nt + 256;
     if (need > sv->tabcap[slot]) {
         HSMA_HIP(hipStreamSynchronize(sv->stream));
@@ -315,13 +316,13 @@ static hsma_status upload(hsma_server_s* sv, const std::vector<ReqDesc>& da,
     char* h = sv->htab[slot];
     if (!da.empty()) std::memcpy(h, da.data(), sizeof(ReqDesc) * da.size());
     if (!db.empty()) std::memcpy(h + na, db.data(), sizeof(ReqDesc) * db.size());
-    if (!tiles.empty()) std::memcpy(h + na + nb, tiles.data(), sizeof(TileItem) * tiles.size());
+    if (!tiles.empty()) std::memcpy(h + na + nb, tiles.data(), sizeof(TileGroup) * tiles.size());
     HSMA_HIP(hipMemcpyAsync(sv->dtab[slot], h, na + nb + nt, hipMemcpyHostToDevice, sv->stream));
     HSMA_HIP(hipEventRecord(sv->tabev[slot], sv->stream));
     sv->tabused[slot] = true;
     *dA = (ReqDesc*)sv->dtab[slot];
     *dB = (ReqDesc*)(sv->dtab[slot] + na);
-    *dT = (TileItem*)(sv->dtab[slot] + na + nb);
+    *dT = (TileGroup*)(sv->dtab[slot] + na + nb);
     return HSMA_OK;
 }
 
@@ -374,7 +375,8 @@ static hsma_status tick(hsma_server_s* sv) {
     if (newA.empty() && stB.empty()) return HSMA_OK;
     const bool f32 = sv->desc.precision == HSMA_FP32_COMP;
     std::vector<ReqDesc> da, db;
-    std::vector<TileItem> tiles;
+    std::vector<TileGroup> tiles;
+    int ntiles = 0;
     int maxA_blk = 1, maxA_ns = 1, maxB_K = 1, maxB_nu = 1, maxB_M = 1, maxB_e = 1;
     for (SrvReq* r : newA) {
         da.push_back(r->d);
@@ -388,24 +390,22 @@ static hsma_status tick(hsma_server_s* sv) {
         maxB_M = std::max(maxB_M, (r->d.M + 3) / 4);
         maxB_e = std::max(maxB_e, r->d.n_eblk);
     }
-    // tiles: near first (the longest), then right-hand side, then surface
+    // tile groups: near first (the longest), then right-hand side, then surface
     for (SrvReq* r : newA) {
-        const hsma_plan_s* pl = r->plan;
         const ReqDesc& d = r->d;
-        if (f32) add_tiles(tiles, TILE_NEAR, d.img, r->ly.g_near, d.src32, d.src32, d.near_part, d.L);
-        else add_tiles(tiles, TILE_NEAR, d.img, r->ly.g_near, d.src64, d.src64, d.near_part, d.L);
-        (void)pl;
+        if (f32) add_group(tiles, &ntiles, TILE_NEAR, d.img, r->ly.g_near, d.src32, d.src32, d.near_part, d.L);
+        else add_group(tiles, &ntiles, TILE_NEAR, d.img, r->ly.g_near, d.src64, d.src64, d.near_part, d.L);
     }
     for (SrvReq* r : newA) {
         const hsma_plan_s* pl = r->plan;
         const ReqDesc& d = r->d;
-        if (f32) add_tiles(tiles, TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk32, d.src32, d.rhs_part, d.L);
-        else add_tiles(tiles, TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk64, d.src64, d.rhs_part, d.L);
+        if (f32) add_group(tiles, &ntiles, TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk32, d.src32, d.rhs_part, d.L);
+        else add_group(tiles, &ntiles, TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk64, d.src64, d.rhs_part, d.L);
     }
     for (SrvReq* r : stB)
-        add_tiles(tiles, TILE_SURFACE, 0, r->ly.g_surf, r->d.src64, r->d.surf, r->d.surf_part, r->d.L);
+        add_group(tiles, &ntiles, TILE_SURFACE, 0, r->ly.g_surf, r->d.src64, r->d.surf, r->d.surf_part, r->d.L);
     ReqDesc *dA = nullptr, *dB = nullptr;
-    TileItem* dT = nullptr;
+    TileGroup* dT = nullptr;
     hsma_status st = upload(sv, da, db, tiles, &dA, &dB, &dT);
     if (st != HSMA_OK) return st;
     hipStream_t s = sv->stream;
@@ -425,7 +425,7 @@ static hsma_status tick(hsma_server_s* sv) {
     HSMA_HIP(hipGetLastError());
     // all pair tiles of the tick in one launch
     timing_begin(0, s);
-    HSMA_HIP(launch_group_tiles(f32, dT, (int)tiles.size(), s));
+    HSMA_HIP(launch_group_tiles(f32, dT, (int)tiles.size(), ntiles, s));
     timing_end(0, s);
     // stage B, part 2: finalize, energy, results to host
     if (nB) {
@@ -448,7 +448,7 @@ static hsma_status tick(hsma_server_s* sv) {
     HSMA_HIP(hipEventRecord(te, s));
     sv->inflight.push_back(te);
     sv->stats.ticks += 1;
-    sv->stats.tiles += (int64_t)tiles.size();
+    sv->stats.tiles += (int64_t)ntiles;
     return HSMA_OK;
 }
 

@@ -23,6 +23,10 @@ struct Layout {
            off_real32 = 0, off_ud = 0;
     size_t off_cnt = 0, off_imgoff = 0, off_img64 = 0, off_img32 = 0;   // sphere near set
     int64_t img_max = 0;
+    // near sum with each unordered pair once (periodic or grounded box, block
+    // near set, single precision); its accumulators replace the chunk partials
+    bool sym = false;
+    SymGeom g_sym;
     int n_eblk = 1;
     size_t total = 0;
 };

@@ -38,6 +38,16 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     const int ns_pairs = sphere ? (int)std::min<int64_t>(ly.img_max, INT32_MAX) : ly.ns;
     ly.g_rhs = pair_geometry(pl->nchk, ns_pairs, tpl_rhs, pl->ncu);
     ly.g_near = pair_geometry(ly.N, ns_pairs, tpl_near, pl->ncu);
+    // Pair-once near sum: worth it once a round holds enough waves to fill the
+    // GPU.  HSMA_SYM=0 turns it off, HSMA_SYM=1 forces it (any N), otherwise
+    // it is used from HSMA_SYM_MIN particles on.
+    {
+        const int mode = env_int("HSMA_SYM", -1);
+        const int nmin = env_int("HSMA_SYM_MIN", 262144);
+        const bool eligible = f32 && !sphere && pl->bc != HSMA_BC_SLAB_METALLIC_Z && ly.N > 0;
+        ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
+        if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 2) == 1 ? 1 : 2, pl->ncu);
+    }
     const int nsurf = pl->dipole_mode == HSMA_DIPOLE_LAYERS ? 3 * pl->M : pl->M;
     ly.g_surf = pair_geometry(ly.N, nsurf, 1, pl->ncu);
     size_t o = 0;
@@ -48,7 +58,12 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.off_b = take(sizeof(double) * (size_t)pl->K);
     ly.off_A = take(sizeof(double) * (size_t)pl->nb);
     ly.off_surf = take(sizeof(double) * 12 * (size_t)pl->M);   // 8 per point, or 3 charges
-    ly.off_near_part = take(sizeof(double) * 4 * (size_t)ly.g_near.S * ly.g_near.nt_pad);
+    {
+        size_t near_doubles = 4 * (size_t)ly.g_near.S * ly.g_near.nt_pad;
+        if (ly.sym)
+            near_doubles = std::max(near_doubles, (size_t)(ly.g_sym.C + ly.g_sym.s) * 4 * ly.g_sym.n_pad);
+        ly.off_near_part = take(sizeof(double) * near_doubles);
+    }
     ly.off_surf_part = take(sizeof(double) * 4 * (size_t)ly.g_surf.S * ly.g_surf.nt_pad);
     ly.n_eblk = (ly.N + WG - 1) / WG;
     if (ly.n_eblk < 1) ly.n_eblk = 1;
@@ -198,6 +213,36 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int 
 }
 
 // ---------------------------------------------------------------- pipeline
+// Auxiliary stream and events of the calling host thread on a device: the
+// right-hand-side chain (pairs, reduction, least squares, mapping) runs on it
+// while the near-field kernel runs on the caller's stream.  Default priority,
+// created once per thread and device.
+struct AuxStream {
+    int device = -1;
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static hipError_t aux_stream(int device, AuxStream** out) {
+    static thread_local AuxStream aux[16];
+    if (device < 0 || device >= 16) return hipErrorInvalidDevice;
+    AuxStream& a = aux[device];
+    if (a.s == nullptr) {
+        hipError_t e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
+        a.device = device;
+    }
+    *out = &a;
+    return hipSuccess;
+}
+
+static bool overlap_enabled() {
+    static const int v = env_int("HSMA_OVERLAP", 1);
+    return v != 0;
+}
+
 #define CK(call)                                                                             \
     do {                                                                                     \
         hipError_t e_ = (call);                                                              \
@@ -256,42 +301,55 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
             CK(launch_make_rec32(img64, n_img, pl->L, img32, s));
         }
     }
+    // fork: the right-hand-side chain goes to the auxiliary stream
+    hipStream_t s1 = s;
+    AuxStream* aux = nullptr;
+    if (overlap_enabled()) {
+        CK(aux_stream(pl->device, &aux));
+        CK(hipEventRecord(aux->fork, s));
+        CK(hipStreamWaitEvent(aux->s, aux->fork, 0));
+        s1 = aux->s;
+    }
     // right-hand side at the monitoring points (and twins)
-    timing_begin(1, s);
+    timing_begin(1, s1);
     if (sphere)
         CK(launch_explicit(f32, false, false, f32 ? (const void*)pl->d_chk32 : (const void*)pl->d_chk64,
-                           f32 ? (const void*)img32 : (const void*)img64, g_rhs, pl->L, rhs_part, s));
+                           f32 ? (const void*)img32 : (const void*)img64, g_rhs, pl->L, rhs_part, s1));
     else if (f32)
-        CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, g_rhs, pl->L, rhs_part, s));
+        CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, g_rhs, pl->L, rhs_part, s1));
     else
-        CK(launch_pair_f64(pl->img, false, false, pl->d_chk64, src64, g_rhs, pl->L, rhs_part, s));
-    timing_end(1, s);
-    hipLaunchKernelGGL(k_rhs_finalize, dim3((pl->K + WG - 1) / WG), dim3(WG), 0, s, rhs_part,
+        CK(launch_pair_f64(pl->img, false, false, pl->d_chk64, src64, g_rhs, pl->L, rhs_part, s1));
+    timing_end(1, s1);
+    hipLaunchKernelGGL(k_rhs_finalize, dim3((pl->K + WG - 1) / WG), dim3(WG), 0, s1, rhs_part,
                        g_rhs.S, g_rhs.nt_pad, pl->K, pl->img == IMG_PERIODIC ? 1 : 0, b);
-    hipLaunchKernelGGL(k_lsq, dim3((pl->nu + 3) / 4), dim3(WG), 0, s, pl->d_P, pl->nu, pl->K, b,
+    hipLaunchKernelGGL(k_lsq, dim3((pl->nu + 3) / 4), dim3(WG), 0, s1, pl->d_P, pl->nu, pl->K, b,
                        pl->nb - pl->nu, A);
     const bool layers = pl->dipole_mode == HSMA_DIPOLE_LAYERS;
     const bool direct = pl->far_mode == HSMA_FAR_DIRECT;
     if (direct) {
         // no mapping: the series is evaluated at the particles below
     } else if (layers)
-        hipLaunchKernelGGL(k_map_layers, dim3((pl->M + 3) / 4), dim3(WG), 0, s, pl->d_Wq, pl->d_Wp,
+        hipLaunchKernelGGL(k_map_layers, dim3((pl->M + 3) / 4), dim3(WG), 0, s1, pl->d_Wq, pl->d_Wp,
                            pl->M, pl->nb, A, pl->d_spos, pl->Rs, pl->dr, (double4*)surf);
     else
-        hipLaunchKernelGGL(k_map, dim3((pl->M + 3) / 4), dim3(WG), 0, s, pl->d_Wq, pl->d_Wp, pl->M,
+        hipLaunchKernelGGL(k_map, dim3((pl->M + 3) / 4), dim3(WG), 0, s1, pl->d_Wq, pl->d_Wp, pl->M,
                            pl->nb, A, pl->d_spos, pl->Rs, surf);
     CK(hipGetLastError());
+    if (aux != nullptr) CK(hipEventRecord(aux->join, s1));
     // near field at the particles: the sources and their 27 images, self excluded
     timing_begin(0, s);
     if (sphere)
         CK(launch_explicit(f32, true, true, f32 ? (const void*)src32 : (const void*)src64,
                            f32 ? (const void*)img32 : (const void*)img64, g_near, pl->L, near_part, s));
+    else if (ly.sym)
+        CK(launch_sym_f32(pl->img, src32, ly.g_sym, pl->L, near_part, s));
     else if (f32)
         CK(launch_pair_f32(pl->img, true, true, src32, src32, g_near, pl->L, near_part, s));
     else
         CK(launch_pair_f64(pl->img, true, true, src64, src64, g_near, pl->L, near_part, s));
     timing_end(0, s);
-    // surface images at the particles
+    // join, then the surface images at the particles
+    if (aux != nullptr) CK(hipStreamWaitEvent(s, aux->join, 0));
     PairGeom g_surf = ly.g_surf;
     timing_begin(2, s);
     if (direct) {
@@ -303,8 +361,10 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
         CK(launch_surface_f64(src64, surf, g_surf, surf_part, s));
     }
     timing_end(2, s);
-    hipLaunchKernelGGL(k_finalize, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, g_near.S,
-                       g_near.nt_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, phi,
+    const int near_S = ly.sym ? ly.g_sym.C + ly.g_sym.s : g_near.S;
+    const int near_pad = ly.sym ? ly.g_sym.n_pad : g_near.nt_pad;
+    hipLaunchKernelGGL(k_finalize, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, near_S,
+                       near_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, phi,
                        forces, dbg ? dbg->phi_near : nullptr, dbg ? dbg->field_near : nullptr,
                        dbg ? dbg->phi_out : nullptr, dbg ? dbg->field_out : nullptr, eblk);
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(WG), 0, s, eblk, ly.n_eblk,

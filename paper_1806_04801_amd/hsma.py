@@ -70,6 +70,12 @@ class ServerStats(ctypes.Structure):
                 ("arena_peak", ctypes.c_size_t)]
 
 
+class NearSchedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("rows_per_lane", ctypes.c_int), ("block", ctypes.c_int),
+                ("slices", ctypes.c_int), ("parts", ctypes.c_int), ("blocks", ctypes.c_int),
+                ("launches", ctypes.c_int)]
+
+
 _TRACE_ARGS = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
 
@@ -84,6 +90,7 @@ EXPORTS = {
     "hsma_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
     "hsma_plan_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "hsma_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
+    "hsma_near_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(NearSchedule)]),
     "hsma_energy_forces": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_void_p, ctypes.c_void_p]),
@@ -191,6 +198,13 @@ class Plan:
 
     def workspace_bytes(self, n):
         return int(load().hsma_workspace_bytes(self._h, int(n)))
+
+    def near_schedule(self, n):
+        """The near-field kernel a step with n particles runs (see hsma.h):
+        kind 0 per-target tiles, kind 1 each unordered pair once."""
+        out = NearSchedule()
+        _check(load().hsma_near_schedule(self._h, int(n), ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in NearSchedule._fields_}
 
     def workspace(self, n, device):
         import torch

@@ -1,0 +1,142 @@
+"""Near sum with each unordered pair once (GPU, through the C ABI).
+
+The pair-once kernel must give what the per-target tile kernel gives, up to
+single-precision rounding, and match the oracle under the FP32 gates:
+|dE|/|E| <= 1e-5, potential error <= 1e-5 of its rms, force error <= 1e-4 of
+its maximum.  Cases cover several rounds, an odd block count (a bye in every
+round), ragged last blocks and slices, one and two rows per lane, both image
+kinds, and the adjoint, which reads the same near accumulators.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import announce, rel_max, rms
+from paper_1806_04801_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04801_amd import hsma
+    hsma.load()
+    return hsma
+
+
+def run(hs, plan, x, q, monkeypatch, sym, T=2):
+    monkeypatch.setenv("HSMA_SYM", "1" if sym else "0")
+    monkeypatch.setenv("HSMA_SYM_T", str(T))
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+    qd = torch.tensor(q, dtype=torch.float64, device="cuda")
+    e, phi, F, inter = plan.energy_forces(xd, qd, intermediates=True)
+    torch.cuda.synchronize()
+    return e, phi.cpu().numpy(), F.cpu().numpy(), {k: v.cpu().numpy() for k, v in inter.items()}
+
+
+def rel_own(a, ref):
+    """max_i |a_i - ref_i| / max(|ref_i|, rms(ref)): each particle against its
+    own magnitude, with the rms as the floor.  A particle next to a grounded
+    wall carries its own reflected image at twice the wall distance; at
+    N = 4e4 the closest one sits 5e-8 from a wall and has |phi| ~ 1e7 against
+    an rms of 5e4, so one single-precision rounding of that term alone is
+    1e-5 of the rms."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.maximum(np.abs(ref), rms(ref))
+    return float((np.abs(a - ref) / scale).max())
+
+
+def charges(bc, n, seed):
+    """n uniform charges of +-1; for the periodic box the last one is adjusted
+    so that the system stays neutral (odd n gives it charge 0 or +-2)."""
+    x, q = W.uniform_neutral(n + (n % 2), 1.0, seed=seed)
+    x, q = x[:n].copy(), q[:n].copy()
+    if bc == 0:
+        q[-1] -= q.sum()
+    return x, q
+
+
+@pytest.mark.parametrize("bc,n,T", [(0, 3000, 1), (0, 3000, 2), (1, 3001, 1), (1, 3001, 2)])
+def test_sym_vs_oracle(hs, monkeypatch, bc, n, T):
+    # n = 3000, T = 1: 47 blocks of 64 (odd: a bye per round), last block 56 rows
+    announce("sym vs oracle bc=%d n=%d T=%d" % (bc, n, T))
+    x, q = charges(bc, n, 41 + n)
+    ref = oracle.solve(oracle.make_plan(1.0, bc, 12, 1000, 600, 2.7), x, q)
+    plan = hs.Plan(1.0, bc, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
+    e, phi, F, inter = run(hs, plan, x, q, monkeypatch, True, T)
+    err_e = abs(e - ref["energy"]) / abs(ref["energy"])
+    err_pn = rel_own(inter["phi_near"], ref["phi_near"])
+    err_fn = rel_max(inter["field_near"], ref["field_near"])
+    err_F = rel_max(F, ref["forces"])
+    print("sym bc=%d n=%d T=%d: dE/E %.2e dphi_near %.2e dE_near %.2e dF %.2e"
+          % (bc, n, T, err_e, err_pn, err_fn, err_F))
+    assert err_e <= 1e-5
+    assert err_pn <= 1e-5
+    assert err_fn <= 1e-4
+    assert err_F <= 1e-4
+
+
+@pytest.mark.parametrize("bc,n,T", [(0, 40001, 1), (1, 40000, 2)])
+def test_sym_vs_tiles(hs, monkeypatch, bc, n, T):
+    # n = 40001, T = 1: blocks of 3 slices x 64 rows; the last block holds 65
+    # rows, so its second slice has one live row and its third none
+    announce("sym vs tiles bc=%d n=%d T=%d" % (bc, n, T))
+    x, q = charges(bc, n, 7 + n)
+    plan = hs.Plan(1.0, bc, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
+    plan64 = hs.Plan(1.0, bc, 12, 1000, 600, 2.7, precision=hs.FP64)
+    e_s, phi_s, F_s, in_s = run(hs, plan, x, q, monkeypatch, True, T)
+    e_t, phi_t, F_t, in_t = run(hs, plan, x, q, monkeypatch, False)
+    e_d, phi_d, F_d, in_d = run(hs, plan64, x, q, monkeypatch, False)
+    for name, (e, pn, fn) in {"sym": (e_s, in_s["phi_near"], in_s["field_near"]),
+                              "tiles": (e_t, in_t["phi_near"], in_t["field_near"])}.items():
+        err_e = abs(e - e_d) / abs(e_d)
+        err_pn = rel_own(pn, in_d["phi_near"])
+        err_fn = rel_max(fn, in_d["field_near"])
+        print("%s bc=%d n=%d: dE/E %.2e dphi_near %.2e dE_near %.2e" % (name, bc, n, err_e, err_pn, err_fn))
+        assert err_e <= 1e-5
+        assert err_pn <= 1e-5
+        assert err_fn <= 1e-4
+    # the two single-precision kernels agree with each other at least as well
+    assert rel_own(in_s["phi_near"], in_t["phi_near"]) <= 1e-5
+
+
+@pytest.mark.parametrize("bc,n", [(1, 1), (1, 2), (0, 2), (0, 64), (1, 65)])
+def test_sym_small(hs, monkeypatch, bc, n):
+    announce("sym small bc=%d n=%d" % (bc, n))
+    if n == 1:
+        x, q = np.array([[0.3, 0.6, 0.45]]), np.array([1.0])
+    else:
+        x, q = charges(bc, n, 100 + n)
+    ref = oracle.solve(oracle.make_plan(1.0, bc, 8, 1000, 600, 2.7), x, q)
+    plan = hs.Plan(1.0, bc, 8, 1000, 600, 2.7, precision=hs.FP32_COMP)
+    e, phi, F, inter = run(hs, plan, x, q, monkeypatch, True, 1)
+    err_pn = rel_max(inter["phi_near"], ref["phi_near"])
+    err_fn = rel_max(inter["field_near"], ref["field_near"])
+    print("sym small bc=%d n=%d: dphi_near %.2e dE_near %.2e" % (bc, n, err_pn, err_fn))
+    assert err_pn <= 1e-5
+    assert err_fn <= 1e-4
+    assert abs(e - ref["energy"]) <= 1e-5 * abs(ref["energy"])
+
+
+def test_sym_adjoint(hs, monkeypatch):
+    announce("sym adjoint")
+    x, q = charges(0, 3000, 77)
+    plan = hs.Plan(1.0, 0, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+    qd = torch.tensor(q, dtype=torch.float64, device="cuda")
+    out = {}
+    for sym in (True, False):
+        monkeypatch.setenv("HSMA_SYM", "1" if sym else "0")
+        e, gx, gq = plan.energy_grad(xd, qd)
+        torch.cuda.synchronize()
+        out[sym] = (e, gx.cpu().numpy(), gq.cpu().numpy())
+    (e1, gx1, gq1), (e0, gx0, gq0) = out[True], out[False]
+    print("sym adjoint: dE %.2e dgx %.2e dgq %.2e"
+          % (abs(e1 - e0) / abs(e0), rel_max(gx1, gx0), rel_max(gq1, gq0, rms(gq0))))
+    assert abs(e1 - e0) <= 1e-5 * abs(e0)
+    assert rel_max(gx1, gx0) <= 1e-4
+    assert rel_max(gq1, gq0, rms(gq0)) <= 1e-5

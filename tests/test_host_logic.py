@@ -43,18 +43,35 @@ def test_bench_sphere_image_count(bc):
 
 
 def test_bench_traffic_needs_matching_kernel_source(tmp_path, monkeypatch):
+    import shutil
+
     import bench
+    csrc = os.path.join(os.path.dirname(HERE), "paper_1806_04801_amd", "csrc")
+    (tmp_path / "paper_1806_04801_amd" / "csrc").mkdir(parents=True)
+    for name in ("pairs.hip", "sym.hip", "pair_math.h"):
+        shutil.copy(os.path.join(csrc, name), tmp_path / "paper_1806_04801_amd" / "csrc" / name)
     prof = tmp_path / "profiles"
     prof.mkdir()
+    h_tiles = bench.kernel_source_hash("tiles")
+    h_once = bench.kernel_source_hash("pair-once")
+    assert h_tiles != h_once
     (prof / "near_f32_w_pmc.md").write_text(
-        "- hbm_bytes_per_launch: 123.5\n- kernel_source_sha256_16: %s   (x)\n" % bench.kernel_source_hash())
+        "- hbm_bytes_per_launch: 123.5\n- kernel_source_sha256_16: %s   (x)\n" % h_tiles)
+    (prof / "near_pair_once_f32_w_pmc.md").write_text(
+        "- hbm_bytes_per_launch: 77.0\n- kernel_source_sha256_16: %s   (x)\n" % h_once)
     (prof / "near_f32_v_pmc.md").write_text(
         "- hbm_bytes_per_launch: 123.5\n- kernel_source_sha256_16: 0000000000000000\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    (tmp_path / "paper_1806_04801_amd" / "csrc").mkdir(parents=True)
-    import shutil
-    shutil.copy(os.path.join(os.path.dirname(HERE), "paper_1806_04801_amd", "csrc", "pairs.hip"),
-                tmp_path / "paper_1806_04801_amd" / "csrc" / "pairs.hip")
     assert bench.profiled_traffic("w", "f32") == 123.5
+    assert bench.profiled_traffic("w", "f32", "pair-once") == 77.0
     assert bench.profiled_traffic("v", "f32") is None
     assert bench.profiled_traffic("missing", "f32") is None
+    # a summary of one kernel does not serve the other
+    (prof / "near_pair_once_f32_v_pmc.md").write_text(
+        "- hbm_bytes_per_launch: 5.0\n- kernel_source_sha256_16: %s   (x)\n" % h_tiles)
+    assert bench.profiled_traffic("v", "f32", "pair-once") is None
+    # an edit to the shared arithmetic invalidates both
+    with open(tmp_path / "paper_1806_04801_amd" / "csrc" / "pair_math.h", "a") as f:
+        f.write("// edit\n")
+    assert bench.profiled_traffic("w", "f32") is None
+    assert bench.profiled_traffic("w", "f32", "pair-once") is None
