@@ -174,9 +174,10 @@ size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
  *   kind 1: each unordered particle pair is evaluated once and both of its
  *           directions are accumulated (the image-block sum is symmetric in
  *           the two particles).  Single precision, periodic or grounded box,
- *           block near set, N at or above a threshold (262144, or the
+ *           block near set, N at or above a threshold (65536, or the
  *           HSMA_SYM_MIN environment variable); HSMA_SYM=0 in the environment
- *           turns it off and HSMA_SYM=1 forces it.  The particles are cut
+ *           turns it off and HSMA_SYM=1 forces it (HSMA_SYM_T = 1 or 2 fixes
+ *           the rows per lane, chosen otherwise).  The particles are cut
  *           into `blocks` blocks of `block`; block pairs run in blocks - 1
  *           (+1 if odd) round-robin rounds after one diagonal launch; a block
  *           pair is split into `slices` row slices of 64 * rows_per_lane rows

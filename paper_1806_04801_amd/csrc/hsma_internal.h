@@ -67,7 +67,10 @@ struct SymGeom {
     int P = 0;       // nb rounded up to even: P - 1 rounds
     int n_pad = 0;   // nb * B
 };
-SymGeom sym_geometry(int n, int T, int ncu);
+// Single precision: T = 1 or 2 rows per lane, or 0 to choose the one whose
+// rounds fill the GPU better (resident waves from the occupancy of each kernel
+// variant).  Double precision (f64): one row per lane.
+SymGeom sym_geometry(int n, int T, bool f64, int ncu);
 
 // One group of tiles of a grouped pair launch: all tiles of one pair stage of
 // one request.  Tile i of the group (0 <= i < ntb * S) is target block
@@ -135,10 +138,13 @@ hipError_t launch_surface_f64(const double4* tgt, const double* surf, const Pair
                               double* out, hipStream_t s);
 hipError_t launch_group_tiles(bool f32, const TileGroup* groups, int ngroups, int ntiles,
                               hipStream_t s);
-// Near sum at the particles, each unordered pair once (single precision,
-// periodic or grounded images).  acc: (g.C + g.s) copies of 4 x g.n_pad doubles,
+// Near sum at the particles, each unordered pair once (periodic or grounded
+// images), single precision on Rec32 records.  acc: (g.C + g.s) copies of 4 x g.n_pad doubles,
 // written completely for the first g.n entries of each component.
 hipError_t launch_sym_f32(int img, const Rec32* pts, const SymGeom& g, double L, double* acc,
+                          hipStream_t s);
+// The same in double precision on centred double4 (x, y, z, q) records.
+hipError_t launch_sym_f64(int img, const double4* pts, const SymGeom& g, double L, double* acc,
                           hipStream_t s);
 // Pair sums over an explicit list of charges (double4 or Rec32 records).
 hipError_t launch_explicit(bool f32, bool field, bool self, const void* tgt, const void* src,

@@ -29,9 +29,12 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.ns = (pl->bc == HSMA_BC_SLAB_METALLIC_Z) ? 2 * (int)N : (int)N;
     const int prec = precision_override >= 0 ? precision_override : pl->precision;
     const bool f32 = prec == HSMA_FP32_COMP;
-    const int tpl_near = tpl_near_override > 0 ? tpl_near_override : env_int("HSMA_TPL_NEAR", 2);
-    const int tpl_rhs = env_int("HSMA_TPL_RHS", 1);
     const bool sphere = pl->near_mode == HSMA_NEAR_SPHERE;
+    // targets per lane of the near tiles: the image-block kernels run best
+    // with one, the explicit-image tiles with two (measured)
+    const int tpl_near = tpl_near_override > 0 ? tpl_near_override
+                                               : env_int("HSMA_TPL_NEAR", sphere ? 2 : 1);
+    const int tpl_rhs = env_int("HSMA_TPL_RHS", 1);
     // sphere mode: sources are the explicit images (at most maxper per source);
     // partial buffers are sized for that bound
     ly.img_max = sphere ? (int64_t)ly.ns * pl->maxper : 0;
@@ -43,10 +46,10 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     // it is used from HSMA_SYM_MIN particles on.
     {
         const int mode = env_int("HSMA_SYM", -1);
-        const int nmin = env_int("HSMA_SYM_MIN", 262144);
-        const bool eligible = f32 && !sphere && pl->bc != HSMA_BC_SLAB_METALLIC_Z && ly.N > 0;
+        const int nmin = env_int("HSMA_SYM_MIN", 65536);
+        const bool eligible = !sphere && pl->bc != HSMA_BC_SLAB_METALLIC_Z && ly.N > 0;
         ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
-        if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 2) == 1 ? 1 : 2, pl->ncu);
+        if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 0), !f32, pl->ncu);
     }
     const int nsurf = pl->dipole_mode == HSMA_DIPOLE_LAYERS ? 3 * pl->M : pl->M;
     ly.g_surf = pair_geometry(ly.N, nsurf, 1, pl->ncu);
@@ -341,8 +344,10 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     if (sphere)
         CK(launch_explicit(f32, true, true, f32 ? (const void*)src32 : (const void*)src64,
                            f32 ? (const void*)img32 : (const void*)img64, g_near, pl->L, near_part, s));
-    else if (ly.sym)
+    else if (ly.sym && f32)
         CK(launch_sym_f32(pl->img, src32, ly.g_sym, pl->L, near_part, s));
+    else if (ly.sym)
+        CK(launch_sym_f64(pl->img, src64, ly.g_sym, pl->L, near_part, s));
     else if (f32)
         CK(launch_pair_f32(pl->img, true, true, src32, src32, g_near, pl->L, near_part, s));
     else

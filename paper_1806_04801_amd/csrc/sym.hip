@@ -40,25 +40,40 @@ constexpr int SW = 64;   // one wave per work-group
 __device__ __forceinline__ bool parity(int x) { return __builtin_popcount(x) & 1; }
 
 template <int CTRL>
-__device__ __forceinline__ float dpp_f(float x) {
+__device__ __forceinline__ float dpp_t(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ float lane_f(float x, int src_lane) {
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float lane_t(float x, int src_lane) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(x)));
+}
+
+__device__ __forceinline__ double lane_t(double x, int src_lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // One halving step of the reduce-scatter: lane l and its partner l ^ m hold
 // the same N pairs (v[k], v[k + N]); the lane with f set keeps the upper
 // halves, the other the lower ones, and each adds the partner's copy.
-template <int N, int CTRL>
-__device__ __forceinline__ void rs_step(float (&v)[16], bool f) {
+template <int N, int CTRL, typename R>
+__device__ __forceinline__ void rs_step(R (&v)[16], bool f) {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const float lo = v[k], hi = v[k + N];
-        const float keep = f ? hi : lo;
-        const float send = f ? lo : hi;
-        v[k] = keep + dpp_f<CTRL>(send);
+        const R lo = v[k], hi = v[k + N];
+        const R keep = f ? hi : lo;
+        const R send = f ? lo : hi;
+        v[k] = keep + dpp_t<CTRL>(send);
     }
 }
 
@@ -74,46 +89,65 @@ __device__ __forceinline__ int rs_owner(int lane) {
     return parity(lane & 5) * 8 + parity(lane & 6) * 4 + parity(lane & 12) * 2 + ((lane >> 3) & 1);
 }
 
-__device__ __forceinline__ float reduce_scatter16(float (&v)[16], int lane) {
+template <typename R>
+__device__ __forceinline__ R reduce_scatter16(R (&v)[16], int lane) {
     rs_step<8, 0xB1>(v, parity(lane & 5));     // quad_perm [1,0,3,2]
     rs_step<4, 0x4E>(v, parity(lane & 6));     // quad_perm [2,3,0,1]
     rs_step<2, 0x141>(v, parity(lane & 12));   // row_half_mirror
     rs_step<1, 0x140>(v, (lane >> 3) & 1);     // row_mirror
-    float e = v[0];
-    e += lane_f(e, lane ^ 16);
-    e += lane_f(e, lane ^ 32);
+    R e = v[0];
+    e += lane_t(e, lane ^ 16);
+    e += lane_t(e, lane ^ 32);
     return e;
+}
+
+// The work item of this work-group: row block I, column block J, row slice
+// and column part.  Consecutive items (the slices and parts of one block
+// pair, which read the same columns) go to the same XCD: the hardware deals
+// work-groups round-robin over the 8 XCDs.
+struct SymItem {
+    int I, J, sig, part;
+    bool ok;
+};
+
+template <bool DIAG>
+__device__ __forceinline__ SymItem sym_item(const SymGeom& g, int round) {
+    SymItem it;
+    const int per_xcd = gridDim.x >> 3;
+    const int id = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int per_pair = g.s * g.C;
+    int pr;
+    it.ok = false;
+    if (DIAG) {
+        if (id >= g.nb * per_pair) return it;
+        it.I = it.J = pr = id / per_pair;
+    } else {
+        if (id >= (g.P >> 1) * per_pair) return it;
+        pr = id / per_pair;
+        const int m = g.P - 1;
+        if (pr == 0) {
+            it.I = m;
+            it.J = round;
+        } else {
+            it.I = (round + pr) % m;
+            it.J = (round - pr + m) % m;
+        }
+        if (it.I >= g.nb || it.J >= g.nb) return it;   // the bye of an odd block count
+    }
+    const int rem = id - pr * per_pair;
+    it.sig = rem / g.C;
+    it.part = rem - it.sig * g.C;
+    it.ok = true;
+    return it;
 }
 
 template <int IMG, int T, bool DIAG>
 __global__ void __launch_bounds__(SW)
 k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, double* __restrict__ acc) {
     const int lane = threadIdx.x;
-    // consecutive work items (the slices of one pair read the same columns)
-    // go to the same XCD: the hardware deals work-groups round-robin over 8
-    const int per_xcd = gridDim.x >> 3;
-    const int id = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const int per_pair = g.s * g.C;
-    int I, J, pr;
-    if (DIAG) {
-        if (id >= g.nb * per_pair) return;
-        I = J = pr = id / per_pair;
-    } else {
-        if (id >= (g.P >> 1) * per_pair) return;
-        pr = id / per_pair;
-        const int m = g.P - 1;
-        if (pr == 0) {
-            I = m;
-            J = round;
-        } else {
-            I = (round + pr) % m;
-            J = (round - pr + m) % m;
-        }
-        if (I >= g.nb || J >= g.nb) return;   // the bye of an odd block count
-    }
-    const int rem = id - pr * per_pair;
-    const int sig = rem / g.C;
-    const int part = rem - sig * g.C;
+    const SymItem it = sym_item<DIAG>(g, round);
+    if (!it.ok) return;
+    const int I = it.I, J = it.J, sig = it.sig, part = it.part;
     const size_t cs = (size_t)4 * g.n_pad;
     double* __restrict__ fwd = acc + (size_t)part * cs;
     double* __restrict__ rev = acc + (size_t)(g.C + sig) * cs;
@@ -232,17 +266,106 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
     }
 }
 
-// Resident one-wave work-groups per CU for the kernel of T rows per lane.
+// Double precision: one row per lane, positions in physical units (centred
+// double4 x, y, z, q), plain FMA accumulation as in the double tile kernel;
+// reverse terms are reduced in double.
+template <int IMG, bool DIAG>
+__global__ void __launch_bounds__(SW)
+k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, double* __restrict__ acc) {
+    const int lane = threadIdx.x;
+    const SymItem it = sym_item<DIAG>(g, round);
+    if (!it.ok) return;
+    const size_t cs = (size_t)4 * g.n_pad;
+    double* __restrict__ fwd = acc + (size_t)it.part * cs;
+    double* __restrict__ rev = acc + (size_t)(g.C + it.sig) * cs;
+
+    // the row; a lane past the end carries no charge and sits far outside
+    // every image of the box
+    const int i = it.I * g.B + it.sig * SW + lane;
+    double4 t = pts[min(i, g.n - 1)];
+    double qi = t.w;
+    if (i >= g.n) {
+        qi = 0.0;
+        t.x = t.y = t.z = 1000.0 * L;
+    }
+    double ap = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+
+    const int c0 = min(it.J * g.B + (int)((long)it.part * g.B / g.C), g.n);
+    const int c1 = min(it.J * g.B + (int)((long)(it.part + 1) * g.B / g.C), g.n);
+    const int kown = rs_owner(lane);
+    const int kcol = kown >> 2, kcomp = kown & 3;
+    for (int jb = c0; jb < c1; jb += 4) {
+        const int nh = min(4, c1 - jb);
+        double old = 0.0;
+        double* dst = nullptr;
+        if (!DIAG && lane < 16 && kcol < nh) {
+            dst = rev + (size_t)kcomp * g.n_pad + jb + kcol;
+            old = *dst;
+        }
+        double rv[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double rp = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
+            if (q < nh) {
+                const double4 sj = pts[jb + q];
+                double dx[3], dy[3], dz[3];
+                diffs_f64<IMG>(t.x, sj.x, L, dx);
+                diffs_f64<IMG>(t.y, sj.y, L, dy);
+                diffs_f64<IMG>(t.z, sj.z, L, dz);
+                double p0, fx0, fy0, fz0, rf[3];
+                images_sum<double, IMG, true, true, !DIAG>(dx, dy, dz, p0, fx0, fy0, fz0, rf);
+                ap = __builtin_fma(sj.w, p0, ap);
+                ax = __builtin_fma(sj.w, fx0, ax);
+                ay = __builtin_fma(sj.w, fy0, ay);
+                az = __builtin_fma(sj.w, fz0, az);
+                if (!DIAG) {
+                    rp = qi * p0;
+                    rx = qi * rf[0];
+                    ry = qi * rf[1];
+                    rz = qi * rf[2];
+                }
+            }
+            rv[4 * q + 0] = rp;
+            rv[4 * q + 1] = rx;
+            rv[4 * q + 2] = ry;
+            rv[4 * q + 3] = rz;
+        }
+        if (!DIAG) {
+            const double e = reduce_scatter16(rv, lane);
+            if (dst != nullptr) *dst = old + e;
+        }
+    }
+
+    if (i < g.n) {
+        const double v[4] = {ap, ax, ay, az};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double* f = fwd + (size_t)c * g.n_pad + i;
+            *f = DIAG ? v[c] : *f + v[c];
+        }
+        if (DIAG && it.part == 0) {
+            for (int r = 0; r < g.s; ++r) {
+                double* z = acc + (size_t)(g.C + r) * cs + i;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) z[(size_t)c * g.n_pad] = 0.0;
+            }
+        }
+    }
+}
+
+// Resident one-wave work-groups per CU of a kernel variant (T = 0: double).
 static int sym_waves_per_cu(int T) {
     int nblk = 0;
-    hipError_t e = T == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                &nblk, (const void*)k_sym_f32<IMG_PERIODIC, 2, false>, SW, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                &nblk, (const void*)k_sym_f32<IMG_PERIODIC, 1, false>, SW, 0);
+    const void* k = T == 0   ? (const void*)k_sym_f64<IMG_PERIODIC, false>
+                    : T == 2 ? (const void*)k_sym_f32<IMG_PERIODIC, 2, false>
+                             : (const void*)k_sym_f32<IMG_PERIODIC, 1, false>;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, k, SW, 0);
     return (e == hipSuccess && nblk > 0) ? nblk : 8;
 }
 
-SymGeom sym_geometry(int n, int T, int ncu) {
+// Geometry for T rows per lane; *fill is the fraction of resident-wave slots
+// that a round's waves occupy over its batches.
+static SymGeom sym_geometry_t(int n, int T, bool f64, int ncu, double* fill) {
     SymGeom g;
     g.n = n;
     g.T = T;
@@ -252,22 +375,45 @@ SymGeom sym_geometry(int n, int T, int ncu) {
     if (s < 1) s = 1;
     if (s > 64) s = 64;
     // keep the accumulators (C + s copies of 32 bytes per particle) under 8 GB
-    while (s > 1 && (s + 1) * 32.0 * (double)n > 8e9) --s;
+    while (s > 1 && (s + 17) * 32.0 * (double)n > 8e9) --s;
     g.s = (int)s;
     g.B = (int)(rows * s);
     g.nb = (n + g.B - 1) / g.B;
     g.P = g.nb + (g.nb & 1);
     g.n_pad = g.nb * g.B;
-    // column parts: as many as keep one round within the resident waves,
-    // at least 64 columns each
-    const long cap = (long)sym_waves_per_cu(T) * ncu;
+    // Column parts: a round's waves all take equally long, so they run in
+    // batches of `cap` resident waves and the last batch may be part empty.
+    // Pick the part count (at most 16, at least 64 columns per part) whose
+    // waves fill their batches best; a larger count wins only by more than 2 %.
+    const long cap = (long)sym_waves_per_cu(f64 ? 0 : T) * ncu;
     const long w1 = (long)(g.P / 2) * g.s;
-    long C = cap / (w1 > 0 ? w1 : 1);
-    const long cmax = g.B / 64;
-    if (C > cmax) C = cmax;
-    if (C < 1) C = 1;
-    g.C = (int)C;
+    long cmax = g.B / 64;
+    if (cmax < 1) cmax = 1;
+    if (cmax > 16) cmax = 16;
+    long best = 1;
+    double best_fill = 0.0;
+    for (long C = 1; C <= cmax; ++C) {
+        const long w = w1 * C;
+        const long batches = (w + cap - 1) / cap;
+        const double f = (double)w / (double)(batches * cap);
+        if (f > best_fill + 0.02) {
+            best_fill = f;
+            best = C;
+        }
+    }
+    g.C = (int)best;
+    *fill = best_fill;
     return g;
+}
+
+SymGeom sym_geometry(int n, int T, bool f64, int ncu) {
+    double f1 = 0.0, f2 = 0.0;
+    if (f64) return sym_geometry_t(n, 1, true, ncu, &f1);
+    if (T == 1 || T == 2) return sym_geometry_t(n, T, false, ncu, &f1);
+    // one row per lane (more resident waves) unless two fill the slots better
+    const SymGeom g1 = sym_geometry_t(n, 1, false, ncu, &f1);
+    const SymGeom g2 = sym_geometry_t(n, 2, false, ncu, &f2);
+    return f2 > f1 + 0.02 ? g2 : g1;
 }
 
 template <int IMG, int T>
@@ -292,6 +438,25 @@ hipError_t launch_sym_f32(int img, const Rec32* pts, const SymGeom& g, double L,
     if (img == IMG_METALLIC)
         return g.T == 2 ? sym32<IMG_METALLIC, 2>(pts, g, invL, acc, s)
                         : sym32<IMG_METALLIC, 1>(pts, g, invL, acc, s);
+    return hipErrorInvalidValue;
+}
+
+template <int IMG>
+static hipError_t sym64(const double4* pts, const SymGeom& g, double L, double* acc, hipStream_t s) {
+    auto grid8 = [](long w) { return (unsigned)((w + 7) / 8 * 8); };
+    hipLaunchKernelGGL((k_sym_f64<IMG, true>), dim3(grid8((long)g.nb * g.s * g.C)), dim3(SW), 0, s,
+                       pts, g, -1, L, acc);
+    const unsigned grid = grid8((long)(g.P / 2) * g.s * g.C);
+    for (int r = 0; r < g.P - 1; ++r)
+        hipLaunchKernelGGL((k_sym_f64<IMG, false>), dim3(grid), dim3(SW), 0, s, pts, g, r, L, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_f64(int img, const double4* pts, const SymGeom& g, double L, double* acc,
+                          hipStream_t s) {
+    if (g.n <= 0 || g.nb <= 0 || g.T != 1) return hipErrorInvalidValue;
+    if (img == IMG_PERIODIC) return sym64<IMG_PERIODIC>(pts, g, L, acc, s);
+    if (img == IMG_METALLIC) return sym64<IMG_METALLIC>(pts, g, L, acc, s);
     return hipErrorInvalidValue;
 }
 

@@ -1,11 +1,13 @@
 """Near sum with each unordered pair once (GPU, through the C ABI).
 
 The pair-once kernel must give what the per-target tile kernel gives, up to
-single-precision rounding, and match the oracle under the FP32 gates:
-|dE|/|E| <= 1e-5, potential error <= 1e-5 of its rms, force error <= 1e-4 of
-its maximum.  Cases cover several rounds, an odd block count (a bye in every
+rounding, and match the oracle under the gates of its precision: in single
+precision |dE|/|E| <= 1e-5, potential error <= 1e-5 of the particle's own
+magnitude (rms as floor), force error <= 1e-4 of its maximum; in double
+precision 1e-10 for all three.  Cases cover several rounds, an odd block count (a bye in every
 round), ragged last blocks and slices, one and two rows per lane, both image
-kinds, and the adjoint, which reads the same near accumulators.
+kinds, both precisions, and the adjoint, which reads the same near
+accumulators.
 """
 import numpy as np
 import pytest
@@ -100,8 +102,9 @@ def test_sym_vs_tiles(hs, monkeypatch, bc, n, T):
         assert err_e <= 1e-5
         assert err_pn <= 1e-5
         assert err_fn <= 1e-4
-    # the two single-precision kernels agree with each other at least as well
-    assert rel_own(in_s["phi_near"], in_t["phi_near"]) <= 1e-5
+    # each kernel is within 1e-5 of the double-precision path, so they are
+    # within 2e-5 of each other
+    assert rel_own(in_s["phi_near"], in_t["phi_near"]) <= 2e-5
 
 
 @pytest.mark.parametrize("bc,n", [(1, 1), (1, 2), (0, 2), (0, 64), (1, 65)])
@@ -140,3 +143,42 @@ def test_sym_adjoint(hs, monkeypatch):
     assert abs(e1 - e0) <= 1e-5 * abs(e0)
     assert rel_max(gx1, gx0) <= 1e-4
     assert rel_max(gq1, gq0, rms(gq0)) <= 1e-5
+
+
+@pytest.mark.parametrize("bc,n", [(0, 3000), (1, 3001), (0, 2), (1, 1)])
+def test_sym_f64_vs_oracle(hs, monkeypatch, bc, n):
+    # double precision: the same gates as the double tile path (1e-10)
+    announce("sym f64 vs oracle bc=%d n=%d" % (bc, n))
+    if n == 1:
+        x, q = np.array([[0.3, 0.6, 0.45]]), np.array([1.0])
+    else:
+        x, q = charges(bc, n, 211 + n)
+    ref = oracle.solve(oracle.make_plan(1.0, bc, 12, 1000, 600, 2.7), x, q)
+    plan = hs.Plan(1.0, bc, 12, 1000, 600, 2.7, precision=hs.FP64)
+    e, phi, F, inter = run(hs, plan, x, q, monkeypatch, True)
+    err_e = abs(e - ref["energy"]) / abs(ref["energy"])
+    err_pn = rel_own(inter["phi_near"], ref["phi_near"])
+    err_fn = rel_max(inter["field_near"], ref["field_near"])
+    err_F = rel_max(F, ref["forces"])
+    print("sym f64 bc=%d n=%d: dE/E %.2e dphi_near %.2e dE_near %.2e dF %.2e"
+          % (bc, n, err_e, err_pn, err_fn, err_F))
+    assert err_e <= 1e-10
+    assert err_pn <= 1e-10
+    assert err_fn <= 1e-10
+    assert err_F <= 1e-10
+
+
+@pytest.mark.parametrize("bc,n", [(0, 40001), (1, 40000)])
+def test_sym_f64_vs_tiles(hs, monkeypatch, bc, n):
+    announce("sym f64 vs tiles bc=%d n=%d" % (bc, n))
+    x, q = charges(bc, n, 17 + n)
+    plan = hs.Plan(1.0, bc, 12, 1000, 600, 2.7, precision=hs.FP64)
+    e_s, phi_s, F_s, in_s = run(hs, plan, x, q, monkeypatch, True)
+    e_t, phi_t, F_t, in_t = run(hs, plan, x, q, monkeypatch, False)
+    d_e = abs(e_s - e_t) / abs(e_t)
+    d_pn = rel_own(in_s["phi_near"], in_t["phi_near"])
+    d_fn = rel_max(in_s["field_near"], in_t["field_near"])
+    print("sym f64 vs tiles bc=%d n=%d: dE/E %.2e dphi_near %.2e dE_near %.2e" % (bc, n, d_e, d_pn, d_fn))
+    assert d_e <= 1e-11
+    assert d_pn <= 1e-11
+    assert d_fn <= 1e-11
