@@ -186,9 +186,12 @@ def serving(args):
     print("serving: open loop (%.1f s sequential)" % wall64, file=sys.stderr, flush=True)
     arr32 = np.cumsum(gaps) / (0.8 * mu32)
     _, lat32, _ = srv.run_trace(arr32, pl, xs, qs)
+    print("serving: open loop, batched at 0.8 of its capacity done", file=sys.stderr, flush=True)
     arr64 = np.cumsum(gaps) / (0.8 * mu64)
     _, lat64, _ = hsma.run_trace_sequential(arr64, pl, xs, qs)
+    print("serving: open loop, sequential at 0.8 of its capacity done", file=sys.stderr, flush=True)
     _, lat32s, _ = srv.run_trace(arr64, pl, xs, qs)      # batched at the sequential path's load
+    print("serving: open loop, batched at the sequential load done", file=sys.stderr, flush=True)
     rel = np.abs(e32 - e64) / np.abs(e64)
     pct = lambda a, q_: float(np.percentile(a, q_)) * 1e3
     rec = {

@@ -173,8 +173,10 @@ size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
  *           targets, so each ordered (target, image) pair is evaluated once.
  *   kind 1: each unordered particle pair is evaluated once and both of its
  *           directions are accumulated (the image-block sum is symmetric in
- *           the two particles).  Single precision, periodic or grounded box,
- *           block near set, N at or above a threshold (65536, or the
+ *           the two particles; for the slab, the real charges with the
+ *           periodic blocks of each charge and of its mirror).  Either
+ *           precision, every boundary condition, block near set, N at or
+ *           above a threshold (65536, or the
  *           HSMA_SYM_MIN environment variable); HSMA_SYM=0 in the environment
  *           turns it off and HSMA_SYM=1 forces it (HSMA_SYM_T = 1 or 2 fixes
  *           the rows per lane, chosen otherwise).  The particles are cut

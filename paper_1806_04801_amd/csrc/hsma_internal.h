@@ -27,7 +27,10 @@ hsma_status fail(hsma_status st, const std::string& msg);
 //   IMG_PERIODIC: r + kL,                  charge q           (periodic sum)
 //   IMG_METALLIC: (-1)^k o r + kL,         charge (-1)^|k| q  (Eq. (diel), gamma = -1)
 //   IMG_FREE    : r only (no images)
-enum { IMG_PERIODIC = 0, IMG_METALLIC = 1, IMG_FREE = 2 };
+//   IMG_SLAB    : the mirror-doubled periodic cube of the slab, taken over
+//                 the real charges only: r + kL with charge q and
+//                 (x, y, -z) + kL with charge -q (pair-once kernel only)
+enum { IMG_PERIODIC = 0, IMG_METALLIC = 1, IMG_FREE = 2, IMG_SLAB = 3 };
 
 // Single-precision record of a point (target or source), in units of the box
 // side L (so the box is [-1/2, 1/2]^3): the centred coordinate c = h0 + l with
@@ -70,7 +73,7 @@ struct SymGeom {
 // Single precision: T = 1 or 2 rows per lane, or 0 to choose the one whose
 // rounds fill the GPU better (resident waves from the occupancy of each kernel
 // variant).  Double precision (f64): one row per lane.
-SymGeom sym_geometry(int n, int T, bool f64, int ncu);
+SymGeom sym_geometry(int n, int T, bool f64, int img, int ncu);
 
 // One group of tiles of a grouped pair launch: all tiles of one pair stage of
 // one request.  Tile i of the group (0 <= i < ntb * S) is target block

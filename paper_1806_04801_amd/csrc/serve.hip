@@ -247,8 +247,8 @@ static bool admit(hsma_server_s* sv, SrvReq* r) {
     d.A = (double*)(ws + ly.off_A);
     d.surf = (double*)(ws + ly.off_surf);
     d.near_part = (double*)(ws + ly.off_near_part);
-    d.near_S = ly.g_near.S;
-    d.near_pad = ly.g_near.nt_pad;
+    d.near_S = ly.sym ? ly.g_sym.C + ly.g_sym.s : ly.g_near.S;
+    d.near_pad = ly.sym ? ly.g_sym.n_pad : ly.g_near.nt_pad;
     d.surf_part = (double*)(ws + ly.off_surf_part);
     d.surf_S = ly.g_surf.S;
     d.surf_pad = ly.g_surf.nt_pad;
@@ -390,9 +390,12 @@ static hsma_status tick(hsma_server_s* sv) {
         maxB_M = std::max(maxB_M, (r->d.M + 3) / 4);
         maxB_e = std::max(maxB_e, r->d.n_eblk);
     }
-    // tile groups: near first (the longest), then right-hand side, then surface
+    // tile groups: near first (the longest), then right-hand side, then surface;
+    // requests large enough for the pair-once near sum run it in rounds of
+    // their own instead (see below)
     for (SrvReq* r : newA) {
         const ReqDesc& d = r->d;
+        if (r->ly.sym) continue;
         if (f32) add_group(tiles, &ntiles, TILE_NEAR, d.img, r->ly.g_near, d.src32, d.src32, d.near_part, d.L);
         else add_group(tiles, &ntiles, TILE_NEAR, d.img, r->ly.g_near, d.src64, d.src64, d.near_part, d.L);
     }
@@ -423,8 +426,16 @@ static hsma_status tick(hsma_server_s* sv) {
         if (f32) hipLaunchKernelGGL(k_g_rec32, dim3(maxA_ns, nA), dim3(SWG), 0, s, dA);
     }
     HSMA_HIP(hipGetLastError());
-    // all pair tiles of the tick in one launch
+    // pair-once near sums of the large new requests (each round fills the GPU
+    // by itself), then all pair tiles of the tick in one launch
     timing_begin(0, s);
+    for (SrvReq* r : newA) {
+        if (!r->ly.sym) continue;
+        if (f32)
+            HSMA_HIP(launch_sym_f32(r->ly.sym_img, r->d.src32, r->ly.g_sym, r->d.L, r->d.near_part, s));
+        else
+            HSMA_HIP(launch_sym_f64(r->ly.sym_img, r->d.src64, r->ly.g_sym, r->d.L, r->d.near_part, s));
+    }
     HSMA_HIP(launch_group_tiles(f32, dT, (int)tiles.size(), ntiles, s));
     timing_end(0, s);
     // stage B, part 2: finalize, energy, results to host

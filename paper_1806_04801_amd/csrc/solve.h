@@ -23,9 +23,10 @@ struct Layout {
            off_real32 = 0, off_ud = 0;
     size_t off_cnt = 0, off_imgoff = 0, off_img64 = 0, off_img32 = 0;   // sphere near set
     int64_t img_max = 0;
-    // near sum with each unordered pair once (periodic or grounded box, block
-    // near set, single precision); its accumulators replace the chunk partials
+    // near sum with each unordered pair once (block near set, any boundary
+    // condition and precision); its accumulators replace the chunk partials
     bool sym = false;
+    int sym_img = 0;   // IMG_* of the pair-once kernel (IMG_SLAB for the slab)
     SymGeom g_sym;
     int n_eblk = 1;
     size_t total = 0;

@@ -47,9 +47,10 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     {
         const int mode = env_int("HSMA_SYM", -1);
         const int nmin = env_int("HSMA_SYM_MIN", 65536);
-        const bool eligible = !sphere && pl->bc != HSMA_BC_SLAB_METALLIC_Z && ly.N > 0;
+        const bool eligible = !sphere && ly.N > 0;
         ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
-        if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 0), !f32, pl->ncu);
+        ly.sym_img = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? IMG_SLAB : pl->img;
+        if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 0), !f32, ly.sym_img, pl->ncu);
     }
     const int nsurf = pl->dipole_mode == HSMA_DIPOLE_LAYERS ? 3 * pl->M : pl->M;
     ly.g_surf = pair_geometry(ly.N, nsurf, 1, pl->ncu);
@@ -345,9 +346,9 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
         CK(launch_explicit(f32, true, true, f32 ? (const void*)src32 : (const void*)src64,
                            f32 ? (const void*)img32 : (const void*)img64, g_near, pl->L, near_part, s));
     else if (ly.sym && f32)
-        CK(launch_sym_f32(pl->img, src32, ly.g_sym, pl->L, near_part, s));
+        CK(launch_sym_f32(ly.sym_img, src32, ly.g_sym, pl->L, near_part, s));
     else if (ly.sym)
-        CK(launch_sym_f64(pl->img, src64, ly.g_sym, pl->L, near_part, s));
+        CK(launch_sym_f64(ly.sym_img, src64, ly.g_sym, pl->L, near_part, s));
     else if (f32)
         CK(launch_pair_f32(pl->img, true, true, src32, src32, g_near, pl->L, near_part, s));
     else

@@ -10,6 +10,12 @@
 // directions: the potential term is the same, the field at j is the field at i
 // with the sign pattern of images_sum<..., REV>.
 //
+// For the slab (mirror-doubled periodic cube) the rows and columns are the
+// real charges and each pair carries two image blocks: the periodic block of
+// the charge and that of its mirror (x, y, -z) with the opposite charge.  The
+// mirror block is symmetric too, with x and y periodic and z reflected, so
+// its reverse field keeps the sign of the z component.
+//
 // Work layout.  Particles are cut into nb blocks of B = 64 * T * s.  The
 // block pairs (I, J), I < J, are scheduled as a round-robin tournament: in
 // each round every block takes part in exactly one pair, so no two
@@ -141,6 +147,62 @@ __device__ __forceinline__ SymItem sym_item(const SymGeom& g, int round) {
     return it;
 }
 
+// Near terms of one pair per unit charges: potential p, field f at the row,
+// and (REV) field rf at the column produced by the row.
+template <int IMG, bool REV>
+__device__ __forceinline__ void pair_terms(const Pt32& t, const Pt32& s, float& p, float (&f)[3],
+                                           float (&rf)[3]) {
+    constexpr int BI = IMG == IMG_SLAB ? IMG_PERIODIC : IMG;
+    float dx[3], dy[3], dz[3];
+    diffs_f32<BI>(t, s, 0, dx);
+    diffs_f32<BI>(t, s, 1, dy);
+    diffs_f32<BI>(t, s, 2, dz);
+    images_sum<float, BI, true, true, REV>(dx, dy, dz, p, f[0], f[1], f[2], rf);
+    if (IMG == IMG_SLAB) {
+        // mirror block: z differences t + s - kL (k = -1, 0, +1), charge -1
+        const float sl = t.l[2] + s.l[2];
+        const float mz[3] = {(t.hm[2] + s.hm[2]) + sl, (t.h0[2] + s.h0[2]) + sl,
+                             (t.hp[2] + s.hp[2]) + sl};
+        float pm, gx, gy, gz;
+        images_sum<float, IMG_PERIODIC, true, false>(dx, dy, mz, pm, gx, gy, gz);
+        p -= pm;
+        f[0] -= gx;
+        f[1] -= gy;
+        f[2] -= gz;
+        if (REV) {
+            rf[0] += gx;
+            rf[1] += gy;
+            rf[2] -= gz;
+        }
+    }
+}
+
+template <int IMG, bool REV>
+__device__ __forceinline__ void pair_terms(const double4& t, const double4& s, double L, double& p,
+                                           double (&f)[3], double (&rf)[3]) {
+    constexpr int BI = IMG == IMG_SLAB ? IMG_PERIODIC : IMG;
+    double dx[3], dy[3], dz[3];
+    diffs_f64<BI>(t.x, s.x, L, dx);
+    diffs_f64<BI>(t.y, s.y, L, dy);
+    diffs_f64<BI>(t.z, s.z, L, dz);
+    images_sum<double, BI, true, true, REV>(dx, dy, dz, p, f[0], f[1], f[2], rf);
+    if (IMG == IMG_SLAB) {
+        const double sm = t.z + s.z;
+        const double mz[3] = {sm + L, sm, sm - L};
+        double pm, gx, gy, gz;
+        images_sum<double, IMG_PERIODIC, true, false>(dx, dy, mz, pm, gx, gy, gz);
+        p -= pm;
+        f[0] -= gx;
+        f[1] -= gy;
+        f[2] -= gz;
+        if (REV) {
+            rf[0] += gx;
+            rf[1] += gy;
+            rf[2] -= gz;
+        }
+    }
+}
+
 template <int IMG, int T, bool DIAG>
 __global__ void __launch_bounds__(SW)
 k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, double* __restrict__ acc) {
@@ -206,16 +268,12 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
                     const float qj = rec.v[0].w;
 #pragma unroll
                     for (int u = 0; u < T; ++u) {
-                        float dx[3], dy[3], dz[3];
-                        diffs_f32<IMG>(tp[u], sj, 0, dx);
-                        diffs_f32<IMG>(tp[u], sj, 1, dy);
-                        diffs_f32<IMG>(tp[u], sj, 2, dz);
-                        float p0, fx0, fy0, fz0, rf[3];
-                        images_sum<float, IMG, true, true, !DIAG>(dx, dy, dz, p0, fx0, fy0, fz0, rf);
+                        float p0, f0[3], rf[3];
+                        pair_terms<IMG, !DIAG>(tp[u], sj, p0, f0, rf);
                         sp[u] = __builtin_fmaf(qj, p0, sp[u]);
-                        sx[u] = __builtin_fmaf(qj, fx0, sx[u]);
-                        sy[u] = __builtin_fmaf(qj, fy0, sy[u]);
-                        sz[u] = __builtin_fmaf(qj, fz0, sz[u]);
+                        sx[u] = __builtin_fmaf(qj, f0[0], sx[u]);
+                        sy[u] = __builtin_fmaf(qj, f0[1], sy[u]);
+                        sz[u] = __builtin_fmaf(qj, f0[2], sz[u]);
                         if (!DIAG) {
                             rp = __builtin_fmaf(qi[u], p0, rp);
                             rx = __builtin_fmaf(qi[u], rf[0], rx);
@@ -308,16 +366,12 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
             double rp = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
             if (q < nh) {
                 const double4 sj = pts[jb + q];
-                double dx[3], dy[3], dz[3];
-                diffs_f64<IMG>(t.x, sj.x, L, dx);
-                diffs_f64<IMG>(t.y, sj.y, L, dy);
-                diffs_f64<IMG>(t.z, sj.z, L, dz);
-                double p0, fx0, fy0, fz0, rf[3];
-                images_sum<double, IMG, true, true, !DIAG>(dx, dy, dz, p0, fx0, fy0, fz0, rf);
+                double p0, f0[3], rf[3];
+                pair_terms<IMG, !DIAG>(t, sj, L, p0, f0, rf);
                 ap = __builtin_fma(sj.w, p0, ap);
-                ax = __builtin_fma(sj.w, fx0, ax);
-                ay = __builtin_fma(sj.w, fy0, ay);
-                az = __builtin_fma(sj.w, fz0, az);
+                ax = __builtin_fma(sj.w, f0[0], ax);
+                ay = __builtin_fma(sj.w, f0[1], ay);
+                az = __builtin_fma(sj.w, f0[2], az);
                 if (!DIAG) {
                     rp = qi * p0;
                     rx = qi * rf[0];
@@ -353,19 +407,27 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
     }
 }
 
-// Resident one-wave work-groups per CU of a kernel variant (T = 0: double).
-static int sym_waves_per_cu(int T) {
+// Resident one-wave work-groups per CU of the round kernel of an image kind
+// (T = 0: double precision).
+template <int IMG>
+static const void* sym_round_kernel(int T) {
+    return T == 0   ? (const void*)k_sym_f64<IMG, false>
+           : T == 2 ? (const void*)k_sym_f32<IMG, 2, false>
+                    : (const void*)k_sym_f32<IMG, 1, false>;
+}
+
+static int sym_waves_per_cu(int T, int img) {
     int nblk = 0;
-    const void* k = T == 0   ? (const void*)k_sym_f64<IMG_PERIODIC, false>
-                    : T == 2 ? (const void*)k_sym_f32<IMG_PERIODIC, 2, false>
-                             : (const void*)k_sym_f32<IMG_PERIODIC, 1, false>;
+    const void* k = img == IMG_SLAB       ? sym_round_kernel<IMG_SLAB>(T)
+                    : img == IMG_METALLIC ? sym_round_kernel<IMG_METALLIC>(T)
+                                          : sym_round_kernel<IMG_PERIODIC>(T);
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, k, SW, 0);
     return (e == hipSuccess && nblk > 0) ? nblk : 8;
 }
 
 // Geometry for T rows per lane; *fill is the fraction of resident-wave slots
 // that a round's waves occupy over its batches.
-static SymGeom sym_geometry_t(int n, int T, bool f64, int ncu, double* fill) {
+static SymGeom sym_geometry_t(int n, int T, bool f64, int img, int ncu, double* fill) {
     SymGeom g;
     g.n = n;
     g.T = T;
@@ -385,7 +447,7 @@ static SymGeom sym_geometry_t(int n, int T, bool f64, int ncu, double* fill) {
     // batches of `cap` resident waves and the last batch may be part empty.
     // Pick the part count (at most 16, at least 64 columns per part) whose
     // waves fill their batches best; a larger count wins only by more than 2 %.
-    const long cap = (long)sym_waves_per_cu(f64 ? 0 : T) * ncu;
+    const long cap = (long)sym_waves_per_cu(f64 ? 0 : T, img) * ncu;
     const long w1 = (long)(g.P / 2) * g.s;
     long cmax = g.B / 64;
     if (cmax < 1) cmax = 1;
@@ -406,13 +468,13 @@ static SymGeom sym_geometry_t(int n, int T, bool f64, int ncu, double* fill) {
     return g;
 }
 
-SymGeom sym_geometry(int n, int T, bool f64, int ncu) {
+SymGeom sym_geometry(int n, int T, bool f64, int img, int ncu) {
     double f1 = 0.0, f2 = 0.0;
-    if (f64) return sym_geometry_t(n, 1, true, ncu, &f1);
-    if (T == 1 || T == 2) return sym_geometry_t(n, T, false, ncu, &f1);
+    if (f64) return sym_geometry_t(n, 1, true, img, ncu, &f1);
+    if (T == 1 || T == 2) return sym_geometry_t(n, T, false, img, ncu, &f1);
     // one row per lane (more resident waves) unless two fill the slots better
-    const SymGeom g1 = sym_geometry_t(n, 1, false, ncu, &f1);
-    const SymGeom g2 = sym_geometry_t(n, 2, false, ncu, &f2);
+    const SymGeom g1 = sym_geometry_t(n, 1, false, img, ncu, &f1);
+    const SymGeom g2 = sym_geometry_t(n, 2, false, img, ncu, &f2);
     return f2 > f1 + 0.02 ? g2 : g1;
 }
 
@@ -438,6 +500,9 @@ hipError_t launch_sym_f32(int img, const Rec32* pts, const SymGeom& g, double L,
     if (img == IMG_METALLIC)
         return g.T == 2 ? sym32<IMG_METALLIC, 2>(pts, g, invL, acc, s)
                         : sym32<IMG_METALLIC, 1>(pts, g, invL, acc, s);
+    if (img == IMG_SLAB)
+        return g.T == 2 ? sym32<IMG_SLAB, 2>(pts, g, invL, acc, s)
+                        : sym32<IMG_SLAB, 1>(pts, g, invL, acc, s);
     return hipErrorInvalidValue;
 }
 
@@ -457,6 +522,7 @@ hipError_t launch_sym_f64(int img, const double4* pts, const SymGeom& g, double 
     if (g.n <= 0 || g.nb <= 0 || g.T != 1) return hipErrorInvalidValue;
     if (img == IMG_PERIODIC) return sym64<IMG_PERIODIC>(pts, g, L, acc, s);
     if (img == IMG_METALLIC) return sym64<IMG_METALLIC>(pts, g, L, acc, s);
+    if (img == IMG_SLAB) return sym64<IMG_SLAB>(pts, g, L, acc, s);
     return hipErrorInvalidValue;
 }
 

@@ -146,3 +146,30 @@ def test_trace_replay_batched_vs_sequential(hs, plans):
     assert np.median(err / np.abs(e64)) <= 1e-5
     assert np.all(lat32 > 0) and np.all(lat64 > 0)
     assert srv.stats()["completed"] == len(reqs)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pair_once_requests_in_the_server(hs, plans, precision, monkeypatch):
+    """With the pair-once threshold lowered to 1000 particles, part of the mix
+    runs its near sum in pair-once rounds and the rest in grouped tiles:
+    results stay bitwise the same alone and in the mix, and agree with the
+    single-request path (which makes the same choice)."""
+    announce("server pair-once precision=%d" % precision)
+    monkeypatch.setenv("HSMA_SYM_MIN", "1000")
+    reqs = mix(10, 9)
+    sizes = [len(q) for _, _, _, q in reqs]
+    assert min(sizes) < 1000 <= max(sizes)
+    srv = hs.Server(memory_bytes=2 << 30, max_active=8, precision=precision)
+    order = sorted(range(len(reqs)), key=lambda i: -sizes[i])[:2] + [sizes.index(min(sizes))]
+    alone = [run_all(srv, plans, [reqs[i]])[0] for i in order]
+    both = run_all(srv, plans, reqs)
+    for i, a in zip(order, alone):
+        b = both[i]
+        assert a[0] == b[0]
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    for (bc, p, x, q), b in zip(reqs, both):
+        e, phi, F = plans[(bc, p)].energy_forces(torch.tensor(x, device="cuda"),
+                                                 torch.tensor(q, device="cuda"))
+        scale = 0.5 * float(np.sum(np.abs(q * phi.cpu().numpy())))
+        tol = 1e-12 if precision == 0 else 1e-6
+        assert abs(b[0] - e) <= tol * scale

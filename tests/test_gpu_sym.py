@@ -182,3 +182,96 @@ def test_sym_f64_vs_tiles(hs, monkeypatch, bc, n):
     assert d_e <= 1e-11
     assert d_pn <= 1e-11
     assert d_fn <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_sym_slab_vs_oracle(hs, monkeypatch, prec):
+    # the slab: real charges only, each pair with its periodic and mirror blocks;
+    # n = 2000: 32 blocks of 64 (T = 1), last block 16 rows
+    announce("sym slab vs oracle %s" % prec)
+    x, q = W.slab_charges(2000, 1.0, seed=23)
+    ref = oracle.solve(oracle.make_plan(1.0, 2, 12, 1000, 600, 2.7), x, q)
+    plan = hs.Plan(1.0, 2, 12, 1000, 600, 2.7, precision=hs.FP32_COMP if prec == "fp32" else hs.FP64)
+    e, phi, F, inter = run(hs, plan, x, q, monkeypatch, True, 1)
+    err_e = abs(e - ref["energy"]) / abs(ref["energy"])
+    err_pn = rel_own(inter["phi_near"], ref["phi_near"])
+    err_fn = rel_max(inter["field_near"], ref["field_near"])
+    err_F = rel_max(F, ref["forces"])
+    print("sym slab %s: dE/E %.2e dphi_near %.2e dE_near %.2e dF %.2e" % (prec, err_e, err_pn, err_fn, err_F))
+    tol = (1e-5, 1e-5, 1e-4) if prec == "fp32" else (1e-10, 1e-10, 1e-10)
+    assert err_e <= tol[0]
+    assert err_pn <= tol[1]
+    assert err_fn <= tol[2]
+    assert err_F <= tol[2]
+
+
+def test_sym_slab_vs_tiles(hs, monkeypatch):
+    announce("sym slab vs tiles")
+    x, q = W.slab_charges(40000, 1.0, seed=29)
+    plan = hs.Plan(1.0, 2, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
+    plan64 = hs.Plan(1.0, 2, 12, 1000, 600, 2.7, precision=hs.FP64)
+    e_s, _, _, in_s = run(hs, plan, x, q, monkeypatch, True)
+    e_t, _, _, in_t = run(hs, plan, x, q, monkeypatch, False)
+    e_d, _, _, in_d = run(hs, plan64, x, q, monkeypatch, False)
+    e_d1, _, _, in_d1 = run(hs, plan64, x, q, monkeypatch, True)
+    for name, (e, pn, fn) in {"sym": (e_s, in_s["phi_near"], in_s["field_near"]),
+                              "tiles": (e_t, in_t["phi_near"], in_t["field_near"])}.items():
+        err_e = abs(e - e_d) / abs(e_d)
+        err_pn = rel_own(pn, in_d["phi_near"])
+        err_fn = rel_max(fn, in_d["field_near"])
+        print("slab %s: dE/E %.2e dphi_near %.2e dE_near %.2e" % (name, err_e, err_pn, err_fn))
+        assert err_e <= 1e-5
+        assert err_pn <= 1e-5
+        assert err_fn <= 1e-4
+    d_pn = rel_own(in_d1["phi_near"], in_d["phi_near"])
+    d_fn = rel_max(in_d1["field_near"], in_d["field_near"])
+    print("slab f64 sym vs tiles: dE/E %.2e dphi_near %.2e dE_near %.2e" % (abs(e_d1 - e_d) / abs(e_d), d_pn, d_fn))
+    assert abs(e_d1 - e_d) <= 1e-11 * abs(e_d)
+    assert d_pn <= 1e-11
+    assert d_fn <= 1e-11
+
+
+def test_sym_slab_adjoint(hs, monkeypatch):
+    announce("sym slab adjoint")
+    x, q = W.slab_charges(3000, 1.0, seed=31)
+    plan = hs.Plan(1.0, 2, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+    qd = torch.tensor(q, dtype=torch.float64, device="cuda")
+    out = {}
+    for sym in (True, False):
+        monkeypatch.setenv("HSMA_SYM", "1" if sym else "0")
+        e, gx, gq = plan.energy_grad(xd, qd)
+        torch.cuda.synchronize()
+        out[sym] = (e, gx.cpu().numpy(), gq.cpu().numpy())
+    (e1, gx1, gq1), (e0, gx0, gq0) = out[True], out[False]
+    print("sym slab adjoint: dE %.2e dgx %.2e dgq %.2e"
+          % (abs(e1 - e0) / abs(e0), rel_max(gx1, gx0), rel_max(gq1, gq0, rms(gq0))))
+    assert abs(e1 - e0) <= 1e-5 * abs(e0)
+    assert rel_max(gx1, gx0) <= 1e-4
+    assert rel_max(gq1, gq0, rms(gq0)) <= 1e-5
+
+
+def test_near_schedule_query(hs, monkeypatch):
+    announce("near schedule query")
+    monkeypatch.delenv("HSMA_SYM", raising=False)
+    monkeypatch.delenv("HSMA_SYM_T", raising=False)
+    monkeypatch.delenv("HSMA_SYM_MIN", raising=False)
+    plan = hs.Plan(1.0, 0, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
+    small = plan.near_schedule(1000)
+    assert small["kind"] == 0 and small["launches"] == 0
+    big = plan.near_schedule(10 ** 6)
+    assert big["kind"] == 1
+    assert big["rows_per_lane"] in (1, 2)
+    assert big["block"] == 64 * big["rows_per_lane"] * big["slices"]
+    assert big["blocks"] * big["block"] >= 10 ** 6 > (big["blocks"] - 1) * big["block"]
+    assert big["launches"] == big["blocks"] + (big["blocks"] & 1)
+    assert 1 <= big["parts"] <= 16 and big["block"] // big["parts"] >= 64
+    monkeypatch.setenv("HSMA_SYM", "0")
+    assert plan.near_schedule(10 ** 6)["kind"] == 0
+    monkeypatch.setenv("HSMA_SYM", "1")
+    assert plan.near_schedule(5)["kind"] == 1
+    # the sphere near set always runs per target
+    sph = hs.Plan(1.0, 0, 12, 1000, 600, 2.7, precision=hs.FP32_COMP, near_mode=hs.NEAR_SPHERE)
+    assert sph.near_schedule(10 ** 6)["kind"] == 0
+    with pytest.raises(Exception):
+        plan.near_schedule(0)
