@@ -72,8 +72,8 @@ __device__ __forceinline__ double lane_t(double x, int src_lane) {
 // One halving step of the reduce-scatter: lane l and its partner l ^ m hold
 // the same N pairs (v[k], v[k + N]); the lane with f set keeps the upper
 // halves, the other the lower ones, and each adds the partner's copy.
-template <int N, int CTRL, typename R>
-__device__ __forceinline__ void rs_step(R (&v)[16], bool f) {
+template <int N, int CTRL, typename R, int NV>
+__device__ __forceinline__ void rs_step(R (&v)[NV], bool f) {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const R lo = v[k], hi = v[k + N];
@@ -83,25 +83,35 @@ __device__ __forceinline__ void rs_step(R (&v)[16], bool f) {
     }
 }
 
-// Sum of 16 values over the 64 lanes of the wave.  The row-local partners are
-// lane ^ 1, ^ 2 (quad permutations), ^ 7 (half-row mirror) and ^ 15 (row
-// mirror); the lane bits that pick the kept half are parities of lane & 5,
-// lane & 6, lane & 12 and lane & 8, which form the dual basis of those four
-// masks, so partners always hold the same subset.  After the four steps each
-// lane of a row holds one distinct value, summed over its row; two exchanges
-// across rows (lane ^ 16, lane ^ 32) finish the sum.  Lane l then holds value
-// rs_owner(l), and lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same one.
+// Sum of NV (16 or 8) values over the 64 lanes of the wave.  The row-local
+// partners are lane ^ 1, ^ 2 (quad permutations), ^ 7 (half-row mirror) and
+// ^ 15 (row mirror); the lane bits that pick the kept half are parities of
+// lane & 5, lane & 6, lane & 12 and lane & 8, the dual basis of those four
+// masks, so partners always hold the same subset.  With 16 values four
+// halving steps leave one distinct value per lane of a row; with 8 values
+// three steps leave each value on a lane and its row mirror, which one more
+// exchange (^ 15) sums.  Two exchanges across rows (^ 16, ^ 32) finish.  Lane
+// l then holds value rs_owner<NV>(l); lanes 0 .. NV - 1 hold distinct values.
+template <int NV>
 __device__ __forceinline__ int rs_owner(int lane) {
-    return parity(lane & 5) * 8 + parity(lane & 6) * 4 + parity(lane & 12) * 2 + ((lane >> 3) & 1);
+    return NV == 16 ? parity(lane & 5) * 8 + parity(lane & 6) * 4 + parity(lane & 12) * 2 +
+                          ((lane >> 3) & 1)
+                    : parity(lane & 5) * 4 + parity(lane & 6) * 2 + parity(lane & 12);
 }
 
-template <typename R>
-__device__ __forceinline__ R reduce_scatter16(R (&v)[16], int lane) {
-    rs_step<8, 0xB1>(v, parity(lane & 5));     // quad_perm [1,0,3,2]
-    rs_step<4, 0x4E>(v, parity(lane & 6));     // quad_perm [2,3,0,1]
-    rs_step<2, 0x141>(v, parity(lane & 12));   // row_half_mirror
-    rs_step<1, 0x140>(v, (lane >> 3) & 1);     // row_mirror
-    R e = v[0];
+template <typename R, int NV>
+__device__ __forceinline__ R reduce_scatter(R (&v)[NV], int lane) {
+    static_assert(NV == 16 || NV == 8, "16 or 8 values");
+    rs_step<NV / 2, 0xB1>(v, parity(lane & 5));    // quad_perm [1,0,3,2]
+    rs_step<NV / 4, 0x4E>(v, parity(lane & 6));    // quad_perm [2,3,0,1]
+    rs_step<NV / 8, 0x141>(v, parity(lane & 12));  // row_half_mirror
+    R e;
+    if (NV == 16) {
+        rs_step<1, 0x140>(v, (lane >> 3) & 1);     // row_mirror
+        e = v[0];
+    } else {
+        e = v[0] + dpp_t<0x140>(v[0]);             // row_mirror
+    }
     e += lane_t(e, lane ^ 16);
     e += lane_t(e, lane ^ 32);
     return e;
@@ -203,9 +213,10 @@ __device__ __forceinline__ void pair_terms(const double4& t, const double4& s, d
     }
 }
 
-template <int IMG, int T, bool DIAG>
+template <int IMG, int T, bool DIAG, int QC>
 __global__ void __launch_bounds__(SW)
 k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, double* __restrict__ acc) {
+    constexpr int NV = 4 * QC;   // reverse values per lane and group
     const int lane = threadIdx.x;
     const SymItem it = sym_item<DIAG>(g, round);
     if (!it.ok) return;
@@ -240,7 +251,7 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
 
     const int c0 = min(J * g.B + (int)((long)part * g.B / g.C), g.n);
     const int c1 = min(J * g.B + (int)((long)(part + 1) * g.B / g.C), g.n);
-    const int kown = rs_owner(lane);
+    const int kown = rs_owner<NV>(lane);
     const int kcol = kown >> 2, kcomp = kown & 3;
     const double oscale = kcomp == 0 ? invL : invL2;
     for (int g0 = c0; g0 < c1; g0 += 8) {
@@ -248,19 +259,19 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
 #pragma unroll
         for (int u = 0; u < T; ++u) sp[u] = sx[u] = sy[u] = sz[u] = 0.0f;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int jb = g0 + 4 * h;
-            const int nh = min(4, c1 - jb);
+        for (int h = 0; h < 8 / QC; ++h) {
+            const int jb = g0 + QC * h;
+            const int nh = min(QC, c1 - jb);
             if (nh <= 0) break;
             double old = 0.0;
             double* dst = nullptr;
-            if (!DIAG && lane < 16 && kcol < nh) {
+            if (!DIAG && lane < NV && kcol < nh) {
                 dst = rev + (size_t)kcomp * g.n_pad + jb + kcol;
                 old = *dst;
             }
-            float rv[16];
+            float rv[NV];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < QC; ++q) {
                 float rp = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f;
                 if (q < nh) {
                     const Rec32 rec = pts[jb + q];
@@ -288,7 +299,7 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
                 rv[4 * q + 3] = rz;
             }
             if (!DIAG) {
-                const float e = reduce_scatter16(rv, lane);
+                const float e = reduce_scatter(rv, lane);
                 if (dst != nullptr) *dst = old + (double)e * oscale;
             }
         }
@@ -327,9 +338,10 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
 // Double precision: one row per lane, positions in physical units (centred
 // double4 x, y, z, q), plain FMA accumulation as in the double tile kernel;
 // reverse terms are reduced in double.
-template <int IMG, bool DIAG>
+template <int IMG, bool DIAG, int QC>
 __global__ void __launch_bounds__(SW)
 k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, double* __restrict__ acc) {
+    constexpr int NV = 4 * QC;   // reverse values per lane and group
     const int lane = threadIdx.x;
     const SymItem it = sym_item<DIAG>(g, round);
     if (!it.ok) return;
@@ -350,19 +362,19 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
 
     const int c0 = min(it.J * g.B + (int)((long)it.part * g.B / g.C), g.n);
     const int c1 = min(it.J * g.B + (int)((long)(it.part + 1) * g.B / g.C), g.n);
-    const int kown = rs_owner(lane);
+    const int kown = rs_owner<NV>(lane);
     const int kcol = kown >> 2, kcomp = kown & 3;
-    for (int jb = c0; jb < c1; jb += 4) {
-        const int nh = min(4, c1 - jb);
+    for (int jb = c0; jb < c1; jb += QC) {
+        const int nh = min(QC, c1 - jb);
         double old = 0.0;
         double* dst = nullptr;
-        if (!DIAG && lane < 16 && kcol < nh) {
+        if (!DIAG && lane < NV && kcol < nh) {
             dst = rev + (size_t)kcomp * g.n_pad + jb + kcol;
             old = *dst;
         }
-        double rv[16];
+        double rv[NV];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QC; ++q) {
             double rp = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
             if (q < nh) {
                 const double4 sj = pts[jb + q];
@@ -385,7 +397,7 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
             rv[4 * q + 3] = rz;
         }
         if (!DIAG) {
-            const double e = reduce_scatter16(rv, lane);
+            const double e = reduce_scatter(rv, lane);
             if (dst != nullptr) *dst = old + e;
         }
     }
@@ -409,11 +421,23 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
 
 // Resident one-wave work-groups per CU of the round kernel of an image kind
 // (T = 0: double precision).
+// Columns per reverse group (reduce-scatter of 4 x QC values): HSMA_SYM_Q = 2
+// or 4 (default 4).
+static int sym_q() {
+    const char* v = getenv("HSMA_SYM_Q");
+    return (v != nullptr && atoi(v) == 2) ? 2 : 4;
+}
+
+template <int IMG, int QC>
+static const void* sym_round_kernel_q(int T) {
+    return T == 0   ? (const void*)k_sym_f64<IMG, false, QC>
+           : T == 2 ? (const void*)k_sym_f32<IMG, 2, false, QC>
+                    : (const void*)k_sym_f32<IMG, 1, false, QC>;
+}
+
 template <int IMG>
 static const void* sym_round_kernel(int T) {
-    return T == 0   ? (const void*)k_sym_f64<IMG, false>
-           : T == 2 ? (const void*)k_sym_f32<IMG, 2, false>
-                    : (const void*)k_sym_f32<IMG, 1, false>;
+    return sym_q() == 2 ? sym_round_kernel_q<IMG, 2>(T) : sym_round_kernel_q<IMG, 4>(T);
 }
 
 static int sym_waves_per_cu(int T, int img) {
@@ -478,51 +502,58 @@ SymGeom sym_geometry(int n, int T, bool f64, int img, int ncu) {
     return f2 > f1 + 0.02 ? g2 : g1;
 }
 
-template <int IMG, int T>
+template <int IMG, int T, int QC>
 static hipError_t sym32(const Rec32* pts, const SymGeom& g, double invL, double* acc, hipStream_t s) {
     auto grid8 = [](long w) { return (unsigned)((w + 7) / 8 * 8); };
-    hipLaunchKernelGGL((k_sym_f32<IMG, T, true>), dim3(grid8((long)g.nb * g.s * g.C)), dim3(SW), 0,
-                       s, pts, g, -1, invL, acc);
+    hipLaunchKernelGGL((k_sym_f32<IMG, T, true, QC>), dim3(grid8((long)g.nb * g.s * g.C)), dim3(SW),
+                       0, s, pts, g, -1, invL, acc);
     const unsigned grid = grid8((long)(g.P / 2) * g.s * g.C);
     for (int r = 0; r < g.P - 1; ++r)
-        hipLaunchKernelGGL((k_sym_f32<IMG, T, false>), dim3(grid), dim3(SW), 0, s, pts, g, r, invL,
-                           acc);
+        hipLaunchKernelGGL((k_sym_f32<IMG, T, false, QC>), dim3(grid), dim3(SW), 0, s, pts, g, r,
+                           invL, acc);
     return hipGetLastError();
+}
+
+template <int IMG>
+static hipError_t sym32_t(const Rec32* pts, const SymGeom& g, double invL, double* acc,
+                          hipStream_t s) {
+    if (sym_q() == 2)
+        return g.T == 2 ? sym32<IMG, 2, 2>(pts, g, invL, acc, s) : sym32<IMG, 1, 2>(pts, g, invL, acc, s);
+    return g.T == 2 ? sym32<IMG, 2, 4>(pts, g, invL, acc, s) : sym32<IMG, 1, 4>(pts, g, invL, acc, s);
 }
 
 hipError_t launch_sym_f32(int img, const Rec32* pts, const SymGeom& g, double L, double* acc,
                           hipStream_t s) {
     if (g.n <= 0 || g.nb <= 0) return hipErrorInvalidValue;
     const double invL = 1.0 / L;
-    if (img == IMG_PERIODIC)
-        return g.T == 2 ? sym32<IMG_PERIODIC, 2>(pts, g, invL, acc, s)
-                        : sym32<IMG_PERIODIC, 1>(pts, g, invL, acc, s);
-    if (img == IMG_METALLIC)
-        return g.T == 2 ? sym32<IMG_METALLIC, 2>(pts, g, invL, acc, s)
-                        : sym32<IMG_METALLIC, 1>(pts, g, invL, acc, s);
-    if (img == IMG_SLAB)
-        return g.T == 2 ? sym32<IMG_SLAB, 2>(pts, g, invL, acc, s)
-                        : sym32<IMG_SLAB, 1>(pts, g, invL, acc, s);
+    if (img == IMG_PERIODIC) return sym32_t<IMG_PERIODIC>(pts, g, invL, acc, s);
+    if (img == IMG_METALLIC) return sym32_t<IMG_METALLIC>(pts, g, invL, acc, s);
+    if (img == IMG_SLAB) return sym32_t<IMG_SLAB>(pts, g, invL, acc, s);
     return hipErrorInvalidValue;
 }
 
-template <int IMG>
+template <int IMG, int QC>
 static hipError_t sym64(const double4* pts, const SymGeom& g, double L, double* acc, hipStream_t s) {
     auto grid8 = [](long w) { return (unsigned)((w + 7) / 8 * 8); };
-    hipLaunchKernelGGL((k_sym_f64<IMG, true>), dim3(grid8((long)g.nb * g.s * g.C)), dim3(SW), 0, s,
-                       pts, g, -1, L, acc);
+    hipLaunchKernelGGL((k_sym_f64<IMG, true, QC>), dim3(grid8((long)g.nb * g.s * g.C)), dim3(SW), 0,
+                       s, pts, g, -1, L, acc);
     const unsigned grid = grid8((long)(g.P / 2) * g.s * g.C);
     for (int r = 0; r < g.P - 1; ++r)
-        hipLaunchKernelGGL((k_sym_f64<IMG, false>), dim3(grid), dim3(SW), 0, s, pts, g, r, L, acc);
+        hipLaunchKernelGGL((k_sym_f64<IMG, false, QC>), dim3(grid), dim3(SW), 0, s, pts, g, r, L, acc);
     return hipGetLastError();
+}
+
+template <int IMG>
+static hipError_t sym64_t(const double4* pts, const SymGeom& g, double L, double* acc, hipStream_t s) {
+    return sym_q() == 2 ? sym64<IMG, 2>(pts, g, L, acc, s) : sym64<IMG, 4>(pts, g, L, acc, s);
 }
 
 hipError_t launch_sym_f64(int img, const double4* pts, const SymGeom& g, double L, double* acc,
                           hipStream_t s) {
     if (g.n <= 0 || g.nb <= 0 || g.T != 1) return hipErrorInvalidValue;
-    if (img == IMG_PERIODIC) return sym64<IMG_PERIODIC>(pts, g, L, acc, s);
-    if (img == IMG_METALLIC) return sym64<IMG_METALLIC>(pts, g, L, acc, s);
-    if (img == IMG_SLAB) return sym64<IMG_SLAB>(pts, g, L, acc, s);
+    if (img == IMG_PERIODIC) return sym64_t<IMG_PERIODIC>(pts, g, L, acc, s);
+    if (img == IMG_METALLIC) return sym64_t<IMG_METALLIC>(pts, g, L, acc, s);
+    if (img == IMG_SLAB) return sym64_t<IMG_SLAB>(pts, g, L, acc, s);
     return hipErrorInvalidValue;
 }
 
