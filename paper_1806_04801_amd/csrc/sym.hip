@@ -421,11 +421,13 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
 
 // Resident one-wave work-groups per CU of the round kernel of an image kind
 // (T = 0: double precision).
-// Columns per reverse group (reduce-scatter of 4 x QC values): HSMA_SYM_Q = 2
-// or 4 (default 4).
-static int sym_q() {
+// Columns per reverse group (reduce-scatter of 4 x QC values): 2 in single
+// precision (fewer registers, more resident waves), 4 in double (measured);
+// HSMA_SYM_Q = 2 or 4 overrides.
+static int sym_q(bool f64) {
     const char* v = getenv("HSMA_SYM_Q");
-    return (v != nullptr && atoi(v) == 2) ? 2 : 4;
+    if (v != nullptr && (atoi(v) == 2 || atoi(v) == 4)) return atoi(v);
+    return f64 ? 4 : 2;
 }
 
 template <int IMG, int QC>
@@ -437,7 +439,7 @@ static const void* sym_round_kernel_q(int T) {
 
 template <int IMG>
 static const void* sym_round_kernel(int T) {
-    return sym_q() == 2 ? sym_round_kernel_q<IMG, 2>(T) : sym_round_kernel_q<IMG, 4>(T);
+    return sym_q(T == 0) == 2 ? sym_round_kernel_q<IMG, 2>(T) : sym_round_kernel_q<IMG, 4>(T);
 }
 
 static int sym_waves_per_cu(int T, int img) {
@@ -517,7 +519,7 @@ static hipError_t sym32(const Rec32* pts, const SymGeom& g, double invL, double*
 template <int IMG>
 static hipError_t sym32_t(const Rec32* pts, const SymGeom& g, double invL, double* acc,
                           hipStream_t s) {
-    if (sym_q() == 2)
+    if (sym_q(false) == 2)
         return g.T == 2 ? sym32<IMG, 2, 2>(pts, g, invL, acc, s) : sym32<IMG, 1, 2>(pts, g, invL, acc, s);
     return g.T == 2 ? sym32<IMG, 2, 4>(pts, g, invL, acc, s) : sym32<IMG, 1, 4>(pts, g, invL, acc, s);
 }
@@ -545,7 +547,7 @@ static hipError_t sym64(const double4* pts, const SymGeom& g, double L, double* 
 
 template <int IMG>
 static hipError_t sym64_t(const double4* pts, const SymGeom& g, double L, double* acc, hipStream_t s) {
-    return sym_q() == 2 ? sym64<IMG, 2>(pts, g, L, acc, s) : sym64<IMG, 4>(pts, g, L, acc, s);
+    return sym_q(true) == 2 ? sym64<IMG, 2>(pts, g, L, acc, s) : sym64<IMG, 4>(pts, g, L, acc, s);
 }
 
 hipError_t launch_sym_f64(int img, const double4* pts, const SymGeom& g, double L, double* acc,
