@@ -176,10 +176,12 @@ size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
  *           the two particles; for the slab, the real charges with the
  *           periodic blocks of each charge and of its mirror).  Either
  *           precision, every boundary condition, block near set, N at or
- *           above a threshold (65536, or the
- *           HSMA_SYM_MIN environment variable); HSMA_SYM=0 in the environment
- *           turns it off and HSMA_SYM=1 forces it (HSMA_SYM_T = 1 or 2 fixes
- *           the rows per lane, chosen otherwise).  The particles are cut
+ *           above a threshold (12288 in single and 6144 in double precision,
+ *           the same for requests of the batched server; the environment
+ *           variable HSMA_SYM_MIN overrides it);
+ *           HSMA_SYM=0 in the environment turns it off and HSMA_SYM=1 forces
+ *           it (HSMA_SYM_T = 1 or 2 fixes the rows per lane, chosen
+ *           otherwise).  The particles are cut
  *           into `blocks` blocks of `block`; block pairs run in blocks - 1
  *           (+1 if odd) round-robin rounds after one diagonal launch; a block
  *           pair is split into `slices` row slices of 64 * rows_per_lane rows

@@ -41,12 +41,14 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     const int ns_pairs = sphere ? (int)std::min<int64_t>(ly.img_max, INT32_MAX) : ly.ns;
     ly.g_rhs = pair_geometry(pl->nchk, ns_pairs, tpl_rhs, pl->ncu);
     ly.g_near = pair_geometry(ly.N, ns_pairs, tpl_near, pl->ncu);
-    // Pair-once near sum: worth it once a round holds enough waves to fill the
-    // GPU.  HSMA_SYM=0 turns it off, HSMA_SYM=1 forces it (any N), otherwise
-    // it is used from HSMA_SYM_MIN particles on.
+    // Pair-once near sum: faster than the tiles from about 8e3 particles in
+    // single and 5e3 in double precision (measured; in the batched server too,
+    // where a request's rounds run between the tick's grouped launches).
+    // HSMA_SYM=0 turns it off, HSMA_SYM=1 forces it (any N); HSMA_SYM_MIN
+    // overrides the threshold.
     {
         const int mode = env_int("HSMA_SYM", -1);
-        const int nmin = env_int("HSMA_SYM_MIN", 65536);
+        const int nmin = env_int("HSMA_SYM_MIN", f32 ? 12288 : 6144);
         const bool eligible = !sphere && ly.N > 0;
         ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
         ly.sym_img = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? IMG_SLAB : pl->img;

@@ -36,6 +36,9 @@
 // reverse from row slice sigma, each 4 components x n_pad doubles (potential,
 // field x, y, z), physical units.  The finalize stage sums the C + s copies in
 // that order.
+#include <algorithm>
+#include <cstdlib>
+
 #include "hsma_internal.h"
 #include "pair_math.h"
 
@@ -451,15 +454,26 @@ static int sym_waves_per_cu(int T, int img) {
     return (e == hipSuccess && nblk > 0) ? nblk : 8;
 }
 
+// Target number of rounds: n / 1024 within [8, 128] (measured best from 4e3
+// to 1.3e5 particles in both precisions: fewer, larger rounds while a round
+// cannot fill the GPU anyway); HSMA_SYM_ROUNDS overrides.
+static long sym_rounds(int n) {
+    const char* v = getenv("HSMA_SYM_ROUNDS");
+    const long r = v != nullptr ? atol(v) : 0;
+    if (r >= 2) return r;
+    return std::min(128L, std::max(8L, (long)n / 1024));
+}
+
 // Geometry for T rows per lane; *fill is the fraction of resident-wave slots
 // that a round's waves occupy over its batches.
 static SymGeom sym_geometry_t(int n, int T, bool f64, int img, int ncu, double* fill) {
     SymGeom g;
     g.n = n;
     g.T = T;
-    // about 128 rounds (blocks of n / 128), at most 64 row slices
+    // about R rounds (blocks of n / R), at most 64 row slices
     const long rows = (long)SW * T;
-    long s = (n + rows * 128 - 1) / (rows * 128);
+    const long R = sym_rounds(n);
+    long s = (n + rows * R - 1) / (rows * R);
     if (s < 1) s = 1;
     if (s > 64) s = 64;
     // keep the accumulators (C + s copies of 32 bytes per particle) under 8 GB
