@@ -59,6 +59,7 @@ PairGeom pair_geometry(int nt, int ns, int tpl, int ncu);
 
 // Geometry of the near sum that visits every unordered particle pair once:
 // blocks of B = 64 * T * s particles, nb blocks (P = nb rounded up to even),
+// each block pair split into s row slices and C column parts (one wave each),
 // accumulators padded to n_pad = nb * B per component.
 struct SymGeom {
     int n = 0;       // particles
@@ -141,9 +142,11 @@ hipError_t launch_surface_f64(const double4* tgt, const double* surf, const Pair
                               double* out, hipStream_t s);
 hipError_t launch_group_tiles(bool f32, const TileGroup* groups, int ngroups, int ntiles,
                               hipStream_t s);
-// Near sum at the particles, each unordered pair once (periodic or grounded
-// images), single precision on Rec32 records.  acc: (g.C + g.s) copies of 4 x g.n_pad doubles,
-// written completely for the first g.n entries of each component.
+// Near sum at the particles, each unordered pair once (img: IMG_PERIODIC,
+// IMG_METALLIC or IMG_SLAB, the last over the n real charges of the slab),
+// single precision on Rec32 records.  acc: (g.C + g.s) copies of 4 x g.n_pad
+// doubles (forward copies, then reverse copies), written completely for the
+// first g.n entries of each component; the caller sums the copies.
 hipError_t launch_sym_f32(int img, const Rec32* pts, const SymGeom& g, double L, double* acc,
                           hipStream_t s);
 // The same in double precision on centred double4 (x, y, z, q) records.
