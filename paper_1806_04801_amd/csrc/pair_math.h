@@ -7,10 +7,13 @@
 
 namespace hsma {
 
-// 1/sqrt(x) in double: hardware estimate (about 2^-24 relative) refined by one
-// third-order Newton step, y <- y + y e (1/2 + 3/8 e), e = 1 - x y^2.
+// 1/sqrt(x) in double: the single-precision hardware estimate of x rounded to
+// float (about 2^-23 relative; valid for the distances here, far inside the
+// float range) refined by one third-order Newton step,
+// y <- y + y e (1/2 + 3/8 e), e = 1 - x y^2, which leaves an error of order
+// e^3 below double rounding.
 __device__ __forceinline__ double rsqrt_f64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
     double t = x * y;
     double e = __builtin_fma(-t, y, 1.0);
     double c = __builtin_fma(e, 0.375, 0.5);
