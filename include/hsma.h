@@ -180,8 +180,9 @@ size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
  *           the same for requests of the batched server; the environment
  *           variable HSMA_SYM_MIN overrides it);
  *           HSMA_SYM=0 in the environment turns it off and HSMA_SYM=1 forces
- *           it (HSMA_SYM_T = 1 or 2 fixes the rows per lane, chosen
- *           otherwise).  The particles are cut
+ *           it; for tuning, HSMA_SYM_T (1 or 2 rows per lane), HSMA_SYM_Q (2
+ *           or 4 columns per reverse group) and HSMA_SYM_ROUNDS (target round
+ *           count) override the choices the library makes.  The particles are cut
  *           into `blocks` blocks of `block`; block pairs run in blocks - 1
  *           (+1 if odd) round-robin rounds after one diagonal launch; a block
  *           pair is split into `slices` row slices of 64 * rows_per_lane rows
