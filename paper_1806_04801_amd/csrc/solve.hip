@@ -307,14 +307,27 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
             CK(launch_make_rec32(img64, n_img, pl->L, img32, s));
         }
     }
-    // fork: the right-hand-side chain goes to the auxiliary stream
+    // fork: the right-hand-side chain goes to the auxiliary stream; the
+    // caller's stream waits for it again before the surface stage, and on
+    // every early return (a failed launch), so that no work of this call on
+    // the auxiliary stream can outlive the call's use of the workspace
     hipStream_t s1 = s;
     AuxStream* aux = nullptr;
+    struct Join {
+        AuxStream* a = nullptr;
+        hipStream_t s = nullptr;
+        ~Join() {
+            if (a != nullptr && hipEventRecord(a->join, a->s) == hipSuccess)
+                (void)hipStreamWaitEvent(s, a->join, 0);
+        }
+    } join_on_exit;
     if (overlap_enabled()) {
         CK(aux_stream(pl->device, &aux));
         CK(hipEventRecord(aux->fork, s));
         CK(hipStreamWaitEvent(aux->s, aux->fork, 0));
         s1 = aux->s;
+        join_on_exit.a = aux;
+        join_on_exit.s = s;
     }
     // right-hand side at the monitoring points (and twins)
     timing_begin(1, s1);
@@ -357,7 +370,10 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
         CK(launch_pair_f64(pl->img, true, true, src64, src64, g_near, pl->L, near_part, s));
     timing_end(0, s);
     // join, then the surface images at the particles
-    if (aux != nullptr) CK(hipStreamWaitEvent(s, aux->join, 0));
+    if (aux != nullptr) {
+        CK(hipStreamWaitEvent(s, aux->join, 0));
+        join_on_exit.a = nullptr;   // joined
+    }
     PairGeom g_surf = ly.g_surf;
     timing_begin(2, s);
     if (direct) {
