@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=256)
     ap.add_argument("--requests", type=int, default=1024, help="serving: trace length")
+    ap.add_argument("--refine", type=float, default=5e-3,
+                    help="serving: recompute in double precision the requests whose FP32 energy "
+                         "is below this fraction of 1/2 sum |q phi| (0: never)")
     ap.add_argument("--grad", action="store_true", help="time energy + exact gradient (adjoint)")
     ap.add_argument("--near", default="block", choices=["block", "sphere"],
                     help="near set: 27-image block or every image inside the auxiliary sphere")
@@ -171,13 +174,16 @@ def serving(args):
     for r in trace:
         nchk = (2 if r["bc"] == 0 else 1) * 10 * r["p"] ** 2
         pairs += 27.0 * r["n"] * r["n"] + 27.0 * nchk * r["n"]
-    srv = hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP)
+    srv = hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
+                      refine_below=args.refine)
     zero = np.zeros(n)
     # warm-up of both paths on a few requests
     srv.run_trace(zero[:8], pl[:8], xs[:8], qs[:8])
     hsma.run_trace_sequential(zero[:8], pl[:8], xs[:8], qs[:8])
     print("serving: closed loop, batched fp32", file=sys.stderr, flush=True)
+    refined0 = srv.stats()["refined"]
     e32, lat32c, wall32 = srv.run_trace(zero, pl, xs, qs)
+    refined = srv.stats()["refined"] - refined0
     print("serving: closed loop, sequential fp64 (%.1f s batched)" % wall32, file=sys.stderr, flush=True)
     e64, lat64c, wall64 = hsma.run_trace_sequential(zero, pl, xs, qs)
     mu32, mu64 = n / wall32, n / wall64
@@ -201,7 +207,8 @@ def serving(args):
         "config": {
             "workload": "serving", "requests": n,
             "desc": "N log-uniform [1e3,1e5] even, bc periodic/grounded 1/2, p in {12,16,20}, "
-                    "K=M=10p^2, R=2.7L; FP32-comp batched server vs FP64 per-request",
+                    "K=M=10p^2, R=2.7L; FP32-comp batched server (ill-conditioned energies "
+                    "refined in FP64) vs FP64 per-request",
             "pair_interactions": pairs,
             "batched_fp32": {"solves_per_s": mu32, "pairs_per_s": pairs / wall32,
                              "p50_ms_at_0.8mu": pct(lat32, 50), "p99_ms_at_0.8mu": pct(lat32, 99),
@@ -209,6 +216,8 @@ def serving(args):
             "sequential_fp64": {"solves_per_s": mu64, "pairs_per_s": pairs / wall64,
                                 "p50_ms_at_0.8mu": pct(lat64, 50), "p99_ms_at_0.8mu": pct(lat64, 99)},
             "speedup_solves_per_s": mu32 / mu64,
+            "refine_below": args.refine,
+            "refined_in_fp64": {"requests": int(refined), "fraction": refined / n},
             "rel_energy_err_fp32_vs_fp64": {"p50": float(np.median(rel)),
                                             "p99": float(np.percentile(rel, 99)),
                                             "max": float(rel.max()),

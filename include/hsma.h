@@ -135,7 +135,10 @@ typedef struct {
     double* field_out;   /* N x 3 far fields */
 } hsma_intermediates;
 
-/* Status text and the calling thread's last error message. */
+/* Status text and the calling thread's last error message.  hsma_version()
+   is the version of this interface; it changes whenever a declaration or a
+   struct layout in this header changes (2: the near-schedule query and the
+   server's double-precision refinement). */
 const char* hsma_status_string(int status);
 const char* hsma_last_error(void);
 int hsma_version(void);
@@ -268,6 +271,15 @@ typedef struct {
     size_t memory_bytes;   /* device arena for admitted requests (>= 1 MiB) */
     int max_active;        /* request slots (>= 1) */
     int precision;         /* hsma_precision of the pair sums */
+    double refine_below;   /* HSMA_FP32_COMP only (0 = off): a request whose
+                              energy E comes out with |E| below refine_below
+                              times 1/2 sum |q_i phi_i| is recomputed in double
+                              precision before it completes.  The single-
+                              precision error is a small fraction (~1e-8) of
+                              that sum, so it is a large relative error only
+                              when E is a small difference of large terms;
+                              5e-3 keeps every energy of the synthetic serving
+                              mix within 1e-5 of the double-precision one. */
 } hsma_server_desc;
 
 typedef struct {
@@ -275,6 +287,7 @@ typedef struct {
     int active, pending;
     int64_t ticks, tiles;
     size_t arena_bytes, arena_used, arena_peak;
+    int64_t refined;       /* requests recomputed in double precision */
 } hsma_server_stats_t;
 
 hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out);

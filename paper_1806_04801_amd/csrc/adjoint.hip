@@ -114,7 +114,7 @@ __global__ void k_grad_finalize(const double* __restrict__ near, int Sn, int npa
 
 hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStream_t s,
                      double* dEdx, double* dEdq) {
-    const bool f32 = pl->precision == HSMA_FP32_COMP;
+    const bool f32 = ly.f32;
     const double4* src64 = (const double4*)(ws + ly.off_src64);
     const Rec32* src32 = f32 ? (const Rec32*)(ws + ly.off_src32) : nullptr;
     double* u_part = (double*)(ws + ly.off_u_part);

@@ -119,7 +119,9 @@ __global__ void __launch_bounds__(SWG) k_g_energy(const ReqDesc* __restrict__ D)
 }
 
 // ---------------------------------------------------------------- server
-enum { ST_PENDING = 0, ST_STAGE_A = 1, ST_STAGE_B = 2, ST_COPYING = 3, ST_DONE = 4 };
+enum { ST_PENDING = 0, ST_STAGE_A = 1, ST_STAGE_B = 2, ST_COPYING = 3, ST_DONE = 4,
+       ST_REFINE = 5,         // waiting for arena memory for its double-precision solve
+       ST_REFINE_COPY = 6 };  // double-precision solve and result copies enqueued
 
 struct SrvReq {
     int64_t id = 0;
@@ -157,6 +159,7 @@ struct hsma_server_s {
     int64_t next_id = 1;
     std::deque<hsma::SrvReq*> pending;
     std::vector<hsma::SrvReq*> active;
+    std::deque<hsma::SrvReq*> refine;   // active requests waiting in ST_REFINE
     std::unordered_map<int64_t, hsma::SrvReq*> all;
     // per-tick tables: ring of device buffers with their events
     static constexpr int RING = 3;
@@ -193,6 +196,24 @@ static size_t req_device_bytes(const hsma_plan_s* pl, int N, int precision, Layo
 
 static size_t req_host_bytes(int N) { return sizeof(double) * (4 + 4 * (size_t)N); }
 
+// A request's arena block: x (N x 3), q, phi, F (N x 3), then the workspace.
+struct ReqBlock {
+    double *x, *q, *phi, *F;
+    char* ws;
+};
+
+static ReqBlock carve(char* base, int N) {
+    const size_t a = 256;
+    auto up = [&](size_t v) { return (v + a - 1) & ~(a - 1); };
+    ReqBlock b;
+    b.x = (double*)base;
+    b.q = (double*)(base + up(sizeof(double) * 3 * N));
+    b.phi = (double*)((char*)b.q + up(sizeof(double) * N));
+    b.F = (double*)((char*)b.phi + up(sizeof(double) * N));
+    b.ws = (char*)b.F + up(sizeof(double) * 3 * N);
+    return b;
+}
+
 // Try to admit one request: arena space for x, q, phi, F and workspace.
 static bool admit(hsma_server_s* sv, SrvReq* r) {
     Layout ly;
@@ -207,15 +228,13 @@ static bool admit(hsma_server_s* sv, SrvReq* r) {
     r->host_off = hoff;
     r->ly = ly;
     r->h_out = (double*)(sv->host_base + hoff);
-    char* base = sv->arena_base + off;
-    const size_t a = 256;
-    auto up = [&](size_t v) { return (v + a - 1) & ~(a - 1); };
     const int N = r->N;
-    double* dx = (double*)base;
-    double* dq = (double*)(base + up(sizeof(double) * 3 * N));
-    double* dphi = (double*)((char*)dq + up(sizeof(double) * N));
-    double* dF = (double*)((char*)dphi + up(sizeof(double) * N));
-    char* ws = (char*)dF + up(sizeof(double) * 3 * N);
+    const ReqBlock blk = carve(sv->arena_base + off, N);
+    double* dx = blk.x;
+    double* dq = blk.q;
+    double* dphi = blk.phi;
+    double* dF = blk.F;
+    char* ws = blk.ws;
     const hsma_plan_s* pl = r->plan;
     ReqDesc& d = r->d;
     d.N = N;
@@ -326,27 +345,92 @@ static hsma_status upload(hsma_server_s* sv, const std::vector<ReqDesc>& da,
     return HSMA_OK;
 }
 
+// Whether a finished single-precision result is recomputed in double
+// precision: its energy is below refine_below * 1/2 sum |q_i phi_i|, and the
+// double-precision block fits the arena.
+static bool wants_refine(const hsma_server_s* sv, const SrvReq* r) {
+    if (sv->desc.precision != HSMA_FP32_COMP || !(sv->desc.refine_below > 0.0) ||
+        r->status != HSMA_OK)
+        return false;
+    Layout ly64;
+    if (req_device_bytes(r->plan, r->N, HSMA_FP64, &ly64) > sv->arena->cap()) return false;
+    const double* q = r->ext_q ? r->ext_q : r->hq.data();
+    const double* phi = r->h_out + 4;
+    double scale = 0.0;
+    for (int i = 0; i < r->N; ++i) scale += std::fabs(q[i] * phi[i]);
+    return std::fabs(r->energy) < sv->desc.refine_below * 0.5 * scale;
+}
+
 static void retire(hsma_server_s* sv) {
     std::vector<SrvReq*> keep;
     for (SrvReq* r : sv->active) {
-        if (r->state == ST_COPYING && hipEventQuery(r->ev) == hipSuccess) {
-            r->t_done = now_s();
-            const Result* res = (const Result*)r->h_out;
-            r->energy = res->energy;
-            if (res->status & 1) r->status = HSMA_E_INVALID;
-            else if (res->status & 2) r->status = HSMA_E_OUT_OF_BOX;
-            else if (res->status & 4) r->status = HSMA_E_NOT_NEUTRAL;
-            r->state = ST_DONE;
-            sv->evpool.push_back(r->ev);
-            r->ev = nullptr;
-            sv->arena->release(r->off);
-            sv->stats.completed += 1;
-            // host staging stays until the caller reads the result
-        } else {
+        const bool copied = (r->state == ST_COPYING || r->state == ST_REFINE_COPY) &&
+                            hipEventQuery(r->ev) == hipSuccess;
+        if (!copied) {
             keep.push_back(r);
+            continue;
         }
+        const Result* res = (const Result*)r->h_out;
+        r->energy = res->energy;
+        if (res->status & 1) r->status = HSMA_E_INVALID;
+        else if (res->status & 2) r->status = HSMA_E_OUT_OF_BOX;
+        else if (res->status & 4) r->status = HSMA_E_NOT_NEUTRAL;
+        sv->evpool.push_back(r->ev);
+        r->ev = nullptr;
+        sv->arena->release(r->off);
+        if (r->state == ST_COPYING && wants_refine(sv, r)) {
+            // the block is free again: the double-precision solve takes a new
+            // one (inputs copied from the host again), so a request waiting
+            // for memory holds none
+            r->state = ST_REFINE;
+            sv->refine.push_back(r);
+            keep.push_back(r);
+            continue;
+        }
+        if (r->state == ST_REFINE_COPY) sv->stats.refined += 1;
+        r->t_done = now_s();
+        r->state = ST_DONE;
+        sv->stats.completed += 1;
+        // host staging stays until the caller reads the result
     }
     sv->active.swap(keep);
+}
+
+// Enqueue the double-precision solves of queued refinements that fit the
+// arena, in queue order; false when the head must wait for memory.
+static hsma_status start_refinements(hsma_server_s* sv, bool* blocked) {
+    *blocked = false;
+    hipStream_t s = sv->stream;
+    while (!sv->refine.empty()) {
+        SrvReq* r = sv->refine.front();
+        Layout ly64;
+        const size_t bytes = req_device_bytes(r->plan, r->N, HSMA_FP64, &ly64);
+        size_t off = 0;
+        if (!sv->arena->alloc(bytes, &off)) {
+            *blocked = true;
+            return HSMA_OK;
+        }
+        sv->refine.pop_front();
+        r->off = off;
+        const int N = r->N;
+        const ReqBlock blk = carve(sv->arena_base + off, N);
+        const double* hx = r->ext_x ? r->ext_x : r->hx.data();
+        const double* hq = r->ext_q ? r->ext_q : r->hq.data();
+        HSMA_HIP(hipMemcpyAsync(blk.x, hx, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+        HSMA_HIP(hipMemcpyAsync(blk.q, hq, sizeof(double) * N, hipMemcpyHostToDevice, s));
+        hsma_status st = forward(r->plan, ly64, blk.x, blk.q, blk.ws, s, blk.phi, blk.F, nullptr);
+        if (st != HSMA_OK) return st;
+        HSMA_HIP(hipMemcpyAsync(r->h_out, blk.ws + ly64.off_result, sizeof(Result),
+                                hipMemcpyDeviceToHost, s));
+        HSMA_HIP(hipMemcpyAsync(r->h_out + 4, blk.phi, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        HSMA_HIP(hipMemcpyAsync(r->h_out + 4 + N, blk.F, sizeof(double) * 3 * N,
+                                hipMemcpyDeviceToHost, s));
+        r->ev = srv_event(sv);
+        if (r->ev == nullptr) return fail(HSMA_E_DEVICE, "event creation failed");
+        HSMA_HIP(hipEventRecord(r->ev, s));
+        r->state = ST_REFINE_COPY;
+    }
+    return HSMA_OK;
 }
 
 static hsma_status tick(hsma_server_s* sv) {
@@ -359,9 +443,19 @@ static hsma_status tick(hsma_server_s* sv) {
         sv->inflight.pop_front();
         retire(sv);
     }
+    // double-precision refinements first; while one waits for memory no new
+    // request is admitted, so the memory that finishing requests free goes to it
+    bool refine_blocked = false;
+    const size_t refine_queued = sv->refine.size();
+    {
+        hsma_status st = start_refinements(sv, &refine_blocked);
+        if (st != HSMA_OK) return st;
+    }
+    const bool refine_started = sv->refine.size() < refine_queued;
     // admission
     std::vector<SrvReq*> newA;
-    while (!sv->pending.empty() && (int)sv->active.size() < sv->desc.max_active) {
+    while (!refine_blocked && !sv->pending.empty() &&
+           (int)sv->active.size() < sv->desc.max_active) {
         SrvReq* r = sv->pending.front();
         if (!admit(sv, r)) break;
         sv->pending.pop_front();
@@ -372,7 +466,17 @@ static hsma_status tick(hsma_server_s* sv) {
     std::vector<SrvReq*> stB;
     for (SrvReq* r : sv->active)
         if (r->state == ST_STAGE_B) stB.push_back(r);
-    if (newA.empty() && stB.empty()) return HSMA_OK;
+    if (newA.empty() && stB.empty()) {
+        if (refine_started) {
+            // the refinements are this tick's work: track them like a tick
+            hipEvent_t te = srv_event(sv);
+            if (te == nullptr) return fail(HSMA_E_DEVICE, "event creation failed");
+            HSMA_HIP(hipEventRecord(te, sv->stream));
+            sv->inflight.push_back(te);
+            sv->stats.ticks += 1;
+        }
+        return HSMA_OK;
+    }
     const bool f32 = sv->desc.precision == HSMA_FP32_COMP;
     std::vector<ReqDesc> da, db;
     std::vector<TileGroup> tiles;
@@ -478,6 +582,8 @@ hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out) {
         return fail(HSMA_E_INVALID, "server needs >= 1 MiB of memory and >= 1 slot");
     if (desc->precision != HSMA_FP64 && desc->precision != HSMA_FP32_COMP)
         return fail(HSMA_E_INVALID, "unknown precision");
+    if (!(desc->refine_below >= 0.0) || !std::isfinite(desc->refine_below))
+        return fail(HSMA_E_INVALID, "refine_below must be finite and >= 0");
     hsma_server_s* sv = new (std::nothrow) hsma_server_s();
     if (sv == nullptr) return fail(HSMA_E_NOMEM, "host allocation failed");
     sv->desc = *desc;
@@ -589,7 +695,7 @@ hsma_status hsma_server_wait(hsma_server sv, int64_t id) {
         }
         hsma_status st = tick(sv);
         if (st != HSMA_OK) return st;
-        if (it->second->state == ST_COPYING) {
+        if (it->second->state == ST_COPYING || it->second->state == ST_REFINE_COPY) {
             HSMA_HIP(hipEventSynchronize(it->second->ev));
             retire(sv);
         }

@@ -14,6 +14,7 @@ struct Result {
 };
 
 struct Layout {
+    bool f32 = false;   // single-precision pair sums (records and partials sized for them)
     int N = 0;     // real particles
     int ns = 0;    // sources (2N for the slab: real + mirror)
     PairGeom g_rhs, g_near, g_surf, g_u, g_G;

@@ -29,6 +29,7 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.ns = (pl->bc == HSMA_BC_SLAB_METALLIC_Z) ? 2 * (int)N : (int)N;
     const int prec = precision_override >= 0 ? precision_override : pl->precision;
     const bool f32 = prec == HSMA_FP32_COMP;
+    ly.f32 = f32;
     const bool sphere = pl->near_mode == HSMA_NEAR_SPHERE;
     // targets per lane of the near tiles: the image-block kernels run best
     // with one, the explicit-image tiles with two (measured)
@@ -260,7 +261,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
                     char* ws, hipStream_t s, double* phi, double* forces,
                     const hsma_intermediates* dbg) {
     const int N = ly.N;
-    const bool f32 = pl->precision == HSMA_FP32_COMP;
+    const bool f32 = ly.f32;
     double4* src64 = (double4*)(ws + ly.off_src64);
     Rec32* src32 = f32 ? (Rec32*)(ws + ly.off_src32) : nullptr;
     double* rhs_part = (double*)(ws + ly.off_rhs_part);

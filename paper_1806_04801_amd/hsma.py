@@ -59,7 +59,7 @@ class Intermediates(ctypes.Structure):
 
 class ServerDesc(ctypes.Structure):
     _fields_ = [("memory_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("refine_below", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
@@ -67,7 +67,7 @@ class ServerStats(ctypes.Structure):
                 ("rejected", ctypes.c_int64), ("active", ctypes.c_int), ("pending", ctypes.c_int),
                 ("ticks", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
-                ("arena_peak", ctypes.c_size_t)]
+                ("arena_peak", ctypes.c_size_t), ("refined", ctypes.c_int64)]
 
 
 class NearSchedule(ctypes.Structure):
@@ -283,10 +283,10 @@ class Plan:
 class Server:
     """Continuous-batching server of energy/force requests (see hsma.h)."""
 
-    def __init__(self, memory_bytes=8 << 30, max_active=64, precision=FP32_COMP):
+    def __init__(self, memory_bytes=8 << 30, max_active=64, precision=FP32_COMP, refine_below=0.0):
         lib = load()
         d = ServerDesc(memory_bytes=int(memory_bytes), max_active=int(max_active),
-                       precision=int(precision))
+                       precision=int(precision), refine_below=float(refine_below))
         h = ctypes.c_void_p()
         _check(lib.hsma_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

@@ -38,7 +38,7 @@ def test_status_strings_without_gpu():
     lib = hsma.load()
     assert lib.hsma_status_string(0) == b"ok"
     assert lib.hsma_status_string(-2) == b"system not neutral"
-    assert lib.hsma_version() == 1
+    assert lib.hsma_version() == 2
 
 
 def test_plan_argument_validation_without_gpu():

@@ -173,3 +173,43 @@ def test_pair_once_requests_in_the_server(hs, plans, precision, monkeypatch):
         scale = 0.5 * float(np.sum(np.abs(q * phi.cpu().numpy())))
         tol = 1e-12 if precision == 0 else 1e-6
         assert abs(b[0] - e) <= tol * scale
+
+
+def test_refinement_in_double_precision(hs, plans):
+    """refine_below: a single-precision result whose energy is below that
+    fraction of 1/2 sum |q phi| is recomputed in double precision before it
+    completes.  A threshold above every request's ratio refines all of them,
+    and each then equals the double-precision single-request path bitwise
+    (the refinement is that path); with 0 nothing is refined; a realistic
+    threshold refines some and keeps the rest within the single-precision
+    bound."""
+    announce("server refinement")
+    reqs = mix(8, 11)
+    singles = []
+    for bc, p, x, q in reqs:
+        e, phi, F = plans[(bc, p)].energy_forces(torch.tensor(x, device="cuda"),
+                                                 torch.tensor(q, device="cuda"))
+        singles.append((e, phi.cpu().numpy(), F.cpu().numpy()))
+    srv = hs.Server(memory_bytes=2 << 30, max_active=8, precision=hs.FP32_COMP, refine_below=1e9)
+    out = run_all(srv, plans, reqs)
+    assert srv.stats()["refined"] == len(reqs) and srv.stats()["completed"] == len(reqs)
+    for (e, phi, F), r in zip(singles, out):
+        assert r[0] == e
+        assert np.array_equal(r[1], phi) and np.array_equal(r[2], F)
+    srv0 = hs.Server(memory_bytes=2 << 30, max_active=8, precision=hs.FP32_COMP, refine_below=0.0)
+    out0 = run_all(srv0, plans, reqs)
+    assert srv0.stats()["refined"] == 0
+    srv1 = hs.Server(memory_bytes=2 << 30, max_active=8, precision=hs.FP32_COMP, refine_below=5e-3)
+    out1 = run_all(srv1, plans, reqs)
+    n_ref = 0
+    for (bc, p, x, q), (e, phi, F), a0, a1 in zip(reqs, singles, out0, out1):
+        scale = 0.5 * float(np.sum(np.abs(q * phi)))
+        if abs(a0[0]) < 5e-3 * scale:          # ill-conditioned: refined
+            n_ref += 1
+            assert a1[0] == e
+        else:
+            assert a1[0] == a0[0]              # untouched single-precision result
+            assert abs(a1[0] - e) <= 1e-6 * scale
+    assert srv1.stats()["refined"] == n_ref
+    with pytest.raises(hs.HsmaError):
+        hs.Server(memory_bytes=2 << 30, max_active=8, precision=hs.FP32_COMP, refine_below=-1.0)
