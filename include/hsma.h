@@ -278,8 +278,9 @@ typedef struct {
                               precision error is a small fraction (~1e-8) of
                               that sum, so it is a large relative error only
                               when E is a small difference of large terms;
-                              5e-3 keeps every energy of the synthetic serving
-                              mix within 1e-5 of the double-precision one. */
+                              1e-2 kept every energy of a 4096-request
+                              synthetic serving mix within 1e-5 of the double-
+                              precision one (9 % of the requests refined). */
 } hsma_server_desc;
 
 typedef struct {
