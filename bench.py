@@ -91,11 +91,17 @@ NEAR_SOURCES = {"tiles": ("pairs.hip", "pair_math.h"), "pair-once": ("sym.hip", 
 
 
 def kernel_source_hash(kind="tiles"):
-    """Hash of the sources that define the near kernel of that kind."""
+    """Hash of the code (line comments and blank lines removed) of the sources
+    that define the near kernel of that kind."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in NEAR_SOURCES[kind]:
-        h.update(open(os.path.join(ROOT, "paper_1806_04801_amd", "csrc", name), "rb").read())
+        text = open(os.path.join(ROOT, "paper_1806_04801_amd", "csrc", name)).read()
+        for line in text.splitlines():
+            code = re.sub(r"//.*", "", line).rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

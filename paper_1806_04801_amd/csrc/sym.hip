@@ -17,7 +17,7 @@
 // its reverse field keeps the sign of the z component.
 //
 // Work layout.  Particles are cut into nb blocks of B = 64 * T * s.  The
-// block pairs (I, J), I < J, are scheduled as a round-robin tournament: in
+// block pairs (I, J), I != J, are scheduled as a round-robin tournament: in
 // each round every block takes part in exactly one pair, so no two
 // work-groups of a round touch the same particle's accumulators and the
 // rounds accumulate in place, in a fixed order, without atomics.  A pair is
@@ -36,6 +36,10 @@
 // reverse from row slice sigma, each 4 components x n_pad doubles (potential,
 // field x, y, z), physical units.  The finalize stage sums the C + s copies in
 // that order.
+//
+// Two precisions: k_sym_f32 on Rec32 records (hi/lo coordinates in units of
+// L) with 8-column plain partials folded by two-sum, k_sym_f64 on centred
+// double4 records with plain FMA accumulation.
 #include <algorithm>
 #include <cstdlib>
 

@@ -70,8 +70,12 @@ def test_bench_traffic_needs_matching_kernel_source(tmp_path, monkeypatch):
     (prof / "near_pair_once_f32_v_pmc.md").write_text(
         "- hbm_bytes_per_launch: 5.0\n- kernel_source_sha256_16: %s   (x)\n" % h_tiles)
     assert bench.profiled_traffic("v", "f32", "pair-once") is None
-    # an edit to the shared arithmetic invalidates both
+    # a comment does not change the code; an edit to the shared arithmetic
+    # invalidates both
     with open(tmp_path / "paper_1806_04801_amd" / "csrc" / "pair_math.h", "a") as f:
-        f.write("// edit\n")
+        f.write("// a comment\n")
+    assert bench.profiled_traffic("w", "f32") == 123.5
+    with open(tmp_path / "paper_1806_04801_amd" / "csrc" / "pair_math.h", "a") as f:
+        f.write("static int edit_marker;\n")
     assert bench.profiled_traffic("w", "f32") is None
     assert bench.profiled_traffic("w", "f32", "pair-once") is None
