@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=256)
     ap.add_argument("--requests", type=int, default=1024, help="serving: trace length")
-    ap.add_argument("--refine", type=float, default=1e-2,
+    ap.add_argument("--refine", type=float, default=3e-3,
                     help="serving: recompute in double precision the requests whose FP32 energy "
                          "is below this fraction of 1/2 sum |q phi| (0: never)")
     ap.add_argument("--grad", action="store_true", help="time energy + exact gradient (adjoint)")

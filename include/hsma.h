@@ -275,12 +275,12 @@ typedef struct {
                               energy E comes out with |E| below refine_below
                               times 1/2 sum |q_i phi_i| is recomputed in double
                               precision before it completes.  The single-
-                              precision error is a small fraction (~1e-8) of
+                              precision error is a small fraction (~4e-9) of
                               that sum, so it is a large relative error only
                               when E is a small difference of large terms;
-                              1e-2 kept every energy of a 4096-request
+                              3e-3 kept every energy of a 4096-request
                               synthetic serving mix within 1e-5 of the double-
-                              precision one (9 % of the requests refined). */
+                              precision one (2 % of the requests refined). */
 } hsma_server_desc;
 
 typedef struct {

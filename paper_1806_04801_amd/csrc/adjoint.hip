@@ -81,8 +81,9 @@ __device__ __forceinline__ void chunk_sum4(const double* __restrict__ part, int 
 __global__ void k_grad_finalize(const double* __restrict__ near, int Sn, int npad,
                                 const double* __restrict__ surfp, int Ss, int spad,
                                 const double* __restrict__ Gp, int Sg, int gpad,
-                                const double4* __restrict__ src, int N, int slab,
-                                double* __restrict__ dEdx, double* __restrict__ dEdq) {
+                                const double4* __restrict__ src, int N, int slab, NearFix fix,
+                                const double* __restrict__ qnet, double* __restrict__ dEdx,
+                                double* __restrict__ dEdq) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double vn[4], vo[4], vg[4];
@@ -99,6 +100,8 @@ __global__ void k_grad_finalize(const double* __restrict__ near, int Sn, int npa
         vg[3] += vm[3];
     }
     const double q = src[i].w;
+    vn[0] += q * fix.own;   // as in the forward finalize stage
+    if (fix.qc != 0.0) vn[0] += *qnet * fix.qc;
     dEdq[i] = vn[0] + 0.5 * vo[0] - 0.5 * vg[0];
     // grad G = -E_G
     for (int a = 0; a < 3; ++a)
@@ -145,7 +148,8 @@ hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStrea
                        ly.sym ? ly.g_sym.n_pad : ly.g_near.nt_pad,
                        (const double*)(ws + ly.off_surf_part), ly.g_surf.S, ly.g_surf.nt_pad,
                        G_part, ly.g_G.S, ly.g_G.nt_pad, src64, ly.N,
-                       pl->bc == HSMA_BC_SLAB_METALLIC_Z ? 1 : 0, dEdx, dEdq);
+                       pl->bc == HSMA_BC_SLAB_METALLIC_Z ? 1 : 0, near_fix(pl, f32),
+                       &((const Result*)(ws + ly.off_result))->qnet, dEdx, dEdq);
     CK(hipGetLastError());
     return HSMA_OK;
 }

@@ -32,6 +32,23 @@ hsma_status fail(hsma_status st, const std::string& msg);
 //                 (x, y, -z) + kL with charge -q (pair-once kernel only)
 enum { IMG_PERIODIC = 0, IMG_METALLIC = 1, IMG_FREE = 2, IMG_SLAB = 3 };
 
+// Potential of the 26 images k != 0 of a unit charge at the origin in the
+// periodic 3x3x3 block of unit boxes: 6 + 12 / sqrt(2) + 8 / sqrt(3).  The
+// block near-sum kernels leave a particle's own periodic images out and the
+// finalize stages add q_i * OWN_IMAGES_PERIODIC / L in double.
+constexpr double OWN_IMAGES_PERIODIC = 19.1040835277555764088833;
+
+// The same potential split over the nine columns (k_x, k_y) of the block
+// (k_z = -1, 0, 1), rounded to float: the central column (k_x = k_y = 0) 2,
+// the four edge columns 1 + sqrt(2), the four corner columns
+// 1 / sqrt(2) + 2 / sqrt(3).  The single-precision near sum subtracts them
+// per column (images_sum, SHIFT); OWN_COLS_F32 is their sum, exact in double.
+constexpr float OWN_COL_CENTRE = 2.0f;
+constexpr float OWN_COL_EDGE = 2.41421356237309504880f;
+constexpr float OWN_COL_CORNER = 1.86180731956579905342f;
+constexpr double OWN_COLS_F32 =
+    (double)OWN_COL_CENTRE + 4.0 * (double)OWN_COL_EDGE + 4.0 * (double)OWN_COL_CORNER;
+
 // Single-precision record of a point (target or source), in units of the box
 // side L (so the box is [-1/2, 1/2]^3): the centred coordinate c = h0 + l with
 // h0 a multiple of 2^-24 and |l| <= 2^-25, so that h0 - 1/2 and h0 + 1/2 are

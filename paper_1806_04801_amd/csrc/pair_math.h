@@ -57,7 +57,26 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 // and keeps it on the reflected ones (difference t + s - kL), so
 // rf_x = sum_a sigma_a dx_a X_a with sigma = -1 for k = 0 of a grounded axis
 // and sigma = -1 for every k of a periodic axis.
-template <typename R, int IMG, bool FIELD, bool SELF, bool REV = false>
+//
+// OWN (periodic block only): a zero central distance marks the source as the
+// target itself.  Its 26 images then lie at the lattice vectors k != 0, a
+// potential of OWN_IMAGES_PERIODIC / L per unit charge that the caller adds
+// exactly in double, so the pair's potential sum is returned as zero (its
+// field is zero by symmetry).  In single precision this keeps the rounding of
+// a sum of ~19 / L, the same for every particle and so not cancelling in the
+// energy of a neutral system, out of the result.  Distinct particles at the
+// same position are invalid input.
+//
+// SHIFT (single precision, periodic block): as each column (a, b) of the
+// image cube starts, the column's value for a unit charge at the target
+// itself (OWN_COL_*) is subtracted from that column's first term, off the
+// running sum, so the running potential stays of order 1 / L instead of
+// growing to ~19 / L.  Its rounding, which dominates the single-precision
+// error of a neutral system's energy, shrinks about tenfold.  The pair's
+// potential comes back lowered by OWN_COLS_F32 / L per unit charge, which the
+// finalize stage restores exactly.
+template <typename R, int IMG, bool FIELD, bool SELF, bool REV = false, bool OWN = false,
+          bool SHIFT = false>
 __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], const R (&dz)[3],
                                            R& pot, R& fx, R& fy, R& fz, R* rf = nullptr) {
     constexpr int lo = (IMG == IMG_FREE) ? 1 : 0;
@@ -66,6 +85,8 @@ __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], c
 #pragma unroll
     for (int a = lo; a < hi; ++a) sx[a] = dx[a] * dx[a];
     R S[3][3], Z[3];
+    R r2c = R(1);
+    constexpr bool SH = SHIFT && sizeof(R) == sizeof(float) && IMG == IMG_PERIODIC;
     pot = R(0);
 #pragma unroll
     for (int a = lo; a < hi; ++a) {
@@ -75,11 +96,18 @@ __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], c
 #pragma unroll
             for (int c = lo; c < hi; ++c) {
                 const R r2 = fma_t(dz[c], dz[c], sxy);
+                if (a == 1 && b == 1 && c == 1) r2c = r2;
                 R y = rsq_t(r2);
                 if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > R(0)) ? y : R(0);
                 const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
                 const R ys = neg ? -y : y;
-                pot = (a == lo && b == lo && c == lo) ? ys : pot + ys;
+                if (SH && c == lo) {
+                    const R cab = (a == 1 && b == 1) ? R(OWN_COL_CENTRE)
+                                  : (a == 1 || b == 1) ? R(OWN_COL_EDGE) : R(OWN_COL_CORNER);
+                    pot = (a == lo && b == lo) ? ys - cab : pot + (ys - cab);
+                } else {
+                    pot = (a == lo && b == lo && c == lo) ? ys : pot + ys;
+                }
                 if (FIELD) {
                     const R y2 = y * y;
                     S[a][b] = (c == lo) ? y2 * ys : fma_t(y2, ys, S[a][b]);
@@ -88,6 +116,7 @@ __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], c
             }
         }
     }
+    if (OWN && IMG == IMG_PERIODIC) pot = (r2c > R(0)) ? pot : R(0);
     if (FIELD) {
         R X[3], Y[3];
 #pragma unroll

@@ -16,7 +16,11 @@
 // differences (k = -1, 0, +1) and their squares, so an image costs one add
 // for r^2, one rsqrt, and the potential/field updates.  Per-chunk results go to
 // a partial buffer that a second kernel sums in a fixed order, so results do
-// not depend on scheduling.
+// not depend on scheduling.  In the near sum (SELF) a particle's pairing with
+// itself leaves out the central image and, in the periodic block, the images
+// of its own charge, whose constant potential the finalize stage adds; in
+// single precision the periodic pair potentials are also shifted by a
+// constant that the finalize stage restores (images_sum, SHIFT).
 #include "hsma_internal.h"
 #include "pair_math.h"
 #include "stages.h"
@@ -49,7 +53,7 @@ __device__ __forceinline__ void tile_pair_f64(int tb, int c, const double4* __re
             diffs_f64<IMG>(ty[u], s.y, L, dy);
             diffs_f64<IMG>(tz[u], s.z, L, dz);
             double pot, fx, fy, fz;
-            images_sum<double, IMG, FIELD, SELF>(dx, dy, dz, pot, fx, fy, fz);
+            images_sum<double, IMG, FIELD, SELF, false, SELF>(dx, dy, dz, pot, fx, fy, fz);
             ap[u] = __builtin_fma(s.w, pot, ap[u]);
             if (FIELD) {
                 ax[u] = __builtin_fma(s.w, fx, ax[u]);
@@ -116,7 +120,7 @@ __device__ __forceinline__ void tile_pair_f32(int tb, int c, const Rec32* __rest
                 diffs_f32<IMG>(tp[u], s0, 0, dx);
                 diffs_f32<IMG>(tp[u], s0, 1, dy);
                 diffs_f32<IMG>(tp[u], s0, 2, dz);
-                images_sum<float, IMG, FIELD, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
+                images_sum<float, IMG, FIELD, SELF, false, SELF, SELF>(dx, dy, dz, p0, fx0, fy0, fz0);
                 sp[u] = __builtin_fmaf(q0, p0, sp[u]);
                 if (FIELD) {
                     sx[u] = __builtin_fmaf(q0, fx0, sx[u]);

@@ -56,6 +56,7 @@ struct ReqDesc {
     double* surf;
     double* near_part;
     int near_S, near_pad;
+    NearFix fix;   // own-image and shift terms of the near potential
     double* surf_part;
     int surf_S, surf_pad;
     double* eblk;
@@ -72,8 +73,14 @@ __global__ void k_g_zero(const ReqDesc* __restrict__ D) {
         d.res->energy = 0.0;
         d.res->qsum = 0.0;
         d.res->qabs = 0.0;
+        d.res->qnet = 0.0;
         d.res->status = 0;
     }
+}
+
+__global__ void __launch_bounds__(SWG) k_g_net(const ReqDesc* __restrict__ D) {
+    const ReqDesc& d = D[blockIdx.y];
+    if (d.fix.qc != 0.0) net_charge_body(d.src64, d.N, &d.res->qnet);   // uniform over the block
 }
 
 __global__ void __launch_bounds__(SWG) k_g_prep(const ReqDesc* __restrict__ D) {
@@ -110,7 +117,8 @@ __global__ void __launch_bounds__(SWG) k_g_finalize(const ReqDesc* __restrict__ 
     const ReqDesc& d = D[blockIdx.y];
     if ((int)blockIdx.x >= d.n_eblk) return;   // uniform over the block
     finalize_body(blockIdx.x, d.near_part, d.near_S, d.near_pad, d.surf_part, d.surf_S, d.surf_pad,
-                  d.src64, d.N, d.phi, d.forces, nullptr, nullptr, nullptr, nullptr, d.eblk);
+                  d.src64, d.N, d.fix, &d.res->qnet, d.phi, d.forces, nullptr, nullptr, nullptr,
+                  nullptr, d.eblk);
 }
 
 __global__ void __launch_bounds__(SWG) k_g_energy(const ReqDesc* __restrict__ D) {
@@ -135,7 +143,7 @@ struct SrvReq {
     size_t off = 0, host_off = 0;
     Layout ly;
     ReqDesc d{};
-    double* h_out = nullptr;         // pinned: Result (as doubles), phi, forces
+    double* h_out = nullptr;         // pinned: Result (RES_D doubles), phi, forces
     hipEvent_t ev = nullptr;
     hsma_status status = HSMA_OK;
     double energy = 0.0;
@@ -194,7 +202,9 @@ static size_t req_device_bytes(const hsma_plan_s* pl, int N, int precision, Layo
     return up(sizeof(double) * 3 * N) * 2 + up(sizeof(double) * N) * 2 + ly->total;
 }
 
-static size_t req_host_bytes(int N) { return sizeof(double) * (4 + 4 * (size_t)N); }
+// Host output of a request: the Result (padded to whole doubles), phi, forces.
+constexpr size_t RES_D = (sizeof(Result) + sizeof(double) - 1) / sizeof(double);
+static size_t req_host_bytes(int N) { return sizeof(double) * (RES_D + 4 * (size_t)N); }
 
 // A request's arena block: x (N x 3), q, phi, F (N x 3), then the workspace.
 struct ReqBlock {
@@ -268,6 +278,7 @@ static bool admit(hsma_server_s* sv, SrvReq* r) {
     d.near_part = (double*)(ws + ly.off_near_part);
     d.near_S = ly.sym ? ly.g_sym.C + ly.g_sym.s : ly.g_near.S;
     d.near_pad = ly.sym ? ly.g_sym.n_pad : ly.g_near.nt_pad;
+    d.fix = near_fix(pl, sv->desc.precision == HSMA_FP32_COMP);
     d.surf_part = (double*)(ws + ly.off_surf_part);
     d.surf_S = ly.g_surf.S;
     d.surf_pad = ly.g_surf.nt_pad;
@@ -355,7 +366,7 @@ static bool wants_refine(const hsma_server_s* sv, const SrvReq* r) {
     Layout ly64;
     if (req_device_bytes(r->plan, r->N, HSMA_FP64, &ly64) > sv->arena->cap()) return false;
     const double* q = r->ext_q ? r->ext_q : r->hq.data();
-    const double* phi = r->h_out + 4;
+    const double* phi = r->h_out + RES_D;
     double scale = 0.0;
     for (int i = 0; i < r->N; ++i) scale += std::fabs(q[i] * phi[i]);
     return std::fabs(r->energy) < sv->desc.refine_below * 0.5 * scale;
@@ -422,8 +433,8 @@ static hsma_status start_refinements(hsma_server_s* sv, bool* blocked) {
         if (st != HSMA_OK) return st;
         HSMA_HIP(hipMemcpyAsync(r->h_out, blk.ws + ly64.off_result, sizeof(Result),
                                 hipMemcpyDeviceToHost, s));
-        HSMA_HIP(hipMemcpyAsync(r->h_out + 4, blk.phi, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-        HSMA_HIP(hipMemcpyAsync(r->h_out + 4 + N, blk.F, sizeof(double) * 3 * N,
+        HSMA_HIP(hipMemcpyAsync(r->h_out + RES_D, blk.phi, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        HSMA_HIP(hipMemcpyAsync(r->h_out + RES_D + N, blk.F, sizeof(double) * 3 * N,
                                 hipMemcpyDeviceToHost, s));
         r->ev = srv_event(sv);
         if (r->ev == nullptr) return fail(HSMA_E_DEVICE, "event creation failed");
@@ -527,6 +538,7 @@ static hsma_status tick(hsma_server_s* sv) {
     if (nA) {
         hipLaunchKernelGGL(k_g_zero, dim3(nA), dim3(64), 0, s, dA);
         hipLaunchKernelGGL(k_g_prep, dim3(maxA_blk, nA), dim3(SWG), 0, s, dA);
+        hipLaunchKernelGGL(k_g_net, dim3(1, nA), dim3(SWG), 0, s, dA);
         if (f32) hipLaunchKernelGGL(k_g_rec32, dim3(maxA_ns, nA), dim3(SWG), 0, s, dA);
     }
     HSMA_HIP(hipGetLastError());
@@ -549,9 +561,9 @@ static hsma_status tick(hsma_server_s* sv) {
         HSMA_HIP(hipGetLastError());
         for (SrvReq* r : stB) {
             HSMA_HIP(hipMemcpyAsync(r->h_out, r->d.res, sizeof(Result), hipMemcpyDeviceToHost, s));
-            HSMA_HIP(hipMemcpyAsync(r->h_out + 4, r->d.phi, sizeof(double) * r->N,
+            HSMA_HIP(hipMemcpyAsync(r->h_out + RES_D, r->d.phi, sizeof(double) * r->N,
                                     hipMemcpyDeviceToHost, s));
-            HSMA_HIP(hipMemcpyAsync(r->h_out + 4 + r->N, r->d.forces, sizeof(double) * 3 * r->N,
+            HSMA_HIP(hipMemcpyAsync(r->h_out + RES_D + r->N, r->d.forces, sizeof(double) * 3 * r->N,
                                     hipMemcpyDeviceToHost, s));
             r->ev = srv_event(sv);
             HSMA_HIP(hipEventRecord(r->ev, s));
@@ -718,8 +730,8 @@ hsma_status hsma_server_result(hsma_server sv, int64_t id, int* done, double* en
     }
     *done = 1;
     if (energy) *energy = r->energy;
-    if (phi) std::memcpy(phi, r->h_out + 4, sizeof(double) * r->N);
-    if (forces) std::memcpy(forces, r->h_out + 4 + r->N, sizeof(double) * 3 * r->N);
+    if (phi) std::memcpy(phi, r->h_out + RES_D, sizeof(double) * r->N);
+    if (forces) std::memcpy(forces, r->h_out + RES_D + r->N, sizeof(double) * 3 * r->N);
     if (latency_s) *latency_s = r->t_done - r->t_submit;
     const hsma_status st = r->status;
     sv->host_arena->release(r->host_off);

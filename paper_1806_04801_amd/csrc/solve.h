@@ -9,6 +9,7 @@ struct Result {
     double energy;
     double qsum;
     double qabs;
+    double qnet;  // net charge, summed before the finalize stage when NearFix::qc != 0
     int status;   // bit 0 non-finite input, bit 1 outside the walls, bit 2 not neutral
     int pad;
 };
@@ -32,6 +33,18 @@ struct Layout {
     int n_eblk = 1;
     size_t total = 0;
 };
+
+// What the finalize stages add to the near potential of particle i:
+// q_i * own + Q * qc, Q the net charge (Result::qnet).  With the block near
+// set of the periodic cube and of the slab (its doubled cube), own restores
+// the particle's own periodic images, which the near-sum kernels leave out,
+// less the per-pair shift of the single-precision kernels (OWN_COLS_F32 / L,
+// images_sum SHIFT); qc restores that shift for the other charges (periodic
+// cube; in the slab the mirror charges cancel it).  Both are 0 otherwise.
+struct NearFix {
+    double own = 0.0, qc = 0.0;
+};
+NearFix near_fix(const hsma_plan_s* pl, bool f32);
 
 Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_override = 0,
                    int precision_override = -1);

@@ -22,6 +22,15 @@ static int env_int(const char* name, int dflt) {
     return atoi(v);
 }
 
+NearFix near_fix(const hsma_plan_s* pl, bool f32) {
+    NearFix f;
+    if (pl->near_mode != HSMA_NEAR_BLOCK || pl->img != IMG_PERIODIC) return f;
+    const double shift = f32 ? OWN_COLS_F32 : 0.0;
+    f.own = (OWN_IMAGES_PERIODIC - shift) / pl->L;
+    if (pl->bc == HSMA_BC_PERIODIC) f.qc = shift / pl->L;
+    return f;
+}
+
 Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_override,
                    int precision_override) {
     Layout ly;
@@ -108,6 +117,7 @@ __global__ void k_zero_result(Result* r) {
         r->energy = 0.0;
         r->qsum = 0.0;
         r->qabs = 0.0;
+        r->qnet = 0.0;
         r->status = 0;
     }
 }
@@ -145,11 +155,17 @@ __global__ void __launch_bounds__(WG) k_map_layers(const double* __restrict__ Wq
 
 __global__ void __launch_bounds__(WG)
 k_finalize(const double* __restrict__ near, int Sn, int npad, const double* __restrict__ surfp,
-           int Ss, int spad, const double4* __restrict__ src, int N, double* __restrict__ phi,
-           double* __restrict__ forces, double* __restrict__ dbg_pn, double* __restrict__ dbg_fn,
-           double* __restrict__ dbg_po, double* __restrict__ dbg_fo, double* __restrict__ eblk) {
-    finalize_body(blockIdx.x, near, Sn, npad, surfp, Ss, spad, src, N, phi, forces, dbg_pn, dbg_fn,
-                  dbg_po, dbg_fo, eblk);
+           int Ss, int spad, const double4* __restrict__ src, int N, NearFix fix,
+           const double* __restrict__ qnet, double* __restrict__ phi, double* __restrict__ forces,
+           double* __restrict__ dbg_pn, double* __restrict__ dbg_fn, double* __restrict__ dbg_po,
+           double* __restrict__ dbg_fo, double* __restrict__ eblk) {
+    finalize_body(blockIdx.x, near, Sn, npad, surfp, Ss, spad, src, N, fix, qnet, phi, forces,
+                  dbg_pn, dbg_fn, dbg_po, dbg_fo, eblk);
+}
+
+__global__ void __launch_bounds__(SWG) k_net_charge(const double4* __restrict__ src, int N,
+                                                    double* __restrict__ out) {
+    net_charge_body(src, N, out);
 }
 
 __global__ void __launch_bounds__(WG) k_energy(const double* __restrict__ eblk, int nblk,
@@ -276,6 +292,9 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, s, res);
     hipLaunchKernelGGL(k_prep, dim3((N + WG - 1) / WG), dim3(WG), 0, s, x, q, N, pl->bc, pl->L,
                        src64, &res->status);
+    const NearFix fix = near_fix(pl, f32);
+    if (fix.qc != 0.0)
+        hipLaunchKernelGGL(k_net_charge, dim3(1), dim3(SWG), 0, s, src64, N, &res->qnet);
     CK(hipGetLastError());
     if (f32) CK(launch_make_rec32(src64, ly.ns, pl->L, src32, s));
     PairGeom g_rhs = ly.g_rhs, g_near = ly.g_near;
@@ -389,7 +408,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     const int near_S = ly.sym ? ly.g_sym.C + ly.g_sym.s : g_near.S;
     const int near_pad = ly.sym ? ly.g_sym.n_pad : g_near.nt_pad;
     hipLaunchKernelGGL(k_finalize, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, near_S,
-                       near_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, phi,
+                       near_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, fix, &res->qnet, phi,
                        forces, dbg ? dbg->phi_near : nullptr, dbg ? dbg->field_near : nullptr,
                        dbg ? dbg->phi_out : nullptr, dbg ? dbg->field_out : nullptr, eblk);
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(WG), 0, s, eblk, ly.n_eblk,

@@ -174,12 +174,26 @@ __device__ __forceinline__ void block_sum3(double (&sh)[3][SWG], double& a, doub
     c = sh[2][0];
 }
 
-// phi = near + surface (chunk sums in fixed order), F = q E, block partial
+// Net charge sum_i q_i of src[0 .. N) in a fixed order (one block of SWG
+// threads; the result is written by thread 0).
+__device__ __forceinline__ void net_charge_body(const double4* __restrict__ src, int N,
+                                                double* __restrict__ out) {
+    __shared__ double sh[3][SWG];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < N; i += SWG) a += src[i].w;
+    block_sum3(sh, a, b, c);
+    if (threadIdx.x == 0) *out = a;
+}
+
+// phi = near + surface (chunk sums in fixed order) + q * fix.own + Q * fix.qc
+// (NearFix; Q = *qnet, read only when fix.qc != 0), F = q E, block partial
 // sums of q phi, q and |q| (block blk, all SWG threads participate).
 __device__ __forceinline__ void finalize_body(int blk, const double* __restrict__ near, int Sn,
                                               int npad, const double* __restrict__ surfp, int Ss,
                                               int spad, const double4* __restrict__ src, int N,
-                                              double* __restrict__ phi, double* __restrict__ forces,
+                                              NearFix fix, const double* __restrict__ qnet,
+                                              double* __restrict__ phi,
+                                              double* __restrict__ forces,
                                               double* __restrict__ dbg_pn, double* __restrict__ dbg_fn,
                                               double* __restrict__ dbg_po, double* __restrict__ dbg_fo,
                                               double* __restrict__ eblk) {
@@ -196,6 +210,8 @@ __device__ __forceinline__ void finalize_body(int blk, const double* __restrict_
             vo[comp] = b;
         }
         const double qi = src[i].w;
+        vn[0] += qi * fix.own;
+        if (fix.qc != 0.0) vn[0] += *qnet * fix.qc;
         const double p = vn[0] + vo[0];
         if (phi) phi[i] = p;
         if (forces) {

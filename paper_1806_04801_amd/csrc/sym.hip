@@ -29,8 +29,9 @@
 // accumulators; reverse terms (at the columns) are reduced over the wave's
 // rows with a 64-lane reduce-scatter and go to slice sigma's copy of the
 // column accumulators.  The diagonal pairs (I, I) run first, forward only,
-// with the self term of the central image left out; they also initialise
-// every accumulator of their rows.
+// with a particle's pairing with itself reduced to the images of its
+// reflections (none in the periodic block, whose own images the finalize
+// stage adds exactly); they also initialise every accumulator of their rows.
 //
 // Accumulators: acc[c] = forward from column part c (c < C), acc[C + sigma] =
 // reverse from row slice sigma, each 4 components x n_pad doubles (potential,
@@ -165,8 +166,12 @@ __device__ __forceinline__ SymItem sym_item(const SymGeom& g, int round) {
 }
 
 // Near terms of one pair per unit charges: potential p, field f at the row,
-// and (REV) field rf at the column produced by the row.
-template <int IMG, bool REV>
+// and (REV) field rf at the column produced by the row.  OWN (diagonal
+// blocks): the periodic images of a particle's own charge are left to the
+// caller (images_sum).  In single precision both image blocks of the slab are
+// shifted by the same constant (images_sum, SHIFT), which cancels in their
+// difference.
+template <int IMG, bool REV, bool OWN>
 __device__ __forceinline__ void pair_terms(const Pt32& t, const Pt32& s, float& p, float (&f)[3],
                                            float (&rf)[3]) {
     constexpr int BI = IMG == IMG_SLAB ? IMG_PERIODIC : IMG;
@@ -174,14 +179,14 @@ __device__ __forceinline__ void pair_terms(const Pt32& t, const Pt32& s, float& 
     diffs_f32<BI>(t, s, 0, dx);
     diffs_f32<BI>(t, s, 1, dy);
     diffs_f32<BI>(t, s, 2, dz);
-    images_sum<float, BI, true, true, REV>(dx, dy, dz, p, f[0], f[1], f[2], rf);
+    images_sum<float, BI, true, true, REV, OWN, true>(dx, dy, dz, p, f[0], f[1], f[2], rf);
     if (IMG == IMG_SLAB) {
         // mirror block: z differences t + s - kL (k = -1, 0, +1), charge -1
         const float sl = t.l[2] + s.l[2];
         const float mz[3] = {(t.hm[2] + s.hm[2]) + sl, (t.h0[2] + s.h0[2]) + sl,
                              (t.hp[2] + s.hp[2]) + sl};
         float pm, gx, gy, gz;
-        images_sum<float, IMG_PERIODIC, true, false>(dx, dy, mz, pm, gx, gy, gz);
+        images_sum<float, IMG_PERIODIC, true, false, false, false, true>(dx, dy, mz, pm, gx, gy, gz);
         p -= pm;
         f[0] -= gx;
         f[1] -= gy;
@@ -194,7 +199,7 @@ __device__ __forceinline__ void pair_terms(const Pt32& t, const Pt32& s, float& 
     }
 }
 
-template <int IMG, bool REV>
+template <int IMG, bool REV, bool OWN>
 __device__ __forceinline__ void pair_terms(const double4& t, const double4& s, double L, double& p,
                                            double (&f)[3], double (&rf)[3]) {
     constexpr int BI = IMG == IMG_SLAB ? IMG_PERIODIC : IMG;
@@ -202,7 +207,7 @@ __device__ __forceinline__ void pair_terms(const double4& t, const double4& s, d
     diffs_f64<BI>(t.x, s.x, L, dx);
     diffs_f64<BI>(t.y, s.y, L, dy);
     diffs_f64<BI>(t.z, s.z, L, dz);
-    images_sum<double, BI, true, true, REV>(dx, dy, dz, p, f[0], f[1], f[2], rf);
+    images_sum<double, BI, true, true, REV, OWN>(dx, dy, dz, p, f[0], f[1], f[2], rf);
     if (IMG == IMG_SLAB) {
         const double sm = t.z + s.z;
         const double mz[3] = {sm + L, sm, sm - L};
@@ -287,7 +292,7 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
 #pragma unroll
                     for (int u = 0; u < T; ++u) {
                         float p0, f0[3], rf[3];
-                        pair_terms<IMG, !DIAG>(tp[u], sj, p0, f0, rf);
+                        pair_terms<IMG, !DIAG, DIAG>(tp[u], sj, p0, f0, rf);
                         sp[u] = __builtin_fmaf(qj, p0, sp[u]);
                         sx[u] = __builtin_fmaf(qj, f0[0], sx[u]);
                         sy[u] = __builtin_fmaf(qj, f0[1], sy[u]);
@@ -386,7 +391,7 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
             if (q < nh) {
                 const double4 sj = pts[jb + q];
                 double p0, f0[3], rf[3];
-                pair_terms<IMG, !DIAG>(t, sj, L, p0, f0, rf);
+                pair_terms<IMG, !DIAG, DIAG>(t, sj, L, p0, f0, rf);
                 ap = __builtin_fma(sj.w, p0, ap);
                 ax = __builtin_fma(sj.w, f0[0], ax);
                 ay = __builtin_fma(sj.w, f0[1], ay);

@@ -79,3 +79,39 @@ def test_bench_traffic_needs_matching_kernel_source(tmp_path, monkeypatch):
         f.write("static int edit_marker;\n")
     assert bench.profiled_traffic("w", "f32") is None
     assert bench.profiled_traffic("w", "f32", "pair-once") is None
+
+
+def test_own_image_constants_match_lattice_sums():
+    """The own-image constants that the near-sum kernels leave to the finalize
+    stage equal the lattice sums they stand for: the potential of the 26
+    images k != 0 of the periodic 3x3x3 block of a unit charge at the origin
+    (box side 1), and its split over the nine columns (k_x, k_y), which the
+    single-precision kernels subtract as float values."""
+    import itertools
+    import re
+
+    import numpy as np
+
+    src = open(os.path.join(HERE, "..", "paper_1806_04801_amd", "csrc", "hsma_internal.h")).read()
+
+    def const(name):
+        m = re.search(r"constexpr (?:float|double) %s = ([0-9.]+)f?;" % name, src)
+        assert m, name
+        return float(m.group(1))
+
+    total = const("OWN_IMAGES_PERIODIC")
+    cols = {}
+    for kx, ky in itertools.product((-1, 0, 1), repeat=2):
+        cols[(kx, ky)] = sum(1.0 / np.sqrt(kx * kx + ky * ky + kz * kz)
+                             for kz in (-1, 0, 1) if (kx, ky, kz) != (0, 0, 0))
+    brute = sum(cols.values())
+    assert abs(total - brute) <= 1e-15 * brute
+    # closed form 6 + 12/sqrt(2) + 8/sqrt(3): faces, edges, corners of the cube
+    assert abs(brute - (6 + 12 / np.sqrt(2) + 8 / np.sqrt(3))) <= 1e-14
+    centre, edge, corner = const("OWN_COL_CENTRE"), const("OWN_COL_EDGE"), const("OWN_COL_CORNER")
+    assert np.float32(centre) == np.float32(cols[(0, 0)])
+    assert np.float32(edge) == np.float32(cols[(1, 0)]) == np.float32(cols[(0, -1)])
+    assert np.float32(corner) == np.float32(cols[(1, 1)]) == np.float32(cols[(-1, 1)])
+    # the nine float constants add up to the total within float rounding
+    shift = float(np.float32(centre)) + 4 * float(np.float32(edge)) + 4 * float(np.float32(corner))
+    assert abs(shift - total) <= 9 * 2.0 ** -22
