@@ -26,9 +26,9 @@
 // lane) and reads its part of the B columns of block J at wave-uniform
 // addresses (scalar loads).  Forward terms (at the rows) accumulate per lane
 // as in the plain tile kernel and go to part c's copy of the row
-// accumulators; reverse terms (at the columns) are reduced over the wave's
-// rows with a 64-lane reduce-scatter and go to slice sigma's copy of the
-// column accumulators.  The diagonal pairs (I, I) run first, forward only,
+// accumulators; reverse terms (at the columns) are summed over the wave's
+// rows by a transpose through LDS and go to slice sigma's copy of the column
+// accumulators.  The diagonal pairs (I, I) run first, forward only,
 // with a particle's pairing with itself reduced to the images of its
 // reflections (none in the periodic block, whose own images the finalize
 // stage adds exactly); they also initialise every accumulator of their rows.
@@ -51,8 +51,6 @@ namespace hsma {
 
 constexpr int SW = 64;   // one wave per work-group
 
-__device__ __forceinline__ bool parity(int x) { return __builtin_popcount(x) & 1; }
-
 template <int CTRL>
 __device__ __forceinline__ float dpp_t(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
@@ -66,62 +64,47 @@ __device__ __forceinline__ double dpp_t(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ float lane_t(float x, int src_lane) {
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(x)));
+// Orders the LDS accesses before and after it within the wave.  The
+// work-group is one wave and a wave's LDS operations complete in issue order,
+// so no hardware wait is needed: a wavefront-scope fence keeps the compiler
+// from moving memory operations across.
+__device__ __forceinline__ void wave_order() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-__device__ __forceinline__ double lane_t(double x, int src_lane) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)b);
-    const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// One halving step of the reduce-scatter: lane l and its partner l ^ m hold
-// the same N pairs (v[k], v[k + N]); the lane with f set keeps the upper
-// halves, the other the lower ones, and each adds the partner's copy.
-template <int N, int CTRL, typename R, int NV>
-__device__ __forceinline__ void rs_step(R (&v)[NV], bool f) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const R lo = v[k], hi = v[k + N];
-        const R keep = f ? hi : lo;
-        const R send = f ? lo : hi;
-        v[k] = keep + dpp_t<CTRL>(send);
-    }
-}
-
-// Sum of NV (16 or 8) values over the 64 lanes of the wave.  The row-local
-// partners are lane ^ 1, ^ 2 (quad permutations), ^ 7 (half-row mirror) and
-// ^ 15 (row mirror); the lane bits that pick the kept half are parities of
-// lane & 5, lane & 6, lane & 12 and lane & 8, the dual basis of those four
-// masks, so partners always hold the same subset.  With 16 values four
-// halving steps leave one distinct value per lane of a row; with 8 values
-// three steps leave each value on a lane and its row mirror, which one more
-// exchange (^ 15) sums.  Two exchanges across rows (^ 16, ^ 32) finish.  Lane
-// l then holds value rs_owner<NV>(l); lanes 0 .. NV - 1 hold distinct values.
-template <int NV>
-__device__ __forceinline__ int rs_owner(int lane) {
-    return NV == 16 ? parity(lane & 5) * 8 + parity(lane & 6) * 4 + parity(lane & 12) * 2 +
-                          ((lane >> 3) & 1)
-                    : parity(lane & 5) * 4 + parity(lane & 6) * 2 + parity(lane & 12);
-}
-
+// Reverse-term table of one wave in LDS: NV rows (values) of 64 entries
+// (lanes), each row padded by 16 bytes.
 template <typename R, int NV>
-__device__ __forceinline__ R reduce_scatter(R (&v)[NV], int lane) {
-    static_assert(NV == 16 || NV == 8, "16 or 8 values");
-    rs_step<NV / 2, 0xB1>(v, parity(lane & 5));    // quad_perm [1,0,3,2]
-    rs_step<NV / 4, 0x4E>(v, parity(lane & 6));    // quad_perm [2,3,0,1]
-    rs_step<NV / 8, 0x141>(v, parity(lane & 12));  // row_half_mirror
-    R e;
-    if (NV == 16) {
-        rs_step<1, 0x140>(v, (lane >> 3) & 1);     // row_mirror
-        e = v[0];
-    } else {
-        e = v[0] + dpp_t<0x140>(v[0]);             // row_mirror
-    }
-    e += lane_t(e, lane ^ 16);
-    e += lane_t(e, lane ^ 32);
+struct RevTable {
+    static constexpr int G = SW / NV;                         // lanes per value: 8 or 4
+    static constexpr int STRIDE = SW + 16 / (int)sizeof(R);   // row stride in elements
+    static constexpr int SIZE = NV * STRIDE;
+};
+
+// Sum of NV (8 or 16) values over the 64 lanes of the wave, as a transpose
+// through LDS: lane l stores its values in column l of the table; then lane
+// l adds the NV consecutive entries [NV (l % G), NV (l % G) + NV) of row
+// v = l / G (G = 64 / NV lanes per value), and the G lanes of a value finish
+// with DPP exchanges (lane ^ 1, ^ 2 and, for G = 8, the half-row mirror, which
+// pairs the two quads).  Every lane of group v returns the total of value v.
+// The LDS accesses take no vector-ALU issue slots: per value the ALU work is
+// NV - 1 adds plus the exchanges.  Fixed order, so the result is
+// deterministic.
+template <typename R, int NV>
+__device__ __forceinline__ R reduce_lds(const R (&v)[NV], int lane, R* __restrict__ tab) {
+    using TT = RevTable<R, NV>;
+    static_assert(NV == 8 || NV == 16, "8 or 16 values");
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tab[k * TT::STRIDE + lane] = v[k];
+    wave_order();   // the stores before the loads of other lanes
+    const R* row = tab + (lane / TT::G) * TT::STRIDE + (lane % TT::G) * NV;
+    R e = row[0];
+#pragma unroll
+    for (int i = 1; i < NV; ++i) e += row[i];
+    wave_order();   // the next call's stores after these loads
+    e += dpp_t<0xB1>(e);                     // quad_perm [1,0,3,2]: lane ^ 1
+    e += dpp_t<0x4E>(e);                     // quad_perm [2,3,0,1]: lane ^ 2
+    if (TT::G == 8) e += dpp_t<0x141>(e);    // row_half_mirror: the other quad
     return e;
 }
 
@@ -167,8 +150,9 @@ __device__ __forceinline__ SymItem sym_item(const SymGeom& g, int round) {
 
 // Near terms of one pair per unit charges: potential p, field f at the row,
 // and (REV) field rf at the column produced by the row.  OWN (diagonal
-// blocks): the periodic images of a particle's own charge are left to the
-// caller (images_sum).  In single precision both image blocks of the slab are
+// blocks, the only ones where a particle meets itself): a zero central
+// distance is skipped and the periodic images of a particle's own charge are
+// left to the caller (images_sum).  In single precision both image blocks of the slab are
 // shifted by the same constant (images_sum, SHIFT), which cancels in their
 // difference.
 template <int IMG, bool REV, bool OWN>
@@ -179,7 +163,7 @@ __device__ __forceinline__ void pair_terms(const Pt32& t, const Pt32& s, float& 
     diffs_f32<BI>(t, s, 0, dx);
     diffs_f32<BI>(t, s, 1, dy);
     diffs_f32<BI>(t, s, 2, dz);
-    images_sum<float, BI, true, true, REV, OWN, true>(dx, dy, dz, p, f[0], f[1], f[2], rf);
+    images_sum<float, BI, true, OWN, REV, OWN, true>(dx, dy, dz, p, f[0], f[1], f[2], rf);
     if (IMG == IMG_SLAB) {
         // mirror block: z differences t + s - kL (k = -1, 0, +1), charge -1
         const float sl = t.l[2] + s.l[2];
@@ -207,7 +191,7 @@ __device__ __forceinline__ void pair_terms(const double4& t, const double4& s, d
     diffs_f64<BI>(t.x, s.x, L, dx);
     diffs_f64<BI>(t.y, s.y, L, dy);
     diffs_f64<BI>(t.z, s.z, L, dz);
-    images_sum<double, BI, true, true, REV, OWN>(dx, dy, dz, p, f[0], f[1], f[2], rf);
+    images_sum<double, BI, true, OWN, REV, OWN>(dx, dy, dz, p, f[0], f[1], f[2], rf);
     if (IMG == IMG_SLAB) {
         const double sm = t.z + s.z;
         const double mz[3] = {sm + L, sm, sm - L};
@@ -263,7 +247,11 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
 
     const int c0 = min(J * g.B + (int)((long)part * g.B / g.C), g.n);
     const int c1 = min(J * g.B + (int)((long)(part + 1) * g.B / g.C), g.n);
-    const int kown = rs_owner<NV>(lane);
+    // reverse values: lane l owns value l / G of each group when l % G == 0
+    __shared__ float tab[RevTable<float, NV>::SIZE];
+    constexpr int G = RevTable<float, NV>::G;
+    const bool owner = lane % G == 0;
+    const int kown = lane / G;
     const int kcol = kown >> 2, kcomp = kown & 3;
     const double oscale = kcomp == 0 ? invL : invL2;
     for (int g0 = c0; g0 < c1; g0 += 8) {
@@ -277,7 +265,7 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
             if (nh <= 0) break;
             double old = 0.0;
             double* dst = nullptr;
-            if (!DIAG && lane < NV && kcol < nh) {
+            if (!DIAG && owner && kcol < nh) {
                 dst = rev + (size_t)kcomp * g.n_pad + jb + kcol;
                 old = *dst;
             }
@@ -311,7 +299,7 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
                 rv[4 * q + 3] = rz;
             }
             if (!DIAG) {
-                const float e = reduce_scatter(rv, lane);
+                const float e = reduce_lds(rv, lane, tab);
                 if (dst != nullptr) *dst = old + (double)e * oscale;
             }
         }
@@ -374,13 +362,16 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
 
     const int c0 = min(it.J * g.B + (int)((long)it.part * g.B / g.C), g.n);
     const int c1 = min(it.J * g.B + (int)((long)(it.part + 1) * g.B / g.C), g.n);
-    const int kown = rs_owner<NV>(lane);
+    __shared__ double tab[RevTable<double, NV>::SIZE];
+    constexpr int G = RevTable<double, NV>::G;
+    const bool owner = lane % G == 0;
+    const int kown = lane / G;
     const int kcol = kown >> 2, kcomp = kown & 3;
     for (int jb = c0; jb < c1; jb += QC) {
         const int nh = min(QC, c1 - jb);
         double old = 0.0;
         double* dst = nullptr;
-        if (!DIAG && lane < NV && kcol < nh) {
+        if (!DIAG && owner && kcol < nh) {
             dst = rev + (size_t)kcomp * g.n_pad + jb + kcol;
             old = *dst;
         }
@@ -409,7 +400,7 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
             rv[4 * q + 3] = rz;
         }
         if (!DIAG) {
-            const double e = reduce_scatter(rv, lane);
+            const double e = reduce_lds(rv, lane, tab);
             if (dst != nullptr) *dst = old + e;
         }
     }
@@ -433,7 +424,7 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
 
 // Resident one-wave work-groups per CU of the round kernel of an image kind
 // (T = 0: double precision).
-// Columns per reverse group (reduce-scatter of 4 x QC values): 2 in single
+// Columns per reverse group (LDS reduction of 4 x QC values): 2 in single
 // precision (fewer registers, more resident waves), 4 in double (measured);
 // HSMA_SYM_Q = 2 or 4 overrides.
 static int sym_q(bool f64) {
