@@ -179,11 +179,12 @@ size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
  *           the two particles; for the slab, the real charges with the
  *           periodic blocks of each charge and of its mirror).  Either
  *           precision, every boundary condition, block near set, N at or
- *           above a threshold (8192 in single and 6656 in double precision,
+ *           above a threshold (5120 in single and 3584 in double precision,
  *           the same for requests of the batched server; the environment
  *           variable HSMA_SYM_MIN overrides it);
  *           HSMA_SYM=0 in the environment turns it off and HSMA_SYM=1 forces
- *           it; for tuning, HSMA_SYM_T (1 or 2 rows per lane), HSMA_SYM_Q (2
+ *           it; for tuning, HSMA_SYM_T (rows per lane: 1, the default, or 2;
+ *           0 picks by occupancy), HSMA_SYM_Q (2
  *           or 4 columns per reverse group) and HSMA_SYM_ROUNDS (target round
  *           count) override the choices the library makes.  The particles are cut
  *           into `blocks` blocks of `block`; block pairs run in blocks - 1

@@ -90,7 +90,8 @@ struct SymGeom {
 };
 // Single precision: T = 1 or 2 rows per lane, or 0 to choose the one whose
 // rounds fill the GPU better (resident waves from the occupancy of each kernel
-// variant).  Double precision (f64): one row per lane.
+// variant); the library uses 1, which measured at least as fast everywhere.
+// Double precision (f64): one row per lane.
 SymGeom sym_geometry(int n, int T, bool f64, int img, int ncu);
 
 // One group of tiles of a grouped pair launch: all tiles of one pair stage of

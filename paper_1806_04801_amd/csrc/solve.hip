@@ -58,11 +58,11 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     // overrides the threshold.
     {
         const int mode = env_int("HSMA_SYM", -1);
-        const int nmin = env_int("HSMA_SYM_MIN", f32 ? 8192 : 6656);
+        const int nmin = env_int("HSMA_SYM_MIN", f32 ? 5120 : 3584);
         const bool eligible = !sphere && ly.N > 0;
         ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
         ly.sym_img = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? IMG_SLAB : pl->img;
-        if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 0), !f32, ly.sym_img, pl->ncu);
+        if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 1), !f32, ly.sym_img, pl->ncu);
     }
     const int nsurf = pl->dipole_mode == HSMA_DIPOLE_LAYERS ? 3 * pl->M : pl->M;
     ly.g_surf = pair_geometry(ly.N, nsurf, 1, pl->ncu);

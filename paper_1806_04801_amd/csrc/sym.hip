@@ -485,13 +485,14 @@ static SymGeom sym_geometry_t(int n, int T, bool f64, int img, int ncu, double* 
     g.n_pad = g.nb * g.B;
     // Column parts: a round's waves all take equally long, so they run in
     // batches of `cap` resident waves and the last batch may be part empty.
-    // Pick the part count (at most 16, at least 64 columns per part) whose
+    // Pick the part count (at most 64, at least 16 columns per part) whose
     // waves fill their batches best; a larger count wins only by more than 2 %.
+    // Small rounds (N up to ~3e4) need many narrow parts to fill the GPU.
     const long cap = (long)sym_waves_per_cu(f64 ? 0 : T, img) * ncu;
     const long w1 = (long)(g.P / 2) * g.s;
-    long cmax = g.B / 64;
+    long cmax = g.B / 16;
     if (cmax < 1) cmax = 1;
-    if (cmax > 16) cmax = 16;
+    if (cmax > 64) cmax = 64;
     long best = 1;
     double best_fill = 0.0;
     for (long C = 1; C <= cmax; ++C) {
@@ -512,7 +513,8 @@ SymGeom sym_geometry(int n, int T, bool f64, int img, int ncu) {
     double f1 = 0.0, f2 = 0.0;
     if (f64) return sym_geometry_t(n, 1, true, img, ncu, &f1);
     if (T == 1 || T == 2) return sym_geometry_t(n, T, false, img, ncu, &f1);
-    // one row per lane (more resident waves) unless two fill the slots better
+    // T = 0: one row per lane (more resident waves) unless two fill the slots
+    // better
     const SymGeom g1 = sym_geometry_t(n, 1, false, img, ncu, &f1);
     const SymGeom g2 = sym_geometry_t(n, 2, false, img, ncu, &f2);
     return f2 > f1 + 0.02 ? g2 : g1;
