@@ -179,7 +179,7 @@ size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
  *           the two particles; for the slab, the real charges with the
  *           periodic blocks of each charge and of its mirror).  Either
  *           precision, every boundary condition, block near set, N at or
- *           above a threshold (5120 in single and 3584 in double precision,
+ *           above a threshold (1024 in either precision,
  *           the same for requests of the batched server; the environment
  *           variable HSMA_SYM_MIN overrides it);
  *           HSMA_SYM=0 in the environment turns it off and HSMA_SYM=1 forces

@@ -58,7 +58,7 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     // overrides the threshold.
     {
         const int mode = env_int("HSMA_SYM", -1);
-        const int nmin = env_int("HSMA_SYM_MIN", f32 ? 5120 : 3584);
+        const int nmin = env_int("HSMA_SYM_MIN", 1024);
         const bool eligible = !sphere && ly.N > 0;
         ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
         ly.sym_img = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? IMG_SLAB : pl->img;

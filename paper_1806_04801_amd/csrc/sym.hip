@@ -454,14 +454,15 @@ static int sym_waves_per_cu(int T, int img) {
     return (e == hipSuccess && nblk > 0) ? nblk : 8;
 }
 
-// Target number of rounds: n / 1024 within [8, 128] (measured best from 4e3
-// to 1.3e5 particles in both precisions: fewer, larger rounds while a round
-// cannot fill the GPU anyway); HSMA_SYM_ROUNDS overrides.
+// Target number of rounds: n / 1024 within [2, 128] (measured best from 3e3
+// to 1.3e5 particles in both precisions, with up to 64 column parts: fewer,
+// larger rounds while a round cannot fill the GPU anyway, and fewer
+// launches); HSMA_SYM_ROUNDS overrides.
 static long sym_rounds(int n) {
     const char* v = getenv("HSMA_SYM_ROUNDS");
     const long r = v != nullptr ? atol(v) : 0;
     if (r >= 2) return r;
-    return std::min(128L, std::max(8L, (long)n / 1024));
+    return std::min(128L, std::max(2L, (long)n / 1024));
 }
 
 // Geometry for T rows per lane; *fill is the fraction of resident-wave slots
@@ -478,6 +479,12 @@ static SymGeom sym_geometry_t(int n, int T, bool f64, int img, int ncu, double* 
     if (s > 64) s = 64;
     // keep the accumulators (C + s copies of 32 bytes per particle) under 8 GB
     while (s > 1 && (s + 17) * 32.0 * (double)n > 8e9) --s;
+    // an odd block count leaves one block idle in every round (a bye), which
+    // costs 1 / nb of each round: larger blocks make the count even
+    auto blocks = [&](long sl) { return (n + rows * sl - 1) / (rows * sl); };
+    long s2 = s;
+    while (blocks(s2) > 1 && (blocks(s2) & 1) && s2 < 64 && (s2 + 18) * 32.0 * (double)n <= 8e9) ++s2;
+    if (blocks(s2) == 1 || !(blocks(s2) & 1)) s = s2;
     g.s = (int)s;
     g.B = (int)(rows * s);
     g.nb = (n + g.B - 1) / g.B;
