@@ -259,13 +259,17 @@ def test_near_schedule_query(hs, monkeypatch):
     plan = hs.Plan(1.0, 0, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
     small = plan.near_schedule(1000)
     assert small["kind"] == 0 and small["launches"] == 0
-    big = plan.near_schedule(10 ** 6)
-    assert big["kind"] == 1
-    assert big["rows_per_lane"] in (1, 2)
-    assert big["block"] == 64 * big["rows_per_lane"] * big["slices"]
-    assert big["blocks"] * big["block"] >= 10 ** 6 > (big["blocks"] - 1) * big["block"]
-    assert big["launches"] == big["blocks"] + (big["blocks"] & 1)
-    assert 1 <= big["parts"] <= 16 and big["block"] // big["parts"] >= 64
+    for n in (1024, 3000, 5120, 10000, 40001, 200000, 10 ** 6):
+        sc = plan.near_schedule(n)
+        assert sc["kind"] == 1 and sc["rows_per_lane"] == 1
+        assert sc["block"] == 64 * sc["slices"] and 1 <= sc["slices"] <= 64
+        assert sc["blocks"] * sc["block"] >= n > (sc["blocks"] - 1) * sc["block"]
+        assert sc["launches"] == sc["blocks"] + (sc["blocks"] & 1)
+        # at most 64 column parts of at least 16 columns
+        assert 1 <= sc["parts"] <= 64 and sc["block"] // sc["parts"] >= 16
+        # an even block count (no idle block per round) unless slices are at
+        # their limit
+        assert sc["blocks"] % 2 == 0 or sc["slices"] == 64, (n, sc)
     monkeypatch.setenv("HSMA_SYM", "0")
     assert plan.near_schedule(10 ** 6)["kind"] == 0
     monkeypatch.setenv("HSMA_SYM", "1")
