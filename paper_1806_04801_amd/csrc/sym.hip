@@ -71,8 +71,14 @@ __device__ __forceinline__ double dpp_t(double x) {
 // of one copy per lane in VGPRs.
 template <typename P>
 __device__ __forceinline__ P column(const P* __restrict__ pts, int j) {
-    using CP = const __attribute__((address_space(4))) P*;
-    return ((CP)pts)[__builtin_amdgcn_readfirstlane(j)];
+    static_assert(sizeof(P) % sizeof(unsigned int) == 0, "records of whole words");
+    using CW = const __attribute__((address_space(4))) unsigned int*;
+    const CW w = (CW)(pts + __builtin_amdgcn_readfirstlane(j));
+    P out;
+    unsigned int* o = reinterpret_cast<unsigned int*>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(P) / sizeof(unsigned int)); ++k) o[k] = w[k];
+    return out;
 }
 
 // Orders the LDS accesses before and after it within the wave.  The
