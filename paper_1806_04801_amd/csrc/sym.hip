@@ -23,8 +23,8 @@
 // rounds accumulate in place, in a fixed order, without atomics.  A pair is
 // split into s row slices and C column parts; work-group (pair, slice,
 // part) is one wave that keeps 64 * T rows of block I in registers (T per
-// lane) and reads its part of the B columns of block J through scalar loads
-// (column()).  Forward terms (at the rows) accumulate per lane
+// lane) and reads its part of the B columns of block J at wave-uniform
+// addresses (scalar loads).  Forward terms (at the rows) accumulate per lane
 // as in the plain tile kernel and go to part c's copy of the row
 // accumulators; reverse terms (at the columns) are summed over the wave's
 // rows by a transpose through LDS and go to slice sigma's copy of the column
@@ -62,23 +62,6 @@ __device__ __forceinline__ double dpp_t(double x) {
     const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// A column record, read through the scalar data cache: the index is uniform
-// over the wave (made explicit, so the compiler can prove it) and the records
-// are not written while the kernel runs, so a constant-address-space read
-// lets them arrive in SGPRs, as operands of the vector instructions, instead
-// of one copy per lane in VGPRs.
-template <typename P>
-__device__ __forceinline__ P column(const P* __restrict__ pts, int j) {
-    static_assert(sizeof(P) % sizeof(unsigned int) == 0, "records of whole words");
-    using CW = const __attribute__((address_space(4))) unsigned int*;
-    const CW w = (CW)(pts + __builtin_amdgcn_readfirstlane(j));
-    P out;
-    unsigned int* o = reinterpret_cast<unsigned int*>(&out);
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(P) / sizeof(unsigned int)); ++k) o[k] = w[k];
-    return out;
 }
 
 // Orders the LDS accesses before and after it within the wave.  The
@@ -291,7 +274,7 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
             for (int q = 0; q < QC; ++q) {
                 float rp = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f;
                 if (q < nh) {
-                    const Rec32 rec = column(pts, jb + q);
+                    const Rec32 rec = pts[jb + q];
                     const Pt32 sj = load_pt32(rec);
                     const float qj = rec.v[0].w;
 #pragma unroll
@@ -397,7 +380,7 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
         for (int q = 0; q < QC; ++q) {
             double rp = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
             if (q < nh) {
-                const double4 sj = column(pts, jb + q);
+                const double4 sj = pts[jb + q];
                 double p0, f0[3], rf[3];
                 pair_terms<IMG, !DIAG, DIAG>(t, sj, L, p0, f0, rf);
                 ap = __builtin_fma(sj.w, p0, ap);
