@@ -71,8 +71,9 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 // image cube starts, the column's value for a unit charge at the target
 // itself (OWN_COL_*) is subtracted from that column's first term, off the
 // running sum, so the running potential stays of order 1 / L instead of
-// growing to ~19 / L.  Its rounding, which dominates the single-precision
-// error of a neutral system's energy, shrinks about tenfold.  The pair's
+// growing to ~19 / L.  Its rounding dominates the single-precision error of a
+// neutral system's energy, which the shift cuts several-fold (tenfold for a
+// periodic cube of 1e6 charges).  The pair's
 // potential comes back lowered by OWN_COLS_F32 / L per unit charge, which the
 // finalize stage restores exactly.
 template <typename R, int IMG, bool FIELD, bool SELF, bool REV = false, bool OWN = false,
