@@ -24,7 +24,8 @@
 // split into s row slices and C column parts; work-group (pair, slice,
 // part) is one wave that keeps 64 * T rows of block I in registers (T per
 // lane) and reads its part of the B columns of block J at wave-uniform
-// addresses (scalar loads).  Forward terms (at the rows) accumulate per lane
+// addresses (vector loads: every lane fetches the same record, one cache line
+// per load, no LDS staging).  Forward terms (at the rows) accumulate per lane
 // as in the plain tile kernel and go to part c's copy of the row
 // accumulators; reverse terms (at the columns) are summed over the wave's
 // rows by a transpose through LDS and go to slice sigma's copy of the column
