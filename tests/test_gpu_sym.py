@@ -64,7 +64,9 @@ def charges(bc, n, seed):
 
 @pytest.mark.parametrize("bc,n,T", [(0, 3000, 1), (0, 3000, 2), (1, 3001, 1), (1, 3001, 2)])
 def test_sym_vs_oracle(hs, monkeypatch, bc, n, T):
-    # n = 3000, T = 1: 47 blocks of 64 (odd: a bye per round), last block 56 rows
+    # n = 3000: 2 blocks of 1536 rows (24 slices of 64 at T = 1, 12 of 128 at
+    # T = 2); the second holds 1464 rows, so its last live slice is ragged
+    # (56 rows) and the rest of the block is empty
     announce("sym vs oracle bc=%d n=%d T=%d" % (bc, n, T))
     x, q = charges(bc, n, 41 + n)
     ref = oracle.solve(oracle.make_plan(1.0, bc, 12, 1000, 600, 2.7), x, q)
@@ -84,8 +86,9 @@ def test_sym_vs_oracle(hs, monkeypatch, bc, n, T):
 
 @pytest.mark.parametrize("bc,n,T", [(0, 40001, 1), (1, 40000, 2)])
 def test_sym_vs_tiles(hs, monkeypatch, bc, n, T):
-    # n = 40001, T = 1: blocks of 3 slices x 64 rows; the last block holds 65
-    # rows, so its second slice has one live row and its third none
+    # n = 40001, T = 1: 32 blocks of 20 slices x 64 rows (31 rounds); the last
+    # block holds 321 rows, so its sixth slice has one live row and the other
+    # 14 none
     announce("sym vs tiles bc=%d n=%d T=%d" % (bc, n, T))
     x, q = charges(bc, n, 7 + n)
     plan = hs.Plan(1.0, bc, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
@@ -166,6 +169,47 @@ def test_sym_f64_vs_oracle(hs, monkeypatch, bc, n):
     assert err_pn <= 1e-10
     assert err_fn <= 1e-10
     assert err_F <= 1e-10
+
+
+_ODD_REF = {}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_sym_odd_block_count_vs_oracle(hs, monkeypatch, bc, prec):
+    """An odd block count, where one block sits out every round.  Block sizes
+    are chosen to make the count even unless the slices reach their limit of
+    64, so the default schedule gives an odd count only above ~5e5 particles;
+    two rounds forced at n = 12000 give 3 blocks of 64 slices x 64 rows.  The
+    last block holds 3808 rows: 59 full slices, one of 32 rows, four empty."""
+    n = 12000
+    announce("sym odd blocks vs oracle bc=%d %s" % (bc, prec))
+    monkeypatch.setenv("HSMA_SYM", "1")
+    monkeypatch.setenv("HSMA_SYM_T", "1")
+    monkeypatch.setenv("HSMA_SYM_ROUNDS", "2")
+    x, q = charges(bc, n, 301 + bc)
+    if bc not in _ODD_REF:
+        _ODD_REF[bc] = oracle.solve(oracle.make_plan(1.0, bc, 12, 1000, 600, 2.7), x, q)
+    ref = _ODD_REF[bc]
+    plan = hs.Plan(1.0, bc, 12, 1000, 600, 2.7,
+                   precision=hs.FP32_COMP if prec == "fp32" else hs.FP64)
+    sc = plan.near_schedule(n)
+    assert sc["kind"] == 1 and sc["slices"] == 64 and sc["block"] == 4096, sc
+    assert sc["blocks"] == 3 and sc["launches"] == 4, sc
+    e, phi, F, inter = run(hs, plan, x, q, monkeypatch, True, 1)
+    err_e = abs(e - ref["energy"]) / abs(ref["energy"])
+    err_pn = rel_own(inter["phi_near"], ref["phi_near"])
+    err_fn = rel_max(inter["field_near"], ref["field_near"])
+    err_F = rel_max(F, ref["forces"])
+    print("sym odd blocks bc=%d %s: dE/E %.2e dphi_near %.2e dE_near %.2e dF %.2e"
+          % (bc, prec, err_e, err_pn, err_fn, err_F))
+    if prec == "fp32":
+        assert err_e <= 1e-5
+        assert err_pn <= 1e-5
+        assert err_fn <= 1e-4
+        assert err_F <= 1e-4
+    else:
+        assert max(err_e, err_pn, err_fn, err_F) <= 1e-10
 
 
 @pytest.mark.parametrize("bc,n", [(0, 40001), (1, 40000)])
