@@ -168,6 +168,12 @@ hsma_status hsma_plan_points(hsma_plan plan, int which, double* xyz, double* w);
 
 /* Device bytes of workspace needed by the device entry points for N particles. */
 size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
+/* For tuning, HSMA_TPL_NEAR and HSMA_TPL_RHS in the environment set the
+ * targets per lane (1 or 2; other values are ignored) of the per-target near
+ * tiles and of the right-hand-side tiles; defaults 1, and 2 for the near tiles
+ * of the sphere near set.  These and the HSMA_SYM variables of
+ * hsma_near_schedule change the workspace size, so they must not change
+ * between this query and the calls that use the workspace. */
 
 /*
  * The near-field kernel that an update step with N particles runs, and its

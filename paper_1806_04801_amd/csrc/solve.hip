@@ -41,10 +41,15 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.f32 = f32;
     const bool sphere = pl->near_mode == HSMA_NEAR_SPHERE;
     // targets per lane of the near tiles: the image-block kernels run best
-    // with one, the explicit-image tiles with two (measured)
+    // with one, the explicit-image tiles with two (measured); an override other
+    // than 1 or 2 is ignored
+    auto tpl_env = [](const char* name, int dflt) {
+        const int v = env_int(name, dflt);
+        return (v == 1 || v == 2) ? v : dflt;
+    };
     const int tpl_near = tpl_near_override > 0 ? tpl_near_override
-                                               : env_int("HSMA_TPL_NEAR", sphere ? 2 : 1);
-    const int tpl_rhs = env_int("HSMA_TPL_RHS", 1);
+                                               : tpl_env("HSMA_TPL_NEAR", sphere ? 2 : 1);
+    const int tpl_rhs = tpl_env("HSMA_TPL_RHS", 1);
     // sphere mode: sources are the explicit images (at most maxper per source);
     // partial buffers are sized for that bound
     ly.img_max = sphere ? (int64_t)ly.ns * pl->maxper : 0;

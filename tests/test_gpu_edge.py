@@ -107,3 +107,23 @@ def test_plan_reuse_across_sizes_and_streams(hs):
         with torch.cuda.stream(s):
             e, phi, F = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
         assert abs(e - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+
+
+@pytest.mark.parametrize("value", ["0", "3", "-1", "x"])
+def test_invalid_tile_overrides_are_ignored(hs, monkeypatch, value):
+    """Rows-per-lane overrides other than 1 or 2 fall back to the defaults
+    (a zero once divided by zero when the tile grid was sized): the result is
+    the same as without them, bit for bit."""
+    announce("edge tile override %s" % value)
+    x, q = W.uniform_neutral(300, 1.0, 12)
+    plan = hs.Plan(1.0, 0, 8, 600, 300, 2.7, precision=hs.FP32_COMP)
+    xd = torch.tensor(x, device="cuda")
+    qd = torch.tensor(q, device="cuda")
+    monkeypatch.delenv("HSMA_TPL_NEAR", raising=False)
+    monkeypatch.delenv("HSMA_TPL_RHS", raising=False)
+    e0, phi0, F0 = plan.energy_forces(xd, qd)
+    monkeypatch.setenv("HSMA_TPL_NEAR", value)
+    monkeypatch.setenv("HSMA_TPL_RHS", value)
+    e1, phi1, F1 = plan.energy_forces(xd, qd)
+    assert e1 == e0
+    assert torch.equal(phi1, phi0) and torch.equal(F1, F0)
