@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--workload", default="periodic1m")
     ap.add_argument("--precision", default=None, help="fp64 or fp32 (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-targets", type=int, default=256)
+    ap.add_argument("--cpu-targets", type=int, default=2048,
+                    help="particles in the oracle sample (about 17 s on 16 host threads at 1e6)")
     ap.add_argument("--requests", type=int, default=1024, help="serving: trace length")
     ap.add_argument("--refine", type=float, default=3e-3,
                     help="serving: recompute in double precision the requests whose FP32 energy "
