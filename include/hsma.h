@@ -227,7 +227,12 @@ hsma_status hsma_energy_forces(hsma_plan plan, const double* x, const double* q,
  * workspace of hsma_workspace_bytes(plan, N) bytes, all work enqueued on
  * `stream` (a hipStream_t; NULL = default stream).  energy is a host double
  * written after the stream has drained (the call waits for it).  dbg (may be
- * NULL) requests copies of the intermediate stages.
+ * NULL) requests copies of the intermediate stages.  The right-hand-side
+ * chain runs on an auxiliary non-blocking stream of the calling host thread
+ * (created on its first call on a device), forked from `stream` and joined
+ * back into it with events, so that all of a call's work stays ordered on
+ * `stream`; HSMA_OVERLAP=0 in the environment (read once per process) keeps
+ * it on `stream` itself.
  */
 hsma_status hsma_energy_forces_device(hsma_plan plan, const double* x, const double* q, int64_t N,
                                       void* stream, void* workspace, size_t workspace_bytes,

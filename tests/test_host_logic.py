@@ -115,3 +115,20 @@ def test_own_image_constants_match_lattice_sums():
     # the nine float constants add up to the total within float rounding
     shift = float(np.float32(centre)) + 4 * float(np.float32(edge)) + 4 * float(np.float32(corner))
     assert abs(shift - total) <= 9 * 2.0 ** -22
+
+
+def test_header_documents_every_environment_override():
+    """Every environment variable that the library reads is named in the
+    public header, where its meaning and the values it accepts are stated."""
+    import glob
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    names = set()
+    for path in glob.glob(os.path.join(root, "paper_1806_04801_amd", "csrc", "*")):
+        text = open(path).read()
+        # every "HSMA_..." string literal of the sources is a variable name
+        names |= set(re.findall(r'"(HSMA_[A-Z0-9_]+)"', text))
+    assert {"HSMA_SYM", "HSMA_OVERLAP", "HSMA_TPL_NEAR"} <= names
+    header = open(os.path.join(root, "include", "hsma.h")).read()
+    missing = sorted(n for n in names if not re.search(r"\b%s\b" % n, header))
+    assert not missing, missing
