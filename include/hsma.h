@@ -19,6 +19,9 @@
  *     positions must lie strictly inside (HSMA_E_OUT_OF_BOX otherwise).
  *   - Periodic and slab systems must be neutral: |sum q| <= 1e-12 sum |q|
  *     (HSMA_E_NOT_NEUTRAL).
+ *   - Two charges at exactly the same position (compared after periodic
+ *     wrapping) have an infinite interaction: HSMA_E_COINCIDENT.  Close but
+ *     distinct positions are accepted.
  *   - The periodic potential is defined up to a constant; the library fixes
  *     it by A_00 = 0 (the constant harmonic carries no information in the
  *     periodic residual of Sec. II.A).
@@ -80,6 +83,7 @@ typedef enum {
     HSMA_E_INVALID = -1,      /* bad argument (sizes, NULL, non-finite input, K < unknowns, R <= R0) */
     HSMA_E_NOT_NEUTRAL = -2,  /* periodic or slab system with non-zero total charge */
     HSMA_E_OUT_OF_BOX = -3,   /* grounded-cube or slab position on or outside a wall */
+    HSMA_E_COINCIDENT = -4,   /* two charges at exactly the same position (after periodic wrapping) */
     HSMA_E_NOMEM = -5,        /* device allocation failed or workspace too small */
     HSMA_E_DEVICE = -6,       /* HIP runtime error */
     HSMA_E_ILLCOND = -7       /* least-squares matrix numerically rank deficient */

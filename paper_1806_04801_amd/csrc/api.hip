@@ -71,6 +71,7 @@ const char* hsma_status_string(int st) {
         case HSMA_E_INVALID: return "invalid argument";
         case HSMA_E_NOT_NEUTRAL: return "system not neutral";
         case HSMA_E_OUT_OF_BOX: return "position outside the box";
+        case HSMA_E_COINCIDENT: return "two charges at the same position";
         case HSMA_E_NOMEM: return "out of device memory or workspace too small";
         case HSMA_E_DEVICE: return "HIP runtime error";
         case HSMA_E_ILLCOND: return "fitting matrix rank deficient";

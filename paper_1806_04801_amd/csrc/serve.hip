@@ -64,6 +64,8 @@ struct ReqDesc {
     Result* res;
     double* phi;
     double* forces;
+    int* dup;            // exact-coincidence table, dup_mask + 1 slots
+    uint32_t dup_mask;
 };
 
 // ---------------------------------------------------------------- grouped kernels
@@ -87,6 +89,21 @@ __global__ void __launch_bounds__(SWG) k_g_prep(const ReqDesc* __restrict__ D) {
     const ReqDesc& d = D[blockIdx.y];
     const int i = blockIdx.x * SWG + threadIdx.x;
     if (i < d.N) prep_body(i, d.x, d.q, d.N, d.bc, d.L, d.src64, &d.res->status);
+}
+
+// The table of each request is cleared with a grid-stride loop (it holds up
+// to 4N slots, the grid covers N), then every real charge enters it.
+__global__ void __launch_bounds__(SWG) k_g_dup_clear(const ReqDesc* __restrict__ D) {
+    const ReqDesc& d = D[blockIdx.y];
+    for (uint64_t t = (uint64_t)blockIdx.x * SWG + threadIdx.x; t <= (uint64_t)d.dup_mask;
+         t += (uint64_t)gridDim.x * SWG)
+        d.dup[t] = -1;
+}
+
+__global__ void __launch_bounds__(SWG) k_g_dup(const ReqDesc* __restrict__ D) {
+    const ReqDesc& d = D[blockIdx.y];
+    const int i = blockIdx.x * SWG + threadIdx.x;
+    if (i < d.N) dup_insert_body(i, d.src64, d.dup, d.dup_mask, &d.res->status);
 }
 
 __global__ void __launch_bounds__(SWG) k_g_rec32(const ReqDesc* __restrict__ D) {
@@ -287,6 +304,8 @@ static bool admit(hsma_server_s* sv, SrvReq* r) {
     d.res = (Result*)(ws + ly.off_result);
     d.phi = dphi;
     d.forces = dF;
+    d.dup = (int*)(ws + ly.off_dup);
+    d.dup_mask = (uint32_t)(ly.dup_T - 1);
     const double* hx = r->ext_x ? r->ext_x : r->hx.data();
     const double* hq = r->ext_q ? r->ext_q : r->hq.data();
     hipMemcpyAsync(dx, hx, sizeof(double) * 3 * N, hipMemcpyHostToDevice, sv->stream);
@@ -386,6 +405,7 @@ static void retire(hsma_server_s* sv) {
         if (res->status & 1) r->status = HSMA_E_INVALID;
         else if (res->status & 2) r->status = HSMA_E_OUT_OF_BOX;
         else if (res->status & 4) r->status = HSMA_E_NOT_NEUTRAL;
+        else if (res->status & 8) r->status = HSMA_E_COINCIDENT;
         sv->evpool.push_back(r->ev);
         r->ev = nullptr;
         sv->arena->release(r->off);
@@ -538,6 +558,8 @@ static hsma_status tick(hsma_server_s* sv) {
     if (nA) {
         hipLaunchKernelGGL(k_g_zero, dim3(nA), dim3(64), 0, s, dA);
         hipLaunchKernelGGL(k_g_prep, dim3(maxA_blk, nA), dim3(SWG), 0, s, dA);
+        hipLaunchKernelGGL(k_g_dup_clear, dim3(maxA_blk, nA), dim3(SWG), 0, s, dA);
+        hipLaunchKernelGGL(k_g_dup, dim3(maxA_blk, nA), dim3(SWG), 0, s, dA);
         hipLaunchKernelGGL(k_g_net, dim3(1, nA), dim3(SWG), 0, s, dA);
         if (f32) hipLaunchKernelGGL(k_g_rec32, dim3(maxA_ns, nA), dim3(SWG), 0, s, dA);
     }

@@ -24,6 +24,10 @@ struct Layout {
     size_t off_u_part = 0, off_tw = 0, off_lam64 = 0, off_lam32 = 0, off_G_part = 0,
            off_real32 = 0, off_ud = 0;
     size_t off_cnt = 0, off_imgoff = 0, off_img64 = 0, off_img32 = 0;   // sphere near set
+    // exact-coincidence check: open-addressing table of dup_T int slots (a
+    // power of two >= 2N), each -1 or the index of a particle
+    size_t off_dup = 0;
+    int64_t dup_T = 0;
     int64_t img_max = 0;
     // near sum with each unordered pair once (block near set, any boundary
     // condition and precision); its accumulators replace the chunk partials

@@ -56,9 +56,9 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     const int ns_pairs = sphere ? (int)std::min<int64_t>(ly.img_max, INT32_MAX) : ly.ns;
     ly.g_rhs = pair_geometry(pl->nchk, ns_pairs, tpl_rhs, pl->ncu);
     ly.g_near = pair_geometry(ly.N, ns_pairs, tpl_near, pl->ncu);
-    // Pair-once near sum: faster than the tiles from about 8e3 particles in
-    // single and 5e3 in double precision (measured; in the batched server too,
-    // where a request's rounds run between the tick's grouped launches).
+    // Pair-once near sum: faster than the tiles from 1024 particles in either
+    // precision (measured; in the batched server too, where a request's rounds
+    // run between the tick's grouped launches).
     // HSMA_SYM=0 turns it off, HSMA_SYM=1 forces it (any N); HSMA_SYM_MIN
     // overrides the threshold.
     {
@@ -90,6 +90,9 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     if (ly.n_eblk < 1) ly.n_eblk = 1;
     ly.off_eblk = take(sizeof(double) * 3 * (size_t)ly.n_eblk);
     ly.off_result = take(sizeof(Result));
+    ly.dup_T = 64;
+    while (ly.dup_T < 2 * (int64_t)ly.N) ly.dup_T *= 2;
+    ly.off_dup = take(sizeof(int) * (size_t)ly.dup_T);
     if (sphere) {
         ly.off_cnt = take(sizeof(int) * (size_t)ly.ns);
         ly.off_imgoff = take(sizeof(int) * ((size_t)ly.ns + 1));
@@ -115,6 +118,18 @@ __global__ void k_prep(const double* __restrict__ x, const double* __restrict__ 
                        double L, double4* __restrict__ src, int* __restrict__ status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) prep_body(i, x, q, N, bc, L, src, status);
+}
+
+__global__ void k_dup_clear(int* __restrict__ tab, int64_t T) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T;
+         t += (int64_t)gridDim.x * blockDim.x)
+        tab[t] = -1;
+}
+
+__global__ void k_dup_insert(const double4* __restrict__ src, int N, int* __restrict__ tab,
+                             uint32_t mask, int* __restrict__ status) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) dup_insert_body(i, src, tab, mask, status);
 }
 
 __global__ void k_zero_result(Result* r) {
@@ -297,6 +312,14 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, s, res);
     hipLaunchKernelGGL(k_prep, dim3((N + WG - 1) / WG), dim3(WG), 0, s, x, q, N, pl->bc, pl->L,
                        src64, &res->status);
+    {
+        // two charges at the same position (their interaction is infinite)
+        int* dup = (int*)(ws + ly.off_dup);
+        const int64_t nblk = std::min<int64_t>((ly.dup_T + WG - 1) / WG, 65536);
+        hipLaunchKernelGGL(k_dup_clear, dim3((unsigned)nblk), dim3(WG), 0, s, dup, ly.dup_T);
+        hipLaunchKernelGGL(k_dup_insert, dim3((N + WG - 1) / WG), dim3(WG), 0, s, src64, N, dup,
+                           (uint32_t)(ly.dup_T - 1), &res->status);
+    }
     const NearFix fix = near_fix(pl, f32);
     if (fix.qc != 0.0)
         hipLaunchKernelGGL(k_net_charge, dim3(1), dim3(SWG), 0, s, src64, N, &res->qnet);
@@ -435,6 +458,7 @@ hsma_status read_result(const Layout& ly, char* ws, hipStream_t s, double* energ
     if (h.status & 1) return fail(HSMA_E_INVALID, "non-finite position or charge");
     if (h.status & 2) return fail(HSMA_E_OUT_OF_BOX, "position on or outside a grounded wall");
     if (h.status & 4) return fail(HSMA_E_NOT_NEUTRAL, "periodic/slab system is not neutral");
+    if (h.status & 8) return fail(HSMA_E_COINCIDENT, "two charges at the same position");
     if (energy) *energy = h.energy;
     return HSMA_OK;
 }

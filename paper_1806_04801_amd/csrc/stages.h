@@ -45,6 +45,40 @@ __device__ __forceinline__ void prep_body(int i, const double* __restrict__ x,
     if (bc == HSMA_BC_SLAB_METALLIC_Z) src[N + i] = make_double4(c[0], c[1], -c[2], -qi);
 }
 
+// Exact coincidence of two charges, the one configuration whose Coulomb
+// energy is infinite.  Particle i is
+// entered, by its centred and wrapped position (the one the pair kernels
+// use), into an open-addressing table of mask + 1 slots (a power of two at
+// least twice the particle count, all -1 beforehand) with linear probing; a
+// slot already holding a particle at the same position sets bit 8 of status.
+// Every insertion ends within mask + 1 probes, since the table is never full.
+__device__ __forceinline__ uint32_t point_slot(const double4& p, uint32_t mask) {
+    // + 0.0 turns -0.0 into +0.0, so that equal positions hash alike; the
+    // multipliers and the final mix are those of SplitMix64 (Steele et al. 2014)
+    uint64_t h = (uint64_t)__double_as_longlong(p.x + 0.0) * 0x9E3779B97F4A7C15ull;
+    h = (h ^ (uint64_t)__double_as_longlong(p.y + 0.0)) * 0xBF58476D1CE4E5B9ull;
+    h = (h ^ (uint64_t)__double_as_longlong(p.z + 0.0)) * 0x94D049BB133111EBull;
+    h ^= h >> 31;
+    return (uint32_t)h & mask;
+}
+
+__device__ __forceinline__ void dup_insert_body(int i, const double4* __restrict__ src,
+                                                int* __restrict__ tab, uint32_t mask,
+                                                int* __restrict__ status) {
+    const double4 p = src[i];
+    uint32_t slot = point_slot(p, mask);
+    for (uint64_t probe = 0; probe <= (uint64_t)mask; ++probe) {
+        const int j = atomicCAS(&tab[slot], -1, i);
+        if (j < 0) return;
+        const double4 o = src[j];
+        if (o.x == p.x && o.y == p.y && o.z == p.z) {
+            atomicOr(status, 8);
+            return;
+        }
+        slot = (slot + 1) & mask;
+    }
+}
+
 // Single-precision record (see Rec32) of point i: coordinates in units of L,
 // hi part rounded to a multiple of 2^-24, lo part the float remainder.
 __device__ __forceinline__ void rec32_body(int i, const double4* __restrict__ p, double L,

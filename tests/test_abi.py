@@ -38,6 +38,7 @@ def test_status_strings_without_gpu():
     lib = hsma.load()
     assert lib.hsma_status_string(0) == b"ok"
     assert lib.hsma_status_string(-2) == b"system not neutral"
+    assert lib.hsma_status_string(-4) == b"two charges at the same position"
     assert lib.hsma_version() == 2
 
 

@@ -127,3 +127,56 @@ def test_invalid_tile_overrides_are_ignored(hs, monkeypatch, value):
     e1, phi1, F1 = plan.energy_forces(xd, qd)
     assert e1 == e0
     assert torch.equal(phi1, phi0) and torch.equal(F1, F0)
+
+
+def _coincident(bc, n=300, seed=23):
+    """n charges of which particles 3 and 7 sit at exactly the same position."""
+    x, q = (W.slab_charges(n, 1.0, seed) if bc == 2 else W.uniform_neutral(n, 1.0, seed))
+    x = np.array(x, dtype=np.float64)
+    x[7] = x[3]
+    return x, np.array(q, dtype=np.float64)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_coincident_charges_rejected(hs, bc, precision):
+    """Two charges at the same position have an infinite interaction: every
+    entry point returns HSMA_E_COINCIDENT (-4) instead of a result."""
+    announce("edge coincident bc=%d precision=%d" % (bc, precision))
+    x, q = _coincident(bc)
+    plan = hs.Plan(1.0, bc, 8, 600, 300, 2.7, precision=precision)
+    xd = torch.tensor(x, device="cuda")
+    qd = torch.tensor(q, device="cuda")
+    with pytest.raises(hs.HsmaError) as ei:
+        plan.energy_forces(xd, qd)
+    assert ei.value.status == -4
+    with pytest.raises(hs.HsmaError) as ei:
+        plan.energy_forces_host(x, q)
+    assert ei.value.status == -4
+    with pytest.raises(hs.HsmaError) as ei:
+        plan.energy_grad(xd, qd)
+    assert ei.value.status == -4
+    # the same plan and workspace size then solve a valid system
+    x[7] = 0.5 * (x[3] + x[8])
+    e, phi, F = plan.energy_forces(torch.tensor(x, device="cuda"), qd)
+    assert np.isfinite(e)
+
+
+def test_coincident_through_periodic_wrap_and_close_pairs(hs):
+    """Periodic positions one box length apart are the same position; a pair
+    1e-9 apart is not, and is solved as usual (against the oracle)."""
+    announce("edge coincident periodic wrap")
+    x, q = W.uniform_neutral(300, 1.0, seed=29)
+    x = np.array(x, dtype=np.float64)
+    x[3] = [0.25, 0.5, 0.125]          # dyadic, so that the wrap is exact
+    x[7] = [1.25, 0.5, -0.875]
+    plan = hs.Plan(1.0, 0, 8, 600, 300, 2.7)
+    qd = torch.tensor(q, device="cuda")
+    with pytest.raises(hs.HsmaError) as ei:
+        plan.energy_forces(torch.tensor(x, device="cuda"), qd)
+    assert ei.value.status == -4
+    x[7] = x[3] + [1e-9, 0.0, 0.0]
+    ref = oracle.solve(oracle.make_plan(1.0, 0, 8, 600, 300, 2.7), x, q)
+    e, phi, F = plan.energy_forces(torch.tensor(x, device="cuda"), qd)
+    assert abs(e - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+    assert rel_max(F.cpu().numpy(), ref["forces"]) <= 1e-10

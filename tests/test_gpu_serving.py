@@ -213,3 +213,28 @@ def test_refinement_in_double_precision(hs, plans):
     assert srv1.stats()["refined"] == n_ref
     with pytest.raises(hs.HsmaError):
         hs.Server(memory_bytes=2 << 30, max_active=8, precision=hs.FP32_COMP, refine_below=-1.0)
+
+
+def test_server_rejects_coincident_request_alone(hs):
+    """A request with two charges at the same position fails with
+    HSMA_E_COINCIDENT (-4); the requests around it complete as usual."""
+    announce("serving coincident request")
+    plan = hs.Plan(1.0, 0, 12, 1440, 1440, 2.7, precision=hs.FP32_COMP)
+    good = [W.uniform_neutral(2000, 1.0, seed=s) for s in (31, 32)]
+    bad_x, bad_q = W.uniform_neutral(3000, 1.0, seed=33)
+    bad_x = np.array(bad_x)
+    bad_x[100] = bad_x[2500]
+    srv = hs.Server(memory_bytes=2 << 30, max_active=8, precision=hs.FP32_COMP)
+    ids = [srv.submit(plan, *good[0]), srv.submit(plan, bad_x, bad_q), srv.submit(plan, *good[1])]
+    for rid in ids:
+        srv.wait(rid)
+    for rid, (x, q) in ((ids[0], good[0]), (ids[2], good[1])):
+        ok, e, *_ = srv.result(rid, len(q))
+        ref, phi, _ = plan.energy_forces(torch.tensor(x, device="cuda"),
+                                         torch.tensor(q, device="cuda"))
+        scale = 0.5 * float(np.sum(np.abs(np.asarray(q) * phi.cpu().numpy())))
+        assert ok and abs(e - ref) <= 1e-6 * scale
+    with pytest.raises(hs.HsmaError) as ei:
+        srv.result(ids[1], len(bad_q))
+    assert ei.value.status == -4
+    srv.close()
