@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--workload", default="periodic1m")
     ap.add_argument("--precision", default=None, help="fp64 or fp32 (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-entry", type=int, default=0,
+                    help="also time this many calls of the host-array entry point (PCIe copies and "
+                         "its own device allocation included); reported in config, never as value")
     ap.add_argument("--cpu-targets", type=int, default=2048,
                     help="particles in the oracle sample (about 17 s on 16 host threads at 1e6)")
     ap.add_argument("--requests", type=int, default=1024, help="serving: trace length")
@@ -326,6 +329,19 @@ def main():
     hsma.timing_enable(False)
     kt = hsma.timing_read()
 
+    host_entry = None
+    if args.host_entry > 0:
+        import numpy as np
+        xh = np.ascontiguousarray(x, dtype=np.float64)
+        qh = np.ascontiguousarray(q, dtype=np.float64)
+        plan.energy_forces_host(xh, qh)
+        t1 = time.perf_counter()
+        for i in range(args.host_entry):
+            plan.energy_forces_host(xh, qh)
+            print("host-entry call %d done" % i, file=sys.stderr, flush=True)
+        host_entry = {"calls": args.host_entry,
+                      "ms_per_call": 1e3 * (time.perf_counter() - t1) / args.host_entry}
+
     ns = 2 * n if cfg["bc"] == 2 else n
     if near_mode == hsma.NEAR_SPHERE:
         n_img = sphere_image_count(x, cfg)
@@ -384,6 +400,9 @@ def main():
                                         "pair-once" if sched["kind"] == 1 else "tiles"),
         },
     }
+    if host_entry is not None:
+        host_entry["pairs_per_s"] = pairs_step / (host_entry["ms_per_call"] / 1e3)
+        rec["config"]["host_entry"] = host_entry
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(x, q, cfg, args.cpu_targets)
     if args.paper_time:
