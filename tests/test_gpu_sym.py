@@ -303,17 +303,22 @@ def test_near_schedule_query(hs, monkeypatch):
     plan = hs.Plan(1.0, 0, 12, 1000, 600, 2.7, precision=hs.FP32_COMP)
     small = plan.near_schedule(1000)
     assert small["kind"] == 0 and small["launches"] == 0
-    for n in (1024, 3000, 5120, 10000, 40001, 200000, 10 ** 6):
-        sc = plan.near_schedule(n)
-        assert sc["kind"] == 1 and sc["rows_per_lane"] == 1
-        assert sc["block"] == 64 * sc["slices"] and 1 <= sc["slices"] <= 64
-        assert sc["blocks"] * sc["block"] >= n > (sc["blocks"] - 1) * sc["block"]
-        assert sc["launches"] == sc["blocks"] + (sc["blocks"] & 1)
-        # at most 64 column parts of at least 16 columns
-        assert 1 <= sc["parts"] <= 64 and sc["block"] // sc["parts"] >= 16
-        # an even block count (no idle block per round) unless slices are at
-        # their limit
-        assert sc["blocks"] % 2 == 0 or sc["slices"] == 64, (n, sc)
+    # every boundary condition (their kernels differ in resident waves, which
+    # sets the part count) and both precisions
+    plans = [plan] + [hs.Plan(1.0, bc, 12, 1000, 600, 2.7, precision=pr)
+                      for bc, pr in ((1, hs.FP32_COMP), (2, hs.FP32_COMP), (0, hs.FP64), (1, hs.FP64))]
+    for pl in plans:
+        for n in (1024, 3000, 5120, 10000, 40001, 200000, 10 ** 6):
+            sc = pl.near_schedule(n)
+            assert sc["kind"] == 1 and sc["rows_per_lane"] == 1
+            assert sc["block"] == 64 * sc["slices"] and 1 <= sc["slices"] <= 64
+            assert sc["blocks"] * sc["block"] >= n > (sc["blocks"] - 1) * sc["block"]
+            assert sc["launches"] == sc["blocks"] + (sc["blocks"] & 1)
+            # at most 64 column parts of at least 16 columns
+            assert 1 <= sc["parts"] <= 64 and sc["block"] // sc["parts"] >= 16
+            # an even block count (no idle block per round) unless slices are
+            # at their limit
+            assert sc["blocks"] % 2 == 0 or sc["slices"] == 64, (n, sc)
     monkeypatch.setenv("HSMA_SYM", "0")
     assert plan.near_schedule(10 ** 6)["kind"] == 0
     monkeypatch.setenv("HSMA_SYM", "1")
