@@ -142,7 +142,7 @@ typedef struct {
 /* Status text and the calling thread's last error message.  hsma_version()
    is the version of this interface; it changes whenever a declaration or a
    struct layout in this header changes (2: the near-schedule query and the
-   server's double-precision refinement). */
+   server's double-precision refinement; 3: HSMA_E_COINCIDENT). */
 const char* hsma_status_string(int status);
 const char* hsma_last_error(void);
 int hsma_version(void);

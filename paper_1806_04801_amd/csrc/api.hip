@@ -81,7 +81,7 @@ const char* hsma_status_string(int st) {
 
 const char* hsma_last_error(void) { return g_last_error.c_str(); }
 
-int hsma_version(void) { return 2; }
+int hsma_version(void) { return 3; }
 
 hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     if (d == nullptr || out == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
