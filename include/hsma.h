@@ -86,7 +86,10 @@ typedef enum {
     HSMA_E_COINCIDENT = -4,   /* two charges at exactly the same position (after periodic wrapping) */
     HSMA_E_NOMEM = -5,        /* device allocation failed or workspace too small */
     HSMA_E_DEVICE = -6,       /* HIP runtime error */
-    HSMA_E_ILLCOND = -7       /* least-squares matrix numerically rank deficient */
+    HSMA_E_ILLCOND = -7,      /* least-squares matrix numerically rank deficient */
+    HSMA_E_NONFINITE = -8     /* the energy, a potential or a force came out non-finite although
+                                 the input passed every check (e.g. two distinct charges closer
+                                 than single precision resolves); outputs are not usable */
 } hsma_status;
 
 typedef struct hsma_plan_s* hsma_plan;
@@ -142,7 +145,8 @@ typedef struct {
 /* Status text and the calling thread's last error message.  hsma_version()
    is the version of this interface; it changes whenever a declaration or a
    struct layout in this header changes (2: the near-schedule query and the
-   server's double-precision refinement; 3: HSMA_E_COINCIDENT). */
+   server's double-precision refinement; 3: HSMA_E_COINCIDENT; 4:
+   HSMA_E_NONFINITE). */
 const char* hsma_status_string(int status);
 const char* hsma_last_error(void);
 int hsma_version(void);

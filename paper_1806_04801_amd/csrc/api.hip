@@ -75,13 +75,14 @@ const char* hsma_status_string(int st) {
         case HSMA_E_NOMEM: return "out of device memory or workspace too small";
         case HSMA_E_DEVICE: return "HIP runtime error";
         case HSMA_E_ILLCOND: return "fitting matrix rank deficient";
+        case HSMA_E_NONFINITE: return "non-finite result";
         default: return "unknown status";
     }
 }
 
 const char* hsma_last_error(void) { return g_last_error.c_str(); }
 
-int hsma_version(void) { return 3; }
+int hsma_version(void) { return 4; }
 
 hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     if (d == nullptr || out == nullptr) return fail(HSMA_E_INVALID, "NULL argument");

@@ -402,10 +402,11 @@ static void retire(hsma_server_s* sv) {
         }
         const Result* res = (const Result*)r->h_out;
         r->energy = res->energy;
-        if (res->status & 1) r->status = HSMA_E_INVALID;
-        else if (res->status & 2) r->status = HSMA_E_OUT_OF_BOX;
-        else if (res->status & 4) r->status = HSMA_E_NOT_NEUTRAL;
-        else if (res->status & 8) r->status = HSMA_E_COINCIDENT;
+        {
+            const char* msg = nullptr;
+            const hsma_status st = status_of_bits(res->status, &msg);
+            if (st != HSMA_OK) r->status = st;
+        }
         sv->evpool.push_back(r->ev);
         r->ev = nullptr;
         sv->arena->release(r->off);

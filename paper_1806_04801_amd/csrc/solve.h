@@ -10,7 +10,7 @@ struct Result {
     double qsum;
     double qabs;
     double qnet;  // net charge, summed before the finalize stage when NearFix::qc != 0
-    int status;   // bit 0 non-finite input, bit 1 outside the walls, bit 2 not neutral
+    int status;   // RS_* bits (result_status.h)
     int pad;
 };
 

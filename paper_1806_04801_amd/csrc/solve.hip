@@ -455,10 +455,9 @@ hsma_status read_result(const Layout& ly, char* ws, hipStream_t s, double* energ
     Result h;
     CK(hipMemcpyAsync(&h, ws + ly.off_result, sizeof(Result), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
-    if (h.status & 1) return fail(HSMA_E_INVALID, "non-finite position or charge");
-    if (h.status & 2) return fail(HSMA_E_OUT_OF_BOX, "position on or outside a grounded wall");
-    if (h.status & 4) return fail(HSMA_E_NOT_NEUTRAL, "periodic/slab system is not neutral");
-    if (h.status & 8) return fail(HSMA_E_COINCIDENT, "two charges at the same position");
+    const char* msg = nullptr;
+    const hsma_status st = status_of_bits(h.status, &msg);
+    if (st != HSMA_OK) return fail(st, msg);
     if (energy) *energy = h.energy;
     return HSMA_OK;
 }

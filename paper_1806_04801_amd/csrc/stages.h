@@ -4,6 +4,7 @@
 #pragma once
 
 #include "hsma_internal.h"
+#include "result_status.h"
 #include "solve.h"
 
 namespace hsma {
@@ -40,7 +41,7 @@ __device__ __forceinline__ void prep_body(int i, const double* __restrict__ x,
         }
         if (!(c[2] > 0.0 && c[2] < h)) bad |= 2;
     }
-    if (bad) atomicOr(status, bad);
+    if (bad) atomicOr(status, bad);   // RS_BAD_INPUT, RS_OUT_OF_BOX
     src[i] = make_double4(c[0], c[1], c[2], qi);
     if (bc == HSMA_BC_SLAB_METALLIC_Z) src[N + i] = make_double4(c[0], c[1], -c[2], -qi);
 }
@@ -50,7 +51,7 @@ __device__ __forceinline__ void prep_body(int i, const double* __restrict__ x,
 // entered, by its centred and wrapped position (the one the pair kernels
 // use), into an open-addressing table of mask + 1 slots (a power of two at
 // least twice the particle count, all -1 beforehand) with linear probing; a
-// slot already holding a particle at the same position sets bit 8 of status.
+// slot already holding a particle at the same position sets RS_COINCIDENT.
 // Every insertion ends within mask + 1 probes, since the table is never full.
 __device__ __forceinline__ uint32_t point_slot(const double4& p, uint32_t mask) {
     // + 0.0 turns -0.0 into +0.0, so that equal positions hash alike; the
@@ -72,7 +73,7 @@ __device__ __forceinline__ void dup_insert_body(int i, const double4* __restrict
         if (j < 0) return;
         const double4 o = src[j];
         if (o.x == p.x && o.y == p.y && o.z == p.z) {
-            atomicOr(status, 8);
+            atomicOr(status, RS_COINCIDENT);
             return;
         }
         slot = (slot + 1) & mask;
@@ -257,7 +258,12 @@ __device__ __forceinline__ void finalize_body(int blk, const double* __restrict_
         if (dbg_po) dbg_po[i] = vo[0];
         if (dbg_fn) { dbg_fn[3 * i] = vn[1]; dbg_fn[3 * i + 1] = vn[2]; dbg_fn[3 * i + 2] = vn[3]; }
         if (dbg_fo) { dbg_fo[3 * i] = vo[1]; dbg_fo[3 * i + 1] = vo[2]; dbg_fo[3 * i + 2] = vo[3]; }
-        e = qi * p;
+        // a non-finite output (e.g. two distinct charges closer than the
+        // single-precision records resolve) makes the energy NaN, which the
+        // energy stage reports as RS_NONFINITE
+        const bool finite = isfinite(p) && isfinite(vn[1] + vo[1]) && isfinite(vn[2] + vo[2]) &&
+                            isfinite(vn[3] + vo[3]);
+        e = finite ? qi * p : __builtin_nan("");
         qs = qi;
         qa = fabs(qi);
     }
@@ -284,7 +290,8 @@ __device__ __forceinline__ void energy_body(const double* __restrict__ eblk, int
         res->energy = 0.5 * a;
         res->qsum = b;
         res->qabs = c;
-        if (need_neutral && fabs(b) > 1e-12 * c) res->status |= 4;
+        if (need_neutral && fabs(b) > 1e-12 * c) res->status |= RS_NOT_NEUTRAL;
+        if (!isfinite(a)) res->status |= RS_NONFINITE;
     }
 }
 

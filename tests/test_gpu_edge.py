@@ -180,3 +180,41 @@ def test_coincident_through_periodic_wrap_and_close_pairs(hs):
     e, phi, F = plan.energy_forces(torch.tensor(x, device="cuda"), qd)
     assert abs(e - ref["energy"]) <= 1e-10 * abs(ref["energy"])
     assert rel_max(F.cpu().numpy(), ref["forces"]) <= 1e-10
+
+
+def test_non_finite_result_reported(hs):
+    """Two distinct charges 2^-53 apart whose single-precision records are
+    identical (the difference lies below the records' resolution) pass the
+    coincidence check, which compares double positions.  In different blocks
+    of the pair-once kernel their single-precision distance is zero and the
+    result is not finite: the device and host entry points and the server
+    return HSMA_E_NONFINITE (-8) instead of HSMA_OK.  The double-precision
+    path resolves the pair and returns a finite energy."""
+    announce("edge non-finite result fp32")
+    x, q = W.uniform_neutral(3000, 1.0, seed=41)
+    x = np.array(x, dtype=np.float64)
+    base = np.array([0.3125 + 2.0 ** -26, 0.40625, 0.59375])
+    x[100] = base
+    x[2500] = base + np.array([2.0 ** -53, 0.0, 0.0])
+    assert x[100, 0] != x[2500, 0]
+    p32 = hs.Plan(1.0, 0, 8, 600, 300, 2.7, precision=hs.FP32_COMP)
+    sched = p32.near_schedule(3000)
+    assert sched["kind"] == 1 and sched["blocks"] >= 2 and 2500 >= sched["block"] > 100
+    xd = torch.tensor(x, device="cuda")
+    qd = torch.tensor(q, device="cuda")
+    with pytest.raises(hs.HsmaError) as ei:
+        p32.energy_forces(xd, qd)
+    assert ei.value.status == -8
+    with pytest.raises(hs.HsmaError) as ei:
+        p32.energy_forces_host(x, q)
+    assert ei.value.status == -8
+    srv = hs.Server(memory_bytes=1 << 30, max_active=4, precision=hs.FP32_COMP, refine_below=3e-3)
+    rid = srv.submit(p32, x, q)
+    srv.wait(rid)
+    with pytest.raises(hs.HsmaError) as ei:
+        srv.result(rid, len(q))
+    assert ei.value.status == -8
+    srv.close()
+    p64 = hs.Plan(1.0, 0, 8, 600, 300, 2.7, precision=hs.FP64)
+    e, phi, F = p64.energy_forces(xd, qd)
+    assert np.isfinite(e) and torch.isfinite(phi).all() and torch.isfinite(F).all()
