@@ -41,6 +41,20 @@ def hs():
     return hsma
 
 
+@pytest.fixture(scope="module")
+def e64_cache():
+    """Double-precision GPU energies of the full-size workloads, computed in
+    this session (by the FP64 test, or on first use)."""
+    return {}
+
+
+def energy64(hs, cache, name):
+    if name not in cache:
+        announce("%s fp64 reference energy" % name)
+        cache[name] = run(hs, name, hs.FP64)[1]
+    return cache[name]
+
+
 def run(hs, name, precision, grad=False):
     c = W.CONFIGS[name]
     x, q = W.make_inputs(name)
@@ -59,7 +73,7 @@ def report(tag, **errs):
     print("[fullsize] %s: %s" % (tag, " ".join("%s %.3e" % kv for kv in errs.items())), flush=True)
 
 
-def test_periodic1m_fp64(hs):
+def test_periodic1m_fp64(hs, e64_cache):
     g = golden("periodic1m")
     announce("periodic1m fp64 full size")
     q, e, phi, F, inter = run(hs, "periodic1m", hs.FP64)
@@ -71,10 +85,10 @@ def test_periodic1m_fp64(hs):
     assert errs["phi"] <= 1e-10 and errs["F"] <= 1e-10
     pe = 0.5 * np.sum(q[idx] * phi[idx])
     assert abs(pe - g["partial_energy"]) <= 1e-10 * np.sum(np.abs(q[idx] * phi[idx]))
-    np.save("/tmp/periodic1m_fp64_energy.npy", np.array([e]))
+    e64_cache["periodic1m"] = e
 
 
-def test_periodic1m_fp32_comp(hs):
+def test_periodic1m_fp32_comp(hs, e64_cache):
     """The gate of the FP32-compensated path: |dE|/|E| <= 1e-5 against the FP64
     GPU path (full energy) and the oracle (sampled potentials and forces)."""
     g = golden("periodic1m")
@@ -85,20 +99,18 @@ def test_periodic1m_fp32_comp(hs):
     errs = dict(partialE=abs(pe - g["partial_energy"]) / (0.5 * np.sum(np.abs(q[idx] * phi[idx]))),
                 phi=rel_max(phi[idx], g["phi"], rms(g["phi"])), F=rel_max(F[idx], g["forces"]),
                 b=rel_max(inter["b"], g["b"]))
-    path = "/tmp/periodic1m_fp64_energy.npy"
-    if os.path.exists(path):
-        e64 = float(np.load(path)[0])
-        errs["E_vs_fp64"] = abs(e - e64) / abs(e64)
-        assert errs["E_vs_fp64"] <= 1e-5
-        # the shifted single-precision image sums (7.8e-8 measured; 8.2e-7
-        # with the plain sequential image sum)
-        assert errs["E_vs_fp64"] <= 3e-7
+    e64 = energy64(hs, e64_cache, "periodic1m")
+    errs["E_vs_fp64"] = abs(e - e64) / abs(e64)
     report("periodic1m fp32", **errs)
+    assert errs["E_vs_fp64"] <= 1e-5
+    # the shifted single-precision image sums (7.8e-8 measured; 8.2e-7 with
+    # the plain sequential image sum)
+    assert errs["E_vs_fp64"] <= 3e-7
     assert errs["partialE"] <= 1e-5 and errs["phi"] <= 1e-5 and errs["F"] <= 1e-4
     assert errs["phi"] <= 3e-6   # 1.1e-6 measured; 5.2e-6 with the plain image sum
 
 
-def test_slab200k_fp64(hs):
+def test_slab200k_fp64(hs, e64_cache):
     g = golden("slab200k")
     announce("slab200k fp64 full size")
     q, e, phi, F, inter = run(hs, "slab200k", hs.FP64)
@@ -110,10 +122,10 @@ def test_slab200k_fp64(hs):
     report("slab200k fp64", **errs)
     assert errs["b"] <= 1e-10 and errs["A"] <= 1e-8
     assert errs["partialE"] <= 1e-10 and errs["phi"] <= 1e-10 and errs["F"] <= 1e-10
-    np.save("/tmp/slab200k_fp64_energy.npy", np.array([e]))
+    e64_cache["slab200k"] = e
 
 
-def test_slab200k_fp32(hs):
+def test_slab200k_fp32(hs, e64_cache):
     """FP32-compensated slab: full energy against the FP64 GPU path (gate
     1e-5), sampled potentials and forces against the oracle."""
     g = golden("slab200k")
@@ -124,14 +136,12 @@ def test_slab200k_fp32(hs):
     errs = dict(partialE=abs(pe - g["partial_energy"]) / (0.5 * np.sum(np.abs(q[idx] * phi[idx]))),
                 phi=rel_max(phi[idx], g["phi"], rms(g["phi"])), F=rel_max(F[idx], g["forces"]),
                 b=rel_max(inter["b"], g["b"]))
-    path = "/tmp/slab200k_fp64_energy.npy"
-    if os.path.exists(path):
-        e64 = float(np.load(path)[0])
-        errs["E_vs_fp64"] = abs(e - e64) / abs(e64)
-        assert errs["E_vs_fp64"] <= 1e-5
-        # shifted image sums: 1.6e-8 measured, 1.4e-7 with the plain sum
-        assert errs["E_vs_fp64"] <= 6e-8
+    e64 = energy64(hs, e64_cache, "slab200k")
+    errs["E_vs_fp64"] = abs(e - e64) / abs(e64)
     report("slab200k fp32", **errs)
+    assert errs["E_vs_fp64"] <= 1e-5
+    # shifted image sums: 1.6e-8 measured, 1.4e-7 with the plain sum
+    assert errs["E_vs_fp64"] <= 6e-8
     assert errs["partialE"] <= 1e-5 and errs["phi"] <= 1e-5 and errs["F"] <= 1e-4
     assert errs["phi"] <= 3e-6   # 1.1e-6 measured; 5.4e-6 with the plain image sum
 

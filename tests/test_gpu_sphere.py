@@ -47,8 +47,9 @@ def test_sphere_near_set_vs_oracle(hs, bc, n, p, alpha, precision):
         assert rel_max(phi, ref["phi"], rms(ref["phi"])) <= 1e-10
         assert rel_max(F, ref["forces"]) <= 1e-10
     else:
-        scale = 0.5 * np.sum(np.abs(q * ref["phi"]))
-        assert abs(e - ref["energy"]) <= 1e-6 * scale
+        # the single-precision gate: relative energy error 1e-5
+        print("sphere fp32: |dE|/|E| %.3e" % (abs(e - ref["energy"]) / abs(ref["energy"])))
+        assert abs(e - ref["energy"]) <= 1e-5 * abs(ref["energy"])
         assert rel_max(phi, ref["phi"], rms(ref["phi"])) <= 1e-5
         assert rel_max(F, ref["forces"]) <= 1e-4
 
@@ -110,8 +111,8 @@ def test_direct_far_field_vs_oracle(hs, bc, p, precision):
         assert abs(e - ref["energy"]) <= 1e-10 * abs(ref["energy"])
         assert rel_max(F.cpu().numpy(), ref["forces"]) <= 1e-10
     else:
-        scale = 0.5 * np.sum(np.abs(q * ref["phi"]))
-        assert abs(e - ref["energy"]) <= 1e-6 * scale
+        print("direct fp32: |dE|/|E| %.3e" % (abs(e - ref["energy"]) / abs(ref["energy"])))
+        assert abs(e - ref["energy"]) <= 1e-5 * abs(ref["energy"])
     # and it agrees with the surface mapping to the quadrature error (in FP32
     # mode the coefficients carry the single-precision right-hand side)
     sref = oracle.solve(oracle.make_plan(1.0, bc, p, 2500, K, 2.7), x, q)

@@ -19,6 +19,17 @@ def test_serving_arena_allocator(tmp_path):
         assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
 
 
+def test_result_status_mapping(tmp_path):
+    """Status bits raised by the update-step kernels map to the C-ABI statuses
+    (input errors before a non-finite result), as read_result and the server
+    apply them; compiled on the host from the HIP-free header."""
+    exe = tmp_path / "status_check"
+    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                           os.path.join(HERE, "status_check.cpp"), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
+
+
 @pytest.mark.parametrize("bc", [0, 1, 2])
 def test_bench_sphere_image_count(bc):
     """bench.py counts the sphere near set (for its pair totals) exactly as the
@@ -132,3 +143,29 @@ def test_header_documents_every_environment_override():
     header = open(os.path.join(root, "include", "hsma.h")).read()
     missing = sorted(n for n in names if not re.search(r"\b%s\b" % n, header))
     assert not missing, missing
+
+
+@pytest.mark.parametrize("n,block,bc", [(10, 4, 0), (3000, 1536, 1), (1000, 1000, 0), (77, 20, 2)])
+def test_bench_counts_evaluated_near_pairs(n, block, bc):
+    """bench.py's roofline charges 20 flops per pair-image the pair-once
+    kernel evaluates: each cross-block unordered pair once, every ordered pair
+    (self included) inside a diagonal block; counted here by brute force."""
+    import bench
+    blocks = (n + block - 1) // block
+    sched = {"kind": 1, "block": block, "blocks": blocks}
+    blk = [i // block for i in range(n)]
+    cnt = 0
+    for i in range(n if n <= 100 else 0):
+        for j in range(n):
+            if blk[i] == blk[j]:
+                cnt += 1
+            elif i < j:
+                cnt += 1
+    if n > 100:
+        sizes = [min(block, n - b * block) for b in range(blocks)]
+        cnt = sum(s * s for s in sizes) + sum(sizes[a] * sizes[b] for a in range(blocks)
+                                              for b in range(a + 1, blocks))
+    imgs = 54 if bc == 2 else 27
+    assert bench.near_evaluated_pairs(n, {"bc": bc}, sched) == imgs * cnt
+    tiles = bench.near_evaluated_pairs(n, {"bc": bc}, {"kind": 0})
+    assert tiles == 27.0 * n * (2 * n if bc == 2 else n)
