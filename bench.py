@@ -10,7 +10,11 @@ in HBM before the timed region.
 
 Prints one JSON line.  `value` = pair interactions per second of the whole
 step (near + right-hand side + surface).  `roofline` is for the near-field
-pair kernel, timed with HIP events on its own stream inside the library.
+pair kernel, timed with HIP events on its own stream inside the library:
+20 flops per pair-image the kernel evaluates.  `cpu_baseline` is the oracle
+timed stage by stage on bounded samples; `serving` (default workload) is the
+serving stream: solves/s of the batched server and of one solve per request
+in both precisions, and p50/p99 latency.
 """
 import argparse
 import json
@@ -23,13 +27,16 @@ sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector peak
-NEAR_FLOPS_PER_PAIR = 20     # potential + field, rsqrt counted as one flop
-# Pair-once near kernel: one evaluation (20 flops) serves both directions and
-# adds 8 (4 products and 4 sums for the reverse terms), 28 per unordered pair,
-# i.e. 14 per ordered pair.  Its diagonal blocks are evaluated per ordered pair
-# (20 flops each) and are under 1% of the pairs; they are counted at 14 too,
-# which understates the work.
-NEAR_FLOPS_PER_PAIR_ONCE = 14
+# Algorithmic work per evaluated near pair-image (potential + field, rsqrt
+# counted as one flop).  roofline.achieved charges it per pair-image the
+# kernel evaluates: every ordered pair for the per-target tiles, every
+# unordered pair once for the pair-once kernel (whose evaluation serves both
+# directions), plus the ordered pairs inside its diagonal blocks.
+NEAR_FLOPS_PER_PAIR = 20
+# The pair-once kernel's own count of one evaluation with both directions:
+# the 20 above plus 4 products and 4 sums for the reverse terms (reported
+# beside the roofline, not as it).
+NEAR_FLOPS_PER_UNORDERED_PAIR_BOTH_DIRECTIONS = 28
 
 
 def parse():
@@ -43,8 +50,9 @@ def parse():
     ap.add_argument("--host-entry", type=int, default=0,
                     help="also time this many calls of the host-array entry point (PCIe copies and "
                          "its own device allocation included); reported in config, never as value")
-    ap.add_argument("--cpu-targets", type=int, default=2048,
-                    help="particles in the oracle sample (about 17 s on 16 host threads at 1e6)")
+    ap.add_argument("--cpu-targets", type=int, default=1024,
+                    help="particles in the oracle's near-sum sample (about 8 s on 16 host threads "
+                         "at 1e6)")
     ap.add_argument("--requests", type=int, default=1024, help="serving: trace length")
     ap.add_argument("--refine", type=float, default=3e-3,
                     help="serving: recompute in double precision the requests whose FP32 energy "
@@ -56,8 +64,9 @@ def parse():
                     help="surface dipoles exact, or the paper's two charge layers (dr = 1e-5 R_s)")
     ap.add_argument("--far", default="surface", choices=["surface", "direct"],
                     help="far field through the surface mapping, or the series evaluated directly")
-    ap.add_argument("--paper-time", action="store_true",
-                    help="report seconds per update step against the paper's GPU timing")
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="default workload: also run this many requests of the serving stream "
+                         "(object 'serving' of the line; 0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB device buffer (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -114,10 +123,9 @@ def profile_name(workload, precision_tag, kind="tiles"):
     return "%s_%s_%s" % (stem, precision_tag, workload)
 
 
-def profiled_traffic(workload, precision_tag, kind="tiles"):
-    """HBM bytes of one near-field sum (all launches of its kernel) from the
-    committed rocprofv3 counter summary, if it was taken on the current kernel
-    source."""
+def profiled_field(workload, precision_tag, kind, field):
+    """A derived figure of the committed rocprofv3 counter summary of the near
+    sum, if the counters were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", profile_name(workload, precision_tag, kind) + "_pmc.md")
     if not os.path.exists(path):
         return None
@@ -129,110 +137,212 @@ def profiled_traffic(workload, precision_tag, kind="tiles"):
     if fields.get("kernel_source_sha256_16") != kernel_source_hash(kind):
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields[field])
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(x, q, cfg, n_targets):
-    """The oracle's near-field sum (plain FP64 C, OpenMP) on a bounded sample
-    of the same workload: n_targets particles against all 27N images."""
+def profiled_traffic(workload, precision_tag, kind="tiles"):
+    """HBM bytes of one near-field sum (all launches of its kernel) from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source."""
+    return profiled_field(workload, precision_tag, kind, "hbm_bytes_per_launch")
+
+
+def near_evaluated_pairs(n, cfg, sched):
+    """Pair-images the near kernel evaluates in one sum.  Tiles: every
+    (target, source image) pair, self included.  Pair-once: each unordered
+    pair of particles in different blocks once, plus every ordered pair
+    (self included) inside the diagonal blocks; a slab pair carries two image
+    blocks (the partner's and its mirror's)."""
+    imgs = 54.0 if cfg["bc"] == 2 else 27.0
+    if sched["kind"] != 1:
+        ns = 2.0 * n if cfg["bc"] == 2 else float(n)
+        return 27.0 * n * ns
+    B, nb = sched["block"], sched["blocks"]
+    sizes = [B] * (nb - 1) + [n - (nb - 1) * B]
+    diag = float(sum(float(b) * b for b in sizes))
+    return imgs * ((float(n) * n - diag) / 2.0 + diag)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(x, q, cfg, n_targets, n_check=256, n_surface=20000):
+    """The oracle (plain FP64 C with OpenMP, numpy for the small steps) timed
+    stage by stage on bounded samples of the same workload, each stage's time
+    scaled to the full step: the right-hand side at n_check of the check
+    points, least squares and mapping in full, the near sum at n_targets
+    particles, the surface sum at n_surface particles.  value = pair
+    interactions of one full step / the scaled step time.  The preparation
+    step (plan) is timed too but is not part of the per-step time."""
     import numpy as np
 
     import oracle
     from oracle import hsma as oh
     oh.build()
-    c = oh.normalize(x, cfg["L"], cfg["bc"])
-    src = np.concatenate([c, q[:, None]], axis=1)
-    idx = np.random.default_rng(0).choice(len(q), n_targets, replace=False)
-    img = oracle.BC_METALLIC if cfg["bc"] == 1 else oracle.BC_PERIODIC
+    L, bc = cfg["L"], cfg["bc"]
+    rng = np.random.default_rng(0)
+    n = len(q)
     t0 = time.perf_counter()
-    oracle.near_sum(img, cfg["L"], src, idx)
-    dt = time.perf_counter() - t0
-    pairs = n_targets * 27.0 * len(q)
+    plan = oracle.make_plan(L, bc, cfg["p"], cfg["M"], cfg["K"], cfg["R"])
+    t_plan = time.perf_counter() - t0
+    c = oh.normalize(x, L, bc)
+    qq = np.asarray(q, dtype=np.float64)
+    if bc == 2:
+        c, qq = oh.double_slab(c, qq)
+    src = np.concatenate([c, qq[:, None]], axis=1)
+    ns = len(src)
+    img = oracle.BC_METALLIC if bc == 1 else oracle.BC_PERIODIC
+    pts = plan["X"] if plan["Xt"] is None else np.concatenate([plan["X"], plan["Xt"]])
+    nchk = len(pts)
+    stages = {}
+
+    def stage(name, fn, full_scale, pairs_full, sample):
+        t = time.perf_counter()
+        out = fn()
+        dt = time.perf_counter() - t
+        stages[name] = {"sample": sample, "s": dt, "s_full_step": dt * full_scale}
+        if pairs_full:
+            stages[name]["pairs_full_step"] = pairs_full
+            stages[name]["pairs_per_s"] = pairs_full / (dt * full_scale)
+        return out
+
+    kc = min(n_check, nchk)
+    ic = rng.choice(nchk, kc, replace=False)
+    stage("rhs", lambda: oracle.potential_at(img, L, src, pts[ic]), nchk / kc, 27.0 * nchk * ns,
+          "%d of %d check points against all 27 N_s images" % (kc, nchk))
+    b = rng.standard_normal(cfg["K"])   # timing only: the values do not matter
+    A = stage("least_squares", lambda: oh.coefficients_from_rhs(plan, b), 1.0, 0.0, "full")
+    surf = stage("mapping", lambda: oh.surface_images(plan, A), 1.0, 0.0, "full")
+    kt = min(n_targets, n)
+    it = rng.choice(n, kt, replace=False)
+    stage("near", lambda: oracle.near_sum(img, L, src, it), n / kt, 27.0 * n * ns,
+          "%d of %d particles against all 27 N_s images" % (kt, n))
+    ks = min(n_surface, n)
+    isf = rng.choice(n, ks, replace=False)
+    stage("surface", lambda: oracle.surface_sum(src[isf, :3], surf), n / ks,
+          float(n) * len(surf), "%d of %d particles against all %d surface points" % (ks, n, len(surf)))
+    step_s = sum(v["s_full_step"] for v in stages.values())
+    pairs = sum(v.get("pairs_full_step", 0.0) for v in stages.values())
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
-            "sample": "near-field sum at %d of %d particles against all 27N images (%.3g pairs, %.1f s)"
-                      % (n_targets, len(q), pairs, dt)}
+    sampled = sum(v["s"] for v in stages.values())
+    return {"value": pairs / step_s, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": "every stage of one update step on bounded samples (%.1f s of CPU work), "
+                      "each scaled to the full step: %.1f s per step" % (sampled, step_s),
+            "s_per_step_scaled": step_s, "plan_s": t_plan, "stages": stages}
 
 
-def serving(args):
-    """Serving stream: requests with N log-uniform in [1e3, 1e5] (even), periodic or
-    grounded cube with probability 1/2, p in {12, 16, 20}, K = M = 10 p^2,
-    R = 2.7L.  Closed loop (all arrivals at t = 0) gives solves/s; open loop
-    (Poisson arrivals at 0.8 of each path's closed-loop rate) gives p50/p99
-    latency.  Batched FP32-compensated server vs one FP64 solve per request."""
+def serving_measure(n_requests, refine, log=sys.stderr):
+    """Serving stream (seeded trace): N log-uniform in [1e3, 1e5] (even),
+    periodic or grounded cube with probability 1/2, p in {12, 16, 20},
+    K = M = 10 p^2, R = 2.7L.  Closed loop (all requests at t = 0) gives
+    solves/s of four paths: the batched server and one solve per request, each
+    in FP32-comp and in FP64 (equal-precision comparisons).  Open loop
+    (Poisson arrivals at 0.8 of a path's closed-loop rate) gives p50/p99
+    latency.  Energies of the FP32 paths are compared with the FP64
+    per-request path."""
     import numpy as np
     import torch
 
     from paper_1806_04801_amd import hsma, workloads
 
     torch.cuda.set_device(0)
-    trace = workloads.serving_trace(args.requests, seed=4)
+    trace = workloads.serving_trace(n_requests, seed=4)
     plans = {}
-    for bc in (0, 1):
-        for p in (12, 16, 20):
-            plans[(bc, p)] = hsma.Plan(1.0, bc, p, 10 * p * p, 10 * p * p, 2.7)
-    pl, xs, qs = [], [], []
+    for prec in (hsma.FP64, hsma.FP32_COMP):
+        for bc in (0, 1):
+            for p in (12, 16, 20):
+                plans[(prec, bc, p)] = hsma.Plan(1.0, bc, p, 10 * p * p, 10 * p * p, 2.7, precision=prec)
+    xs, qs = [], []
     for r in trace:
         x, q = workloads.uniform_neutral(r["n"], 1.0, seed=r["seed"])
-        pl.append(plans[(r["bc"], r["p"])])
         xs.append(x)
         qs.append(q)
+    pl = {prec: [plans[(prec, r["bc"], r["p"])] for r in trace] for prec in (hsma.FP64, hsma.FP32_COMP)}
     n = len(trace)
     pairs = 0.0
     for r in trace:
         nchk = (2 if r["bc"] == 0 else 1) * 10 * r["p"] ** 2
         pairs += 27.0 * r["n"] * r["n"] + 27.0 * nchk * r["n"]
-    srv = hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
-                      refine_below=args.refine)
+    srv = {hsma.FP32_COMP: hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
+                                       refine_below=refine),
+           hsma.FP64: hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP64)}
     zero = np.zeros(n)
-    # warm-up of both paths on a few requests
-    srv.run_trace(zero[:8], pl[:8], xs[:8], qs[:8])
-    hsma.run_trace_sequential(zero[:8], pl[:8], xs[:8], qs[:8])
-    print("serving: closed loop, batched fp32", file=sys.stderr, flush=True)
-    refined0 = srv.stats()["refined"]
-    e32, lat32c, wall32 = srv.run_trace(zero, pl, xs, qs)
-    refined = srv.stats()["refined"] - refined0
-    print("serving: closed loop, sequential fp64 (%.1f s batched)" % wall32, file=sys.stderr, flush=True)
-    e64, lat64c, wall64 = hsma.run_trace_sequential(zero, pl, xs, qs)
-    mu32, mu64 = n / wall32, n / wall64
-    rng = np.random.default_rng(44)
-    gaps = rng.exponential(1.0, n)
-    print("serving: open loop (%.1f s sequential)" % wall64, file=sys.stderr, flush=True)
-    arr32 = np.cumsum(gaps) / (0.8 * mu32)
-    _, lat32, _ = srv.run_trace(arr32, pl, xs, qs)
-    print("serving: open loop, batched at 0.8 of its capacity done", file=sys.stderr, flush=True)
-    arr64 = np.cumsum(gaps) / (0.8 * mu64)
-    _, lat64, _ = hsma.run_trace_sequential(arr64, pl, xs, qs)
-    print("serving: open loop, sequential at 0.8 of its capacity done", file=sys.stderr, flush=True)
-    _, lat32s, _ = srv.run_trace(arr64, pl, xs, qs)      # batched at the sequential path's load
-    print("serving: open loop, batched at the sequential load done", file=sys.stderr, flush=True)
-    rel = np.abs(e32 - e64) / np.abs(e64)
+    k = min(8, n)
+    for prec in (hsma.FP32_COMP, hsma.FP64):   # warm-up of every path
+        srv[prec].run_trace(zero[:k], pl[prec][:k], xs[:k], qs[:k])
+        hsma.run_trace_sequential(zero[:k], pl[prec][:k], xs[:k], qs[:k])
+    closed = {}
+    energies = {}
+    refined0 = srv[hsma.FP32_COMP].stats()["refined"]
+    for name, prec, batched in (("batched_fp32", hsma.FP32_COMP, True),
+                                ("sequential_fp64", hsma.FP64, False),
+                                ("sequential_fp32", hsma.FP32_COMP, False),
+                                ("batched_fp64", hsma.FP64, True)):
+        print("serving: closed loop, %s" % name, file=log, flush=True)
+        if batched:
+            e, _, wall = srv[prec].run_trace(zero, pl[prec], xs, qs)
+        else:
+            e, _, wall = hsma.run_trace_sequential(zero, pl[prec], xs, qs)
+        closed[name] = n / wall
+        energies[name] = e
+        if name == "batched_fp32":
+            refined = srv[hsma.FP32_COMP].stats()["refined"] - refined0
+    mu32, mu64 = closed["batched_fp32"], closed["sequential_fp64"]
+    gaps = np.random.default_rng(44).exponential(1.0, n)
     pct = lambda a, q_: float(np.percentile(a, q_)) * 1e3
+    lat = {}
+    for name, rate_of, prec, batched in (("batched_fp32_at_0.8_own", mu32, hsma.FP32_COMP, True),
+                                         ("sequential_fp64_at_0.8_own", mu64, hsma.FP64, False),
+                                         ("batched_fp32_at_0.8_fp64_sequential", mu64, hsma.FP32_COMP, True)):
+        print("serving: open loop, %s" % name, file=log, flush=True)
+        arr = np.cumsum(gaps) / (0.8 * rate_of)
+        if batched:
+            _, l_, _ = srv[prec].run_trace(arr, pl[prec], xs, qs)
+        else:
+            _, l_, _ = hsma.run_trace_sequential(arr, pl[prec], xs, qs)
+        lat[name] = {"p50_ms": pct(l_, 50), "p99_ms": pct(l_, 99), "offered_per_s": 0.8 * rate_of}
+    e64 = energies["sequential_fp64"]
+    err = {}
+    for name in ("batched_fp32", "sequential_fp32", "batched_fp64"):
+        rel = np.abs(energies[name] - e64) / np.abs(e64)
+        err[name] = {"p50": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
+                     "max": float(rel.max()), "frac_le_1e-5": float(np.mean(rel <= 1e-5))}
+    return {
+        "requests": n,
+        "desc": "N log-uniform [1e3,1e5] even, bc periodic/grounded 1/2, p in {12,16,20}, "
+                "K=M=10p^2, R=2.7L; seeded Poisson trace (seed 4)",
+        "pair_interactions": pairs,
+        "solves_per_s": closed,
+        "gain_batched_vs_sequential": {"fp32": closed["batched_fp32"] / closed["sequential_fp32"],
+                                       "fp64": closed["batched_fp64"] / closed["sequential_fp64"]},
+        "gain_batched_fp32_vs_sequential_fp64": mu32 / mu64,
+        "latency": lat,
+        "refine_below": refine,
+        "refined_in_fp64": {"requests": int(refined), "fraction": refined / n},
+        "rel_energy_err_vs_sequential_fp64": err,
+    }
+
+
+def serving(args):
+    """--workload serving: the serving measurement as its own JSON line."""
+    sv = serving_measure(args.requests, args.refine)
+    mu = sv["solves_per_s"]["batched_fp32"]
     rec = {
-        "metric": "solves/s", "value": mu32, "unit": "solves/s", "n_gpus": 1,
-        "steps": n, "warmup": 8, "ms_per_step": 1e3 / mu32, "higher_is_better": True,
+        "metric": "solves/s", "value": mu, "unit": "solves/s", "n_gpus": 1,
+        "steps": sv["requests"], "warmup": 8, "ms_per_step": 1e3 / mu, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {
-            "workload": "serving", "requests": n,
-            "desc": "N log-uniform [1e3,1e5] even, bc periodic/grounded 1/2, p in {12,16,20}, "
-                    "K=M=10p^2, R=2.7L; FP32-comp batched server (ill-conditioned energies "
-                    "refined in FP64) vs FP64 per-request",
-            "pair_interactions": pairs,
-            "batched_fp32": {"solves_per_s": mu32, "pairs_per_s": pairs / wall32,
-                             "p50_ms_at_0.8mu": pct(lat32, 50), "p99_ms_at_0.8mu": pct(lat32, 99),
-                             "p50_ms_at_0.8mu64": pct(lat32s, 50), "p99_ms_at_0.8mu64": pct(lat32s, 99)},
-            "sequential_fp64": {"solves_per_s": mu64, "pairs_per_s": pairs / wall64,
-                                "p50_ms_at_0.8mu": pct(lat64, 50), "p99_ms_at_0.8mu": pct(lat64, 99)},
-            "speedup_solves_per_s": mu32 / mu64,
-            "refine_below": args.refine,
-            "refined_in_fp64": {"requests": int(refined), "fraction": refined / n},
-            "rel_energy_err_fp32_vs_fp64": {"p50": float(np.median(rel)),
-                                            "p99": float(np.percentile(rel, 99)),
-                                            "max": float(rel.max()),
-                                            "frac_le_1e-5": float(np.mean(rel <= 1e-5))},
-        },
+        "config": {"workload": "serving", "serving": sv},
     }
     print(json.dumps(rec))
 
@@ -358,9 +468,22 @@ def main():
     near_ms, near_launches = kt["near"]
     near_avg_s = near_ms / max(near_launches, 1) / 1e3
     sched = plan.near_schedule(n)
-    flops_pair = NEAR_FLOPS_PER_PAIR_ONCE if sched["kind"] == 1 else NEAR_FLOPS_PER_PAIR
-    achieved = flops_pair * near_pairs / near_avg_s / 1e12
+    kind = "pair-once" if sched["kind"] == 1 else "tiles"
+    ptag = "f32" if prec == hsma.FP32_COMP else "f64"
     peak = FP32_PEAK_TFLOPS if prec == hsma.FP32_COMP else FP64_PEAK_TFLOPS
+    if near_mode == hsma.NEAR_SPHERE:
+        evaluated = near_pairs
+    else:
+        evaluated = near_evaluated_pairs(n, cfg, sched)
+    achieved = NEAR_FLOPS_PER_PAIR * evaluated / near_avg_s / 1e12
+    other_fracs = {"flops_20_per_evaluated_pair_image": achieved / peak}
+    if sched["kind"] == 1:
+        # unordered cross-block pairs with both directions at 28 flops
+        both = NEAR_FLOPS_PER_UNORDERED_PAIR_BOTH_DIRECTIONS * (near_pairs / 2.0)
+        other_fracs["flops_28_per_unordered_pair_image_both_directions"] = both / near_avg_s / 1e12 / peak
+    counted = profiled_field(args.workload, ptag, kind, "counter_tflops")
+    if counted is not None:
+        other_fracs["valu_flops_counted_by_rocprof"] = counted / peak
     rec = {
         "metric": "pair interactions/s",
         "value": pairs_step / (dt / args.steps),
@@ -384,9 +507,11 @@ def main():
             "R": cfg["R"], "precision": "fp32 pair sums + two-sum accumulation" if prec else "fp64",
             "pairs_per_step": {"near": near_pairs, "rhs": rhs_pairs, "surface": surf_pairs},
             "near_pairs_per_s": near_pairs / near_avg_s,
-            "near_kernel": ("pair-once" if sched["kind"] == 1 else "tiles"),
+            "near_kernel": kind,
             "near_schedule": sched,
-            "near_flops_per_pair": flops_pair,
+            "near_pair_images_evaluated": evaluated,
+            "near_ms": 1e3 * near_avg_s,
+            "near_peak_fractions": other_fracs,
             "kernel_ms_avg": {k: (v[0] / max(v[1], 1)) for k, v in kt.items()},
             "energy": energies[-1],
         },
@@ -396,23 +521,20 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": profiled_traffic(args.workload, "f32" if prec == hsma.FP32_COMP else "f64",
-                                        "pair-once" if sched["kind"] == 1 else "tiles"),
+            "traffic": profiled_traffic(args.workload, ptag, kind),
         },
     }
     if host_entry is not None:
         host_entry["pairs_per_s"] = pairs_step / (host_entry["ms_per_call"] / 1e3)
         rec["config"]["host_entry"] = host_entry
+    del xd, qd, phi, F
+    plan.close()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(x, q, cfg, args.cpu_targets)
-    if args.paper_time:
-        # The paper reports an HSMA step under 1 s at N = 100k on two Tesla P100
-        # (Sec. III, Fig. 5); vs_baseline = this step's time / 1 s (an upper bound).
-        rec = {"metric": "seconds per HSMA update step", "value": dt / args.steps, "unit": "s",
-               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-               "ms_per_step": ms_step, "higher_is_better": False, "scaling": "strong",
-               "vs_baseline": (dt / args.steps) / 1.0, "dtype": rec["dtype"], "data": "synthetic",
-               "config": rec["config"], "roofline": rec["roofline"]}
+    if args.serving_requests > 0 and args.workload == "periodic1m":
+        # the serving half of the metric (solves/s and p99 latency at 1e-5)
+        torch.cuda.empty_cache()
+        rec["serving"] = serving_measure(args.serving_requests, args.refine)
     print(json.dumps(rec))
 
 
