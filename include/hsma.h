@@ -248,6 +248,27 @@ hsma_status hsma_energy_forces_device(hsma_plan plan, const double* x, const dou
                                       const hsma_intermediates* dbg);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the update
+ * step of hsma_energy_forces_device, with the same kernels and results, run
+ * in a static device scratch array of HSMA_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends, instead
+ * of a caller workspace.  Every stage runs on `stream` (no auxiliary stream
+ * or event is created).  x, q, phi, forces: device arrays as in
+ * hsma_energy_forces_device; energy: host double, written after the stream
+ * has drained.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  HSMA_E_NOMEM when the step for N particles
+ * needs more scratch than the array holds (hsma_workspace_bytes(plan, N) is
+ * an upper bound of the need; about 3e4 particles fit at p = 20).  All calls
+ * on one device share its array and it keeps the last call's contents: calls
+ * that overlap on one device (other host threads, other streams) race and
+ * must be serialized by the caller.
+ */
+#define HSMA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+hsma_status hsma_energy_forces_noalloc(hsma_plan plan, const double* x, const double* q, int64_t N,
+                                       void* stream, double* energy, double* phi, double* forces);
+
+/*
  * Exact gradient of the computed energy (adjoint of the update step):
  * dEdx (N x 3) and dEdq (N) on the device, energy on the host.  Unlike the
  * forces above, -dEdx also differentiates the least-squares coefficients with

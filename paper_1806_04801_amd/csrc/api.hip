@@ -239,7 +239,9 @@ hsma_status hsma_near_schedule(hsma_plan pl, int64_t N, hsma_near_schedule_t* ou
     return HSMA_OK;
 }
 
-static hsma_status check_sizes(hsma_plan pl, int64_t N) {
+}  // extern "C"
+
+hsma_status hsma::check_sizes(const hsma_plan_s* pl, int64_t N) {
     if (pl == nullptr) return fail(HSMA_E_INVALID, "NULL plan");
     if (N < 1 || N > (int64_t)1 << 28) return fail(HSMA_E_INVALID, "N out of range");
     if (pl->bc == HSMA_BC_SLAB_METALLIC_Z && N > (int64_t)1 << 27)
@@ -249,6 +251,8 @@ static hsma_status check_sizes(hsma_plan pl, int64_t N) {
         return fail(HSMA_E_INVALID, "too many sphere images for N");
     return HSMA_OK;
 }
+
+extern "C" {
 
 hsma_status hsma_energy_forces_device(hsma_plan pl, const double* x, const double* q, int64_t N,
                                       void* stream, void* workspace, size_t workspace_bytes,

@@ -36,6 +36,9 @@ struct Layout {
     SymGeom g_sym;
     int n_eblk = 1;
     size_t total = 0;
+    // every stage on the caller's stream (no auxiliary stream or events are
+    // created): the allocation-free entry point
+    bool single_stream = false;
 };
 
 // What the finalize stages add to the near potential of particle i:
@@ -58,6 +61,8 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
 hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStream_t s,
                      double* dEdx, double* dEdq);
 hsma_status read_result(const Layout& ly, char* ws, hipStream_t s, double* energy);
+// Argument checks of the update-step entry points (plan, N).
+hsma_status check_sizes(const hsma_plan_s* pl, int64_t N);
 hsma_status build_plan(hsma_plan_s* pl);
 void free_plan(hsma_plan_s* pl);
 

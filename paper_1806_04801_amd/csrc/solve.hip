@@ -369,7 +369,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
                 (void)hipStreamWaitEvent(s, a->join, 0);
         }
     } join_on_exit;
-    if (overlap_enabled()) {
+    if (overlap_enabled() && !ly.single_stream) {
         CK(aux_stream(pl->device, &aux));
         CK(hipEventRecord(aux->fork, s));
         CK(hipStreamWaitEvent(aux->s, aux->fork, 0));

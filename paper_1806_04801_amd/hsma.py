@@ -99,6 +99,10 @@ EXPORTS = {
                                                  ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
                                                  ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.POINTER(Intermediates)]),
+    "hsma_energy_forces_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_int64, ctypes.c_void_p,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
     "hsma_energy_grad_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
@@ -263,6 +267,21 @@ class Plan:
         if intermediates:
             return e.value, phi, forces, inter
         return e.value, phi, forces
+
+    def energy_forces_noalloc(self, x, q, phi, forces):
+        """The allocation-free entry point: x (N x 3), q (N), phi (N), forces
+        (N x 3) float64 CUDA tensors allocated by the caller; the library runs
+        in its static device scratch.  Returns the energy."""
+        import torch
+        for t in (x, q, phi, forces):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        n = q.numel()
+        assert x.numel() == 3 * n and phi.numel() == n and forces.numel() == 3 * n
+        e = ctypes.c_double()
+        _check(load().hsma_energy_forces_noalloc(self._h, _ptr(x), _ptr(q), n,
+                                                 _stream_handle(torch, x.device), ctypes.byref(e),
+                                                 _ptr(phi), _ptr(forces)))
+        return e.value
 
     def energy_grad(self, x, q):
         """Exact gradient of the computed energy: (energy, dE/dx, dE/dq)."""
