@@ -15,11 +15,11 @@ with the paper's central-difference charge layers, and finite differences of
 the adjoint.  Every oracle function is pinned by at least one of these.
 """
 from .hsma import (  # noqa: F401
-    BC_PERIODIC, BC_METALLIC, BC_SLAB,
+    BC_PERIODIC, BC_METALLIC, BC_SLAB, BC_DIELECTRIC,
     normalize, monitoring_points, fibonacci_pair, integration_points,
     basis, householder_qr, qr_solve_ls, qr_apply_q,
     make_plan, solve, adjoint, splitmix64_uniform,
     near_sum, potential_at, surface_sum, charges_sum, check_adjoint,
     surface_images_paper_literal, sphere_images, near_explicit,
-    basis_gradient, far_field_direct,
+    basis_gradient, far_field_direct, far_shells, image_series, far_shell_count,
 )

@@ -27,6 +27,7 @@ import numpy as np
 BC_PERIODIC = 0
 BC_METALLIC = 1
 BC_SLAB = 2  # grounded walls at z = 0 and z = L/2, periodic in x and y
+BC_DIELECTRIC = 3  # dielectric box: the image series of Eq. (diel) with |gamma| < 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
@@ -49,11 +50,14 @@ def _load():
         d = ctypes.POINTER(ctypes.c_double)
         lg = ctypes.POINTER(ctypes.c_long)
         L_ = ctypes.c_long
-        lib.orc_potential_at.argtypes = [ctypes.c_int, ctypes.c_double, d, L_, d, L_, d]
-        lib.orc_near.argtypes = [ctypes.c_int, ctypes.c_double, d, L_, lg, L_, d, d]
+        D = ctypes.c_double
+        lib.orc_potential_at.argtypes = [ctypes.c_int, D, D, d, L_, d, L_, d]
+        lib.orc_near.argtypes = [ctypes.c_int, D, D, d, L_, lg, L_, d, d]
+        lib.orc_far_shells.argtypes = [D, D, d, L_, d, L_, ctypes.c_int, d]
+        lib.orc_image_series.argtypes = [ctypes.c_int, D, D, d, L_, lg, L_, ctypes.c_int, d, d]
         lib.orc_surface.argtypes = [d, L_, d, L_, d, d]
         lib.orc_charges.argtypes = [d, L_, d, L_, d, d]
-        lib.orc_check_adjoint.argtypes = [ctypes.c_int, ctypes.c_double, d, L_, d, d, L_, d, d]
+        lib.orc_check_adjoint.argtypes = [ctypes.c_int, D, D, d, L_, d, d, L_, d, d]
         lib.orc_near_explicit.argtypes = [d, lg, L_, d, lg, ctypes.POINTER(ctypes.c_int), L_, d, d]
         _lib = lib
     return _lib
@@ -70,22 +74,46 @@ def _c(a, dtype=np.float64):
 # --------------------------------------------------------------------------
 # Pair sums (thin wrappers over the C loops)
 # --------------------------------------------------------------------------
-def potential_at(bc, L, src, pts):
-    """Phi_in at points: all 27 images of every source (Sec. II.A)."""
+def potential_at(bc, L, src, pts, gamma=-1.0):
+    """Phi_in at points: all 27 images of every source (Sec. II.A); gamma is
+    the image weight of a dielectric box (Eq. (diel))."""
     src, pts = _c(src), _c(pts)
     out = np.zeros(len(pts))
-    _load().orc_potential_at(bc, L, _p(src), len(src), _p(pts), len(pts), _p(out))
+    _load().orc_potential_at(bc, L, gamma, _p(src), len(src), _p(pts), len(pts), _p(out))
     return out
 
 
-def near_sum(bc, L, src, tidx):
+def near_sum(bc, L, src, tidx, gamma=-1.0):
     """phi and E = -grad phi at source targets from the near images (Sec. II.C)."""
     src = _c(src)
     tidx = np.ascontiguousarray(tidx, dtype=np.int64)
     phi = np.zeros(len(tidx))
     fld = np.zeros((len(tidx), 3))
-    _load().orc_near(bc, L, _p(src), len(src),
+    _load().orc_near(bc, L, gamma, _p(src), len(src),
                      tidx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(tidx), _p(phi), _p(fld))
+    return phi, fld
+
+
+def far_shells(L, gamma, src, pts, S):
+    """The far part of the dielectric image series at points: images in the
+    shells 2 <= max|k_a| <= S with weights gamma^|k| (Eq. (diel))."""
+    src, pts = _c(src), _c(pts)
+    out = np.zeros(len(pts))
+    _load().orc_far_shells(L, gamma, _p(src), len(src), _p(pts), len(pts), int(S), _p(out))
+    return out
+
+
+def image_series(bc, L, src, tidx, S, gamma=-1.0):
+    """The image series itself, truncated at shells max|k_a| <= S, at source
+    targets (bare self term left out): a reference for the whole method.
+    Returns (phi, E) with E = -grad phi, images held fixed."""
+    src = _c(src)
+    tidx = np.ascontiguousarray(tidx, dtype=np.int64)
+    phi = np.zeros(len(tidx))
+    fld = np.zeros((len(tidx), 3))
+    _load().orc_image_series(bc, L, gamma, _p(src), len(src),
+                             tidx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(tidx), int(S),
+                             _p(phi), _p(fld))
     return phi, fld
 
 
@@ -112,7 +140,8 @@ def check_adjoint(bc, L, pos, pts, lam):
     pos, pts, lam = _c(pos), _c(pts), _c(lam)
     g = np.zeros(len(pos))
     dg = np.zeros((len(pos), 3))
-    _load().orc_check_adjoint(bc, L, _p(pos), len(pos), _p(pts), _p(lam), len(pts), _p(g), _p(dg))
+    _load().orc_check_adjoint(bc, L, -1.0, _p(pos), len(pos), _p(pts), _p(lam), len(pts), _p(g),
+                              _p(dg))
     return g, dg
 
 
@@ -172,7 +201,7 @@ def normalize(x, L, bc):
     if bc == BC_PERIODIC:
         c = x - 0.5 * L
         return c - L * np.floor(c / L + 0.5)
-    if bc == BC_METALLIC:
+    if bc in (BC_METALLIC, BC_DIELECTRIC):
         c = x - 0.5 * L
         if np.any(np.abs(c) > 0.5 * L):
             raise ValueError("position outside the box")
@@ -216,9 +245,11 @@ def monitoring_points(bc, L, K, seed):
     twin points x~ = x - kL inside the box with k = floor(x/L + 1/2).
     Metallic: K points on the faces, point i on face i mod 6 (-x,+x,-y,+y,-z,+z),
     tangential coordinates uniform from SplitMix64(seed).
+    Dielectric: the Fibonacci grid on the circumsphere without twins (the far
+    field itself is fitted there).
     Returns (x, x_twin or None).
     """
-    if bc in (BC_PERIODIC, BC_SLAB):
+    if bc in (BC_PERIODIC, BC_SLAB, BC_DIELECTRIC):
         R0 = math.sqrt(3.0) * L / 2.0
         w = (math.sqrt(5.0) - 1.0) / 2.0
         pts = np.zeros((K, 3))
@@ -229,6 +260,8 @@ def monitoring_points(bc, L, K, seed):
             pts[i - 1] = (R0 * math.cos(lat) * math.cos(az),
                           R0 * math.cos(lat) * math.sin(az),
                           R0 * math.sin(lat))
+        if bc == BC_DIELECTRIC:
+            return pts, None
         twin = pts - L * np.floor(pts / L + 0.5)
         return pts, twin
     pts = np.zeros((K, 3))
@@ -448,9 +481,33 @@ def qr_solve_ls(V, R, b):
 # --------------------------------------------------------------------------
 # Plan (preparation step, Sec. II.C) and update step
 # --------------------------------------------------------------------------
-def make_plan(L, bc, p, M, K, R, seed=12345):
+def far_shell_count(gamma, tol=1e-13):
+    """Shells S of the far dielectric images whose omitted tail is below
+    tol * sum|q| / L at every point of the circumsphere: a shell s >= 2 holds
+    images with |k| >= s at distance >= (s - 1/2 - sqrt(3)/2) L, and the
+    weights of a shell sum to at most 6 |gamma|^s c^2 with
+    c = 1 + 2|gamma|/(1 - |gamma|), so the tail beyond S is at most
+    6 c^2 |gamma|^(S+1) / ((1 - |gamma|) (S + 1/2 - sqrt(3)/2))."""
+    g = abs(gamma)
+    if g == 0.0:
+        return 1
+    c = 1.0 + 2.0 * g / (1.0 - g)
+    S = 2
+    while 6.0 * c * c * g ** (S + 1) / ((1.0 - g) * (S + 0.5 - math.sqrt(3.0) / 2.0)) > tol:
+        S += 1
+    return S
+
+
+def make_plan(L, bc, p, M, K, R, seed=12345, gamma=None, shells=None):
     """Preparation step: monitoring points, fitting matrix and its QR,
-    integration points and mapping matrix (Sec. II.C, Table I)."""
+    integration points and mapping matrix (Sec. II.C, Table I).  A dielectric
+    box (bc = BC_DIELECTRIC) takes the image weight gamma, |gamma| < 1, and
+    the number of far image shells (default far_shell_count(gamma))."""
+    if bc == BC_DIELECTRIC:
+        if gamma is None or not abs(gamma) < 1.0:
+            raise ValueError("a dielectric box needs |gamma| < 1")
+        if shells is None:
+            shells = far_shell_count(gamma)
     R0 = math.sqrt(3.0) * L / 2.0
     X, Xt = monitoring_points(bc, L, K, seed)
     B = basis(X, p, R0)
@@ -464,7 +521,7 @@ def make_plan(L, bc, p, M, K, R, seed=12345):
     Bs = basis(S, p, R0)
     return dict(L=L, bc=bc, p=p, M=M, K=K, Rs=R, R0=R0, seed=seed,
                 X=X, Xt=Xt, F=F, V=V, R=Rf, S=S, w=w, nrm=nrm, F1=F1, F2=F2, Bs=Bs,
-                deg=degree_of(p))
+                deg=degree_of(p), gamma=gamma, shells=shells)
 
 
 def _rhs(plan, src, images=None):
@@ -476,6 +533,10 @@ def _rhs(plan, src, images=None):
         if plan["Xt"] is not None:
             b = b - charges_sum(plan["Xt"], images[0])[0]
         return b
+    if plan["bc"] == BC_DIELECTRIC:
+        # the far images themselves: the fit reproduces Phi_far at the points
+        # (A = argmin ||F A + b|| with b = -Phi_far)
+        return -far_shells(plan["L"], plan["gamma"], src, plan["X"], plan["shells"])
     bc = BC_PERIODIC if plan["bc"] in (BC_PERIODIC, BC_SLAB) else BC_METALLIC
     b = potential_at(bc, plan["L"], src, plan["X"])
     if plan["Xt"] is not None:
@@ -543,13 +604,18 @@ def solve(plan, x, q, targets=None, dipole="exact", dr=None, near="block", far="
         targets = np.arange(n_real)
     targets = np.asarray(targets, dtype=np.int64)
     bc_img = BC_PERIODIC if plan["bc"] in (BC_PERIODIC, BC_SLAB) else BC_METALLIC
+    gamma = -1.0
+    if plan["bc"] == BC_DIELECTRIC:
+        if near != "block":
+            raise ValueError("a dielectric box uses the block near set")
+        bc_img, gamma = BC_DIELECTRIC, plan["gamma"]
     images = sphere_images(bc_img, plan["L"], src, plan["Rs"]) if near == "sphere" else None
     b = _rhs(plan, src, images)
     A = coefficients_from_rhs(plan, b)
     if images is not None:
         pn, en = near_explicit(src, targets, *images)
     else:
-        pn, en = near_sum(bc_img, plan["L"], src, targets)
+        pn, en = near_sum(bc_img, plan["L"], src, targets, gamma)
     tpos = src[targets, :3]
     if far == "direct":
         surf = None
@@ -593,6 +659,8 @@ def adjoint(plan, x, q, targets=None):
     derivatives are evaluated at those charges only and E is the partial
     energy 1/2 sum over the targets of q_i phi_i.
     """
+    if plan["bc"] == BC_DIELECTRIC:
+        raise ValueError("no adjoint for the dielectric box")
     x = np.asarray(x, dtype=np.float64)
     n_real = len(x)
     src = _prepare_sources(plan, x, q)

@@ -13,32 +13,42 @@
  *     box, k in {-1,0,1}^3:
  *       periodic  : r_j + kL, charge q_j                       (Sec. II, periodic sum)
  *       metallic  : (-1)^k o r_j + kL, charge (-1)^{|k|} q_j   (Eq. (diel), gamma = -1)
+ *       dielectric: (-1)^k o r_j + kL, charge gamma^{|k|} q_j   (Eq. (diel), |gamma| < 1)
  *     These are the charges "inside the auxiliary sphere" (Sec. II.A).
+ *   - Dielectric boxes also need the images beyond the block, shells
+ *     2 <= max|k_a| <= S of the same series (the far part of Eq. (diel)).
  * Coordinates are centred: the central box is [-L/2, L/2]^3.
  * Every loop is a plain double loop in the order of the definition; OpenMP
  * only splits the outer loop over evaluation points.
  */
 #include <math.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 #define BC_PERIODIC 0
 #define BC_METALLIC 1
+#define BC_DIELECTRIC 3
 
-/* Image k of the source at r (k components in {-1,0,1}); returns the sign s_k. */
-static double image_of(int bc, double L, const int k[3], const double r[3], double out[3])
+/* Image k of the source at r for any integer k; returns its weight s_k:
+ *   periodic  : r + kL, weight 1
+ *   metallic  : (-1)^{k_a} r_a + k_a L per axis, weight (-1)^{|k|}
+ *   dielectric: the same positions, weight gamma^{|k|}
+ * (|k| = |k_x| + |k_y| + |k_z|, one factor per reflection). */
+static double image_of(int bc, double L, double gamma, const int k[3], const double r[3],
+                       double out[3])
 {
-    double sign = 1.0;
+    double w = 1.0;
     for (int a = 0; a < 3; ++a) {
         if (bc == BC_PERIODIC) {
             out[a] = r[a] + k[a] * L;
         } else {
-            /* reflection (-1)^{k_a} r_a, then shift k_a L; one sign flip per reflection */
-            double refl = (k[a] == 0) ? r[a] : -r[a];
+            double refl = (k[a] % 2 == 0) ? r[a] : -r[a];
             out[a] = refl + k[a] * L;
-            if (k[a] != 0) sign = -sign;
+            int n = k[a] < 0 ? -k[a] : k[a];
+            for (int t = 0; t < n; ++t) w *= (bc == BC_METALLIC) ? -1.0 : gamma;
         }
     }
-    return sign;
+    return w;
 }
 
 /*
@@ -48,7 +58,7 @@ static double image_of(int bc, double L, const int k[3], const double r[3], doub
  * This is Phi_in at the monitoring points (Sec. II.A, the right-hand side of
  * the least-squares system).
  */
-void orc_potential_at(int bc, double L, const double *src, long ns,
+void orc_potential_at(int bc, double L, double gamma, const double *src, long ns,
                       const double *pts, long np, double *phi)
 {
     #pragma omp parallel for schedule(dynamic, 4)
@@ -62,7 +72,7 @@ void orc_potential_at(int bc, double L, const double *src, long ns,
             for (int kz = -1; kz <= 1; ++kz) {
                 int k[3] = {kx, ky, kz};
                 double im[3];
-                double s = image_of(bc, L, k, r, im);
+                double s = image_of(bc, L, gamma, k, r, im);
                 double dx = p[0] - im[0], dy = p[1] - im[1], dz = p[2] - im[2];
                 acc += s * r[3] / sqrt(dx * dx + dy * dy + dz * dz);
             }
@@ -79,7 +89,7 @@ void orc_potential_at(int bc, double L, const double *src, long ns,
  * Only the bare self term (j = i, k = 0) is left out; self-images count.
  * tidx: nt indices of the targets among the sources.
  */
-void orc_near(int bc, double L, const double *src, long ns,
+void orc_near(int bc, double L, double gamma, const double *src, long ns,
               const long *tidx, long nt, double *phi, double *field)
 {
     #pragma omp parallel for schedule(dynamic, 4)
@@ -95,7 +105,7 @@ void orc_near(int bc, double L, const double *src, long ns,
                 if (j == i && kx == 0 && ky == 0 && kz == 0) continue;
                 int k[3] = {kx, ky, kz};
                 double im[3];
-                double s = image_of(bc, L, k, r, im);
+                double s = image_of(bc, L, gamma, k, r, im);
                 double dx = ri[0] - im[0], dy = ri[1] - im[1], dz = ri[2] - im[2];
                 double d = sqrt(dx * dx + dy * dy + dz * dz);
                 double qs = s * r[3];
@@ -177,7 +187,7 @@ void orc_charges(const double *pts, long np, const double *chg, long m,
  * diag((-1)^{k_a}) for metallic).
  * pos: ns x 3 centred; pts: np x 3.
  */
-void orc_check_adjoint(int bc, double L, const double *pos, long ns,
+void orc_check_adjoint(int bc, double L, double gamma, const double *pos, long ns,
                        const double *pts, const double *lam, long np,
                        double *g, double *dg)
 {
@@ -192,15 +202,15 @@ void orc_check_adjoint(int bc, double L, const double *pos, long ns,
             for (int kz = -1; kz <= 1; ++kz) {
                 int k[3] = {kx, ky, kz};
                 double im[3];
-                double s = image_of(bc, L, k, r, im);
+                double s = image_of(bc, L, gamma, k, r, im);
                 double dx = p[0] - im[0], dy = p[1] - im[1], dz = p[2] - im[2];
                 double d = sqrt(dx * dx + dy * dy + dz * dz);
                 ag += lam[i] * s / d;
                 double c = lam[i] * s / (d * d * d);
                 /* S_k applied to d: reflected axes flip sign (metallic only) */
-                double sx = (bc == BC_METALLIC && kx != 0) ? -1.0 : 1.0;
-                double sy = (bc == BC_METALLIC && ky != 0) ? -1.0 : 1.0;
-                double sz = (bc == BC_METALLIC && kz != 0) ? -1.0 : 1.0;
+                double sx = (bc != BC_PERIODIC && kx != 0) ? -1.0 : 1.0;
+                double sy = (bc != BC_PERIODIC && ky != 0) ? -1.0 : 1.0;
+                double sz = (bc != BC_PERIODIC && kz != 0) ? -1.0 : 1.0;
                 gx += c * sx * dx; gy += c * sy * dy; gz += c * sz * dz;
             }
         }
@@ -235,6 +245,76 @@ void orc_near_explicit(const double *src, const long *tidx, long nt, const doubl
             ex += c * dx; ey += c * dy; ez += c * dz;
         }
         phi[t] = ap;
+        field[3 * t + 0] = ex; field[3 * t + 1] = ey; field[3 * t + 2] = ez;
+    }
+}
+
+/*
+ * The far part of the dielectric image series (Eq. (diel)) at points: every
+ * image of every source in the shells 2 <= max_a |k_a| <= S,
+ *   phi[i] = sum_j sum_k gamma^{|k|} q_j / |p_i - I_k(r_j)|.
+ * These images lie outside the 3x3x3 block, at least 1.5 L from the centre,
+ * so the sum is harmonic in the ball of radius 1.5 L (the far field that the
+ * least squares fits for a dielectric box).
+ */
+void orc_far_shells(double L, double gamma, const double *src, long ns,
+                    const double *pts, long np, int S, double *phi)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < np; ++i) {
+        const double *p = pts + 3 * i;
+        double acc = 0.0;
+        for (long j = 0; j < ns; ++j) {
+            const double *r = src + 4 * j;
+            for (int kx = -S; kx <= S; ++kx)
+            for (int ky = -S; ky <= S; ++ky)
+            for (int kz = -S; kz <= S; ++kz) {
+                int m = abs(kx) > abs(ky) ? abs(kx) : abs(ky);
+                m = m > abs(kz) ? m : abs(kz);
+                if (m < 2) continue;
+                int k[3] = {kx, ky, kz};
+                double im[3];
+                double w = image_of(BC_DIELECTRIC, L, gamma, k, r, im);
+                double dx = p[0] - im[0], dy = p[1] - im[1], dz = p[2] - im[2];
+                acc += w * r[3] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+        }
+        phi[i] = acc;
+    }
+}
+
+/*
+ * The image series truncated at shells max_a |k_a| <= S, evaluated at source
+ * targets without any splitting (a reference for the whole method):
+ *   phi_t = sum_{(j,k) != (i,0)} s_k q_j / |r_i - I_k(r_j)|,  i = tidx[t]
+ *   E_t   = sum_{(j,k) != (i,0)} s_k q_j (r_i - I_k(r_j)) / |.|^3
+ * (weights and positions of image_of; images held fixed for the field).
+ */
+void orc_image_series(int bc, double L, double gamma, const double *src, long ns,
+                      const long *tidx, long nt, int S, double *phi, double *field)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long t = 0; t < nt; ++t) {
+        long i = tidx[t];
+        const double *ri = src + 4 * i;
+        double acc = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (long j = 0; j < ns; ++j) {
+            const double *r = src + 4 * j;
+            for (int kx = -S; kx <= S; ++kx)
+            for (int ky = -S; ky <= S; ++ky)
+            for (int kz = -S; kz <= S; ++kz) {
+                if (j == i && kx == 0 && ky == 0 && kz == 0) continue;
+                int k[3] = {kx, ky, kz};
+                double im[3];
+                double w = image_of(bc, L, gamma, k, r, im);
+                double dx = ri[0] - im[0], dy = ri[1] - im[1], dz = ri[2] - im[2];
+                double d = sqrt(dx * dx + dy * dy + dz * dz);
+                acc += w * r[3] / d;
+                double c = w * r[3] / (d * d * d);
+                ex += c * dx; ey += c * dy; ez += c * dz;
+            }
+        }
+        phi[t] = acc;
         field[3 * t + 0] = ex; field[3 * t + 1] = ey; field[3 * t + 2] = ez;
     }
 }

@@ -468,3 +468,97 @@ def test_near_block_is_symmetric_in_the_pair(bc):
         assert abs(p_ji[0] - p_ij[0]) <= 1e-12 * scale
         if bc == oracle.BC_PERIODIC:
             assert np.max(np.abs(e_ji + e_ij)) <= 1e-12 * max(np.max(np.abs(e_ij)), 1.0)
+
+
+# ---------------------------------------------------------------- dielectric box (Eq. (diel), |gamma| < 1)
+def _dielectric_system(n=6, seed=11):
+    rng = np.random.default_rng(seed)
+    x = 0.1 + 0.8 * rng.random((n, 3))
+    q = rng.choice([-1.0, 1.0, 2.0], n)
+    return x, q
+
+
+@pytest.mark.parametrize("gamma", [0.3, -0.4])
+def test_dielectric_method_converges_to_the_image_series(gamma):
+    """A dielectric box: the image series of Eq. (diel) summed directly over
+    growing shells converges geometrically (|gamma| < 1, absolutely
+    convergent); the method (block near set + far images fitted by the least
+    squares + surface mapping) reproduces the converged energy, potentials and
+    fields with an error that decays geometrically with p: below 1e-9 at
+    p = 16 and at least 100 times smaller than at p = 8."""
+    x, q = _dielectric_system()
+    src = np.concatenate([x - 0.5, q[:, None]], axis=1)
+    n = len(q)
+    S = oracle.far_shell_count(gamma, 1e-13)
+    phi, fld = oracle.image_series(oracle.BC_DIELECTRIC, 1.0, src, np.arange(n), S, gamma)
+    E = 0.5 * np.sum(q * phi)
+    tail = [abs(0.5 * np.sum(q * oracle.image_series(oracle.BC_DIELECTRIC, 1.0, src, np.arange(n),
+                                                       s, gamma)[0]) - E) for s in (3, 6, 12)]
+    assert tail[0] > tail[1] > tail[2] and tail[2] < 1e-3 * abs(E)
+    errs = {}
+    for p in (8, 16):
+        K = 2 * (p + 1) ** 2
+        plan = oracle.make_plan(1.0, oracle.BC_DIELECTRIC, p, 4 * K, K, 2.7, gamma=gamma)
+        r = oracle.solve(plan, x, q)
+        errs[p] = (abs(r["energy"] - E) / abs(E), np.abs(r["phi"] - phi).max() / np.abs(phi).max(),
+                   np.abs(r["field"] - fld).max() / np.abs(fld).max())
+    assert max(errs[16]) < 1e-9
+    assert errs[16][0] < 1e-2 * errs[8][0] and errs[16][1] < 1e-2 * errs[8][1]
+
+
+def test_dielectric_gamma_zero_is_free_space():
+    """gamma = 0: no image carries charge, the far field is zero and the
+    energy is the bare Coulomb energy of the charges."""
+    x, q = _dielectric_system(7, 3)
+    plan = oracle.make_plan(1.0, oracle.BC_DIELECTRIC, 8, 600, 300, 2.7, gamma=0.0)
+    r = oracle.solve(plan, x, q)
+    d = np.linalg.norm(x[:, None, :] - x[None, :, :], axis=-1)
+    np.fill_diagonal(d, np.inf)
+    E = 0.5 * np.sum(q[:, None] * q[None, :] / d)
+    assert abs(r["energy"] - E) <= 1e-13 * abs(E)
+    assert np.abs(r["A"]).max() == 0.0
+
+
+def test_dielectric_first_order_in_gamma():
+    """dE/dgamma at gamma = 0 is the interaction of every charge with the six
+    single reflections of all charges (images with |k| = 1 weigh gamma^1):
+    E(g) - E(-g) = 2 g E_1 + O(g^3), checked at g = 1e-3."""
+    x, q = _dielectric_system(5, 4)
+    g = 1e-3
+    Ep = oracle.solve(oracle.make_plan(1.0, oracle.BC_DIELECTRIC, 12, 1000, 400, 2.7, gamma=g), x, q)["energy"]
+    Em = oracle.solve(oracle.make_plan(1.0, oracle.BC_DIELECTRIC, 12, 1000, 400, 2.7, gamma=-g), x, q)["energy"]
+    c = x - 0.5
+    E1 = 0.0
+    for a in range(3):
+        for side in (-1.0, 1.0):
+            img = c.copy()
+            img[:, a] = side * 1.0 - c[:, a]      # reflection in the face at side/2
+            d = np.linalg.norm(c[:, None, :] - img[None, :, :], axis=-1)
+            E1 += 0.5 * np.sum(q[:, None] * q[None, :] / d)
+    assert abs((Ep - Em) / (2 * g) - E1) <= 1e-5 * abs(E1)
+
+
+def test_dielectric_cube_symmetry():
+    """The dielectric image series is invariant under the symmetries of the
+    cube: the energy of a rotated and reflected configuration is the same."""
+    x, q = _dielectric_system(6, 5)
+    plan = oracle.make_plan(1.0, oracle.BC_DIELECTRIC, 12, 1000, 400, 2.7, gamma=0.35)
+    E0 = oracle.solve(plan, x, q)["energy"]
+    c = x - 0.5
+    for perm, signs in (((1, 2, 0), (1, -1, 1)), ((2, 1, 0), (-1, -1, 1)), ((0, 2, 1), (1, 1, -1))):
+        y = c[:, perm] * np.array(signs) + 0.5
+        E1 = oracle.solve(plan, y, q)["energy"]
+        assert abs(E1 - E0) <= 1e-8 * abs(E0)
+
+
+def test_far_shell_count_bounds_the_tail():
+    """The far shells chosen for a tolerance leave a tail below it: the image
+    series of one unit charge beyond that shell count changes by less."""
+    for gamma in (0.2, -0.5):
+        S = oracle.far_shell_count(gamma, 1e-8)
+        src = np.array([[0.3, -0.2, 0.1, 1.0]])
+        pts = np.array([[0.5, 0.5, 0.5], [-0.6, 0.1, 0.2]])
+        pts = pts / np.linalg.norm(pts, axis=1)[:, None] * (np.sqrt(3.0) / 2.0)   # on the circumsphere
+        a = oracle.far_shells(1.0, gamma, src, pts, S)
+        b = oracle.far_shells(1.0, gamma, src, pts, S + 12)
+        assert np.abs(b - a).max() <= 1e-8
