@@ -45,8 +45,13 @@ extern "C" {
 typedef enum {
     HSMA_BC_PERIODIC = 0,        /* periodic in x, y, z (Sec. II, periodic image sum) */
     HSMA_BC_METALLIC = 1,        /* grounded cube: Eq. (diel) in the conducting limit gamma = -1 */
-    HSMA_BC_SLAB_METALLIC_Z = 2  /* periodic in x, y, grounded walls at z = 0 and z = L/2 (mirror
+    HSMA_BC_SLAB_METALLIC_Z = 2, /* periodic in x, y, grounded walls at z = 0 and z = L/2 (mirror
                                     reflections plus periodic extension, Sec. I) */
+    HSMA_BC_DIELECTRIC = 3       /* dielectric box: the image series of Eq. (diel) with weight
+                                    gamma^|k|, |gamma| < 1 (hsma_plan_desc.gamma); the far images
+                                    (shells 2..far_shells of the image lattice) are summed at the
+                                    monitoring points and fitted; double precision, block near
+                                    set, no adjoint and no serving */
 } hsma_bc;
 
 typedef enum {
@@ -109,6 +114,11 @@ typedef struct {
     int dipole_mode;   /* hsma_dipole_mode (hsma_plan_create: HSMA_DIPOLE_EXACT) */
     double dr;         /* layer spacing for HSMA_DIPOLE_LAYERS; <= 0 selects 1e-5 R_s */
     int far_mode;      /* hsma_far_mode (hsma_plan_create: HSMA_FAR_SURFACE) */
+    double gamma;      /* HSMA_BC_DIELECTRIC: image weight (1 - eps)/(1 + eps), |gamma| < 1
+                          (Eq. (diel)); ignored otherwise */
+    int far_shells;    /* HSMA_BC_DIELECTRIC: far image shells S, images with
+                          2 <= max_a |k_a| <= S; 0 picks the smallest S whose omitted tail is
+                          below 1e-13 sum|q|/L at the monitoring points */
 } hsma_plan_desc;
 
 typedef struct {
@@ -128,6 +138,8 @@ typedef struct {
     int dipole_mode;
     double dr;
     int far_mode;
+    double gamma;      /* dielectric box: image weight */
+    int far_shells;    /* dielectric box: far image shells in use */
 } hsma_plan_info_t;
 
 /* Optional device outputs of the intermediate stages (any pointer may be NULL). */
@@ -146,7 +158,7 @@ typedef struct {
    is the version of this interface; it changes whenever a declaration or a
    struct layout in this header changes (2: the near-schedule query and the
    server's double-precision refinement; 3: HSMA_E_COINCIDENT; 4:
-   HSMA_E_NONFINITE). */
+   HSMA_E_NONFINITE; 5: the dielectric box). */
 const char* hsma_status_string(int status);
 const char* hsma_last_error(void);
 int hsma_version(void);
@@ -299,7 +311,17 @@ hsma_status hsma_timing_read(double* ms, int64_t* launches);
  * queue until a slot is free and the arena has room (admission by memory).
  * Each hsma_server_tick admits what fits and enqueues one round of grouped
  * launches in which every active request advances one stage; the pair tiles of
- * all requests in the round share one launch.  A request's arithmetic depends
+ * all requests in the round share one launch per kind (near, right-hand
+ * side, surface).  The pair-once near sums of requests at or above the
+ * threshold of hsma_near_schedule run on a few side streams of the server
+ * (HSMA_SRV_STREAMS in the environment, 1 to 8, default 3, read at server
+ * creation), forked from the server stream and joined back within the round,
+ * so that the near sums of several requests and the grouped launches of the
+ * others run on the GPU at the same time.  A round admits requests while
+ * their pair work (27 N_s (N + check points) pair-images each) stays within a
+ * budget (HSMA_SRV_TICK_WORK in the environment, default 1.5e11, read at
+ * server creation; a larger request is admitted alone), so that rounds stay
+ * short and a finished request's slot goes to the queue within a few rounds.  A request's arithmetic depends
  * only on its own inputs and plan, so its result is bitwise the same alone and
  * in any mix.  precision selects the pair sums of every request
  * (HSMA_FP32_COMP: single precision with two-sum accumulation; HSMA_FP64);

@@ -82,13 +82,23 @@ const char* hsma_status_string(int st) {
 
 const char* hsma_last_error(void) { return g_last_error.c_str(); }
 
-int hsma_version(void) { return 4; }
+int hsma_version(void) { return 5; }
 
 hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     if (d == nullptr || out == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
     *out = nullptr;
     if (!(d->L > 0.0) || !std::isfinite(d->L)) return fail(HSMA_E_INVALID, "L must be > 0");
-    if (d->bc < 0 || d->bc > 2) return fail(HSMA_E_INVALID, "unknown boundary condition");
+    if (d->bc < 0 || d->bc > 3) return fail(HSMA_E_INVALID, "unknown boundary condition");
+    const bool diel = d->bc == HSMA_BC_DIELECTRIC;
+    if (diel) {
+        if (!(std::fabs(d->gamma) < 1.0)) return fail(HSMA_E_INVALID, "dielectric box needs |gamma| < 1");
+        if (d->precision != HSMA_FP64)
+            return fail(HSMA_E_INVALID, "the dielectric box runs in double precision only");
+        if (d->near_mode != HSMA_NEAR_BLOCK)
+            return fail(HSMA_E_INVALID, "the dielectric box uses the block near set");
+        if (d->far_shells < 0 || d->far_shells > 400)
+            return fail(HSMA_E_INVALID, "far_shells must be in [0, 400]");
+    }
     if (d->p < 1 || d->p > 40) return fail(HSMA_E_INVALID, "p must be in [1, 40]");
     if (d->precision != HSMA_FP64 && d->precision != HSMA_FP32_COMP)
         return fail(HSMA_E_INVALID, "unknown precision");
@@ -96,7 +106,7 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     if (!(d->R > R0) || !std::isfinite(d->R))
         return fail(HSMA_E_INVALID, "R must exceed the circumsphere radius sqrt(3) L / 2");
     const int nb = (d->p + 1) * (d->p + 1);
-    const int nu = (d->bc == HSMA_BC_METALLIC) ? nb : nb - 1;
+    const int nu = (d->bc == HSMA_BC_METALLIC || diel) ? nb : nb - 1;
     if (d->K < nu || d->K > (1 << 24)) return fail(HSMA_E_INVALID, "K must be >= number of unknowns");
     if (d->M < 4 || d->M > (1 << 22)) return fail(HSMA_E_INVALID, "M out of range");
     if (d->near_mode != HSMA_NEAR_BLOCK && d->near_mode != HSMA_NEAR_SPHERE)
@@ -113,7 +123,11 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     if (pl == nullptr) return fail(HSMA_E_NOMEM, "host allocation failed");
     pl->desc = *d;
     pl->bc = d->bc;
-    pl->img = (d->bc == HSMA_BC_METALLIC) ? IMG_METALLIC : IMG_PERIODIC;
+    pl->img = (d->bc == HSMA_BC_METALLIC) ? IMG_METALLIC : diel ? IMG_DIELECTRIC : IMG_PERIODIC;
+    if (diel) {
+        pl->gamma = d->gamma;
+        pl->far_shells = d->far_shells > 0 ? d->far_shells : far_shell_count(d->gamma, 1e-13);
+    }
     pl->p = d->p;
     pl->nb = nb;
     pl->nu = nu;
@@ -198,6 +212,8 @@ hsma_status hsma_plan_info(hsma_plan pl, hsma_plan_info_t* info) {
     info->dipole_mode = pl->dipole_mode;
     info->dr = pl->dr;
     info->far_mode = pl->far_mode;
+    info->gamma = pl->gamma;
+    info->far_shells = pl->far_shells;
     return HSMA_OK;
 }
 
@@ -282,6 +298,7 @@ hsma_status hsma_energy_grad_device(hsma_plan pl, const double* x, const double*
     if (pl->near_mode != HSMA_NEAR_BLOCK)
         return fail(HSMA_E_INVALID, "the adjoint needs the block near set (the sphere set moves "
                                     "images in and out as charges move)");
+    if (pl->bc == HSMA_BC_DIELECTRIC) return fail(HSMA_E_INVALID, "no adjoint for the dielectric box");
     if (pl->dipole_mode != HSMA_DIPOLE_EXACT || pl->far_mode != HSMA_FAR_SURFACE)
         return fail(HSMA_E_INVALID, "the adjoint needs the surface mapping with exact dipoles");
     const Layout ly = make_layout(pl, N, true);
@@ -307,7 +324,7 @@ hsma_status hsma_energy_forces(hsma_plan pl, const double* x, const double* q, i
         for (int a = 0; a < 3; ++a) {
             const double v = x[3 * i + a];
             if (!std::isfinite(v)) return fail(HSMA_E_INVALID, "non-finite position");
-            if (pl->bc == HSMA_BC_METALLIC && !(std::fabs(v - h) < h))
+            if ((pl->bc == HSMA_BC_METALLIC || pl->bc == HSMA_BC_DIELECTRIC) && !(std::fabs(v - h) < h))
                 return fail(HSMA_E_OUT_OF_BOX, "position on or outside a grounded wall");
             if (pl->bc == HSMA_BC_SLAB_METALLIC_Z && a == 2 && !(v > 0.0 && v < h))
                 return fail(HSMA_E_OUT_OF_BOX, "position on or outside a slab wall");
@@ -316,7 +333,7 @@ hsma_status hsma_energy_forces(hsma_plan pl, const double* x, const double* q, i
         qs += q[i];
         qa += std::fabs(q[i]);
     }
-    if (pl->bc != HSMA_BC_METALLIC && std::fabs(qs) > 1e-12 * qa)
+    if (needs_neutral(pl->bc) && std::fabs(qs) > 1e-12 * qa)
         return fail(HSMA_E_NOT_NEUTRAL, "periodic/slab system is not neutral");
     HSMA_HIP(hipSetDevice(pl->device));
     const Layout ly = make_layout(pl, N, false);

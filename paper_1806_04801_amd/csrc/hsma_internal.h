@@ -30,7 +30,9 @@ hsma_status fail(hsma_status st, const std::string& msg);
 //   IMG_SLAB    : the mirror-doubled periodic cube of the slab, taken over
 //                 the real charges only: r + kL with charge q and
 //                 (x, y, -z) + kL with charge -q (pair-once kernel only)
-enum { IMG_PERIODIC = 0, IMG_METALLIC = 1, IMG_FREE = 2, IMG_SLAB = 3 };
+//   IMG_DIELECTRIC: the positions of IMG_METALLIC with weight gamma^|k| q
+//                 (Eq. (diel), |gamma| < 1; per-target tiles in double)
+enum { IMG_PERIODIC = 0, IMG_METALLIC = 1, IMG_FREE = 2, IMG_SLAB = 3, IMG_DIELECTRIC = 4 };
 
 // Potential of the 26 images k != 0 of a unit charge at the origin in the
 // periodic 3x3x3 block of unit boxes: 6 + 12 / sqrt(2) + 8 / sqrt(3).  The
@@ -72,7 +74,7 @@ struct PairGeom {
     int S = 1;        // source chunks (grid.y)
     int chunk = 0;    // sources per chunk
 };
-PairGeom pair_geometry(int nt, int ns, int tpl, int ncu);
+PairGeom pair_geometry(int nt, int ns, int tpl, int ncu, int min_chunk = 64);
 
 // Geometry of the near sum that visits every unordered particle pair once:
 // blocks of B = 64 * T * s particles, nb blocks (P = nb rounded up to even),
@@ -111,6 +113,25 @@ struct TileGroup {
     double L;             // box side (physical units)
 };
 
+// A device pointer read from a descriptor in memory, marked as global memory
+// (an integer converted to a global pointer), so that accesses through it
+// compile to global or scalar loads instead of flat ones.
+template <typename P>
+__device__ __forceinline__ P* global_ptr(P* p) {
+    return (P*)(__attribute__((address_space(1))) P*)(uintptr_t)p;
+}
+
+// Periodic and slab systems must be neutral (their energy diverges
+// otherwise); grounded and dielectric boxes need not be.
+inline bool needs_neutral(int bc) { return bc == HSMA_BC_PERIODIC || bc == HSMA_BC_SLAB_METALLIC_Z; }
+
+// Far image shells S of a dielectric box (image weight gamma) whose omitted
+// tail is below tol * sum|q| / L on the circumsphere: shell s >= 2 holds
+// images with |k| >= s at distance >= (s - 1/2 - sqrt(3)/2) L from the
+// circumsphere's points, and its weights sum to at most 6 |gamma|^s c^2,
+// c = 1 + 2|gamma|/(1 - |gamma|).
+int far_shell_count(double gamma, double tol);
+
 // ---------------------------------------------------------------- plan
 struct hsma_plan_impl;
 }  // namespace hsma
@@ -130,6 +151,8 @@ struct hsma_plan_s {
     int dipole_mode = 0;  // HSMA_DIPOLE_EXACT or HSMA_DIPOLE_LAYERS
     double dr = 0.0;      // layer spacing (charge-layer dipoles)
     int far_mode = 0;     // HSMA_FAR_SURFACE or HSMA_FAR_DIRECT
+    double gamma = 0.0;   // dielectric box: image weight
+    int far_shells = 0;   // dielectric box: far image shells
     // host geometry (centred)
     std::vector<double> chk;    // nchk x 3: monitoring points then twins
     std::vector<double> spts;   // M x 3
@@ -150,7 +173,13 @@ namespace hsma {
 // Pair sums (pairs.hip).  out layout: out[(c * ncomp + comp) * nt_pad + t],
 // comp 0 = potential, 1..3 = field E = -grad phi; c = source chunk.
 hipError_t launch_pair_f64(int img, bool field, bool self, const double4* tgt, const double4* src,
-                           const PairGeom& g, double L, double* out, hipStream_t s);
+                           const PairGeom& g, double L, double* out, hipStream_t s,
+                           double gamma = 0.0);
+// Far images of a dielectric box at points (right-hand side): out[c * nt_pad + t]
+// = -sum over the sources of chunk c and the images in shells 2..S of
+// gamma^|k| q / |tgt_t - I_k(r)|.
+hipError_t launch_far_shells(const double4* tgt, const double4* src, const PairGeom& g, double L,
+                             double gamma, int S, double* out, hipStream_t s);
 // Single precision: records in units of L; outputs scaled back to physical
 // units (potential / L, field / L^2).
 hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, const Rec32* src,
@@ -158,8 +187,11 @@ hipError_t launch_pair_f32(int img, bool field, bool self, const Rec32* tgt, con
 // Surface images (X, Y, Z, Q, px, py, pz, 0) at targets (x, y, z, q).
 hipError_t launch_surface_f64(const double4* tgt, const double* surf, const PairGeom& g,
                               double* out, hipStream_t s);
-hipError_t launch_group_tiles(bool f32, const TileGroup* groups, int ngroups, int ntiles,
-                              hipStream_t s);
+// Grouped tiles of one kind (TILE_*) and, for near and right-hand-side
+// tiles, one image mode (IMG_PERIODIC or IMG_METALLIC); groups ordered by
+// first, ntiles tiles in all.
+hipError_t launch_group_tiles(bool f32, int kind, int img, const TileGroup* groups, int ngroups,
+                              int ntiles, hipStream_t s);
 // Near sum at the particles, each unordered pair once (img: IMG_PERIODIC,
 // IMG_METALLIC or IMG_SLAB, the last over the n real charges of the slab),
 // single precision on Rec32 records.  acc: (g.C + g.s) copies of 4 x g.n_pad

@@ -28,7 +28,7 @@ __device__ __forceinline__ void diffs_f64(double t, double s, double L, double (
     if (IMG == IMG_PERIODIC) {          // image s + kL
         d[0] = d0 + L;
         d[2] = d0 - L;
-    } else if (IMG == IMG_METALLIC) {   // image -s + kL
+    } else if (IMG == IMG_METALLIC || IMG == IMG_DIELECTRIC) {   // image -s + kL
         double sm = t + s;
         d[0] = sm + L;
         d[2] = sm - L;
@@ -76,10 +76,14 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 // periodic cube of 1e6 charges).  The pair's
 // potential comes back lowered by OWN_COLS_F32 / L per unit charge, which the
 // finalize stage restores exactly.
+//
+// IMG_DIELECTRIC weighs the images of the grounded-cube positions by
+// gamma^|k| (Eq. (diel)), the number of reflections |k| = 0..3.
 template <typename R, int IMG, bool FIELD, bool SELF, bool REV = false, bool OWN = false,
           bool SHIFT = false>
 __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], const R (&dz)[3],
-                                           R& pot, R& fx, R& fy, R& fz, R* rf = nullptr) {
+                                           R& pot, R& fx, R& fy, R& fz, R* rf = nullptr,
+                                           R gamma = R(0)) {
     constexpr int lo = (IMG == IMG_FREE) ? 1 : 0;
     constexpr int hi = (IMG == IMG_FREE) ? 2 : 3;
     R sx[3];
@@ -88,6 +92,11 @@ __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], c
     R S[3][3], Z[3];
     R r2c = R(1);
     constexpr bool SH = SHIFT && sizeof(R) == sizeof(float) && IMG == IMG_PERIODIC;
+    R wgt[4] = {R(1), gamma, R(0), R(0)};   // gamma^(reflections), dielectric only
+    if (IMG == IMG_DIELECTRIC) {
+        wgt[2] = gamma * gamma;
+        wgt[3] = wgt[2] * gamma;
+    }
     pot = R(0);
 #pragma unroll
     for (int a = lo; a < hi; ++a) {
@@ -101,7 +110,8 @@ __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], c
                 R y = rsq_t(r2);
                 if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > R(0)) ? y : R(0);
                 const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
-                const R ys = neg ? -y : y;
+                const int nref = (a != 1) + (b != 1) + (c != 1);
+                const R ys = IMG == IMG_DIELECTRIC ? (nref == 0 ? y : y * wgt[nref]) : neg ? -y : y;
                 if (SH && c == lo) {
                     const R cab = (a == 1 && b == 1) ? R(OWN_COL_CENTRE)
                                   : (a == 1 || b == 1) ? R(OWN_COL_EDGE) : R(OWN_COL_CORNER);
@@ -131,7 +141,7 @@ __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], c
             X[a] = x;
             Y[a] = yv;
         }
-        if (REV && IMG == IMG_METALLIC) {
+        if (REV && (IMG == IMG_METALLIC || IMG == IMG_DIELECTRIC)) {
             // reflected images first, then the central one with both signs
             const R ox = fma_t(dx[0], X[0], dx[2] * X[2]);
             const R oy = fma_t(dy[0], Y[0], dy[2] * Y[2]);

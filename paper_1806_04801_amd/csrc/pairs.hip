@@ -33,7 +33,8 @@ constexpr int WG = 256;
 template <int IMG, bool FIELD, bool SELF, int T>
 __device__ __forceinline__ void tile_pair_f64(int tb, int c, const double4* __restrict__ tgt, int nt,
                                               const double4* __restrict__ src, int ns, int chunk,
-                                              double L, double* __restrict__ out, int nt_pad) {
+                                              double L, double* __restrict__ out, int nt_pad,
+                                              double gamma = 0.0) {
     const int j0 = c * chunk;
     const int j1 = min(j0 + chunk, ns);
     double tx[T], ty[T], tz[T], ap[T], ax[T], ay[T], az[T];
@@ -53,7 +54,8 @@ __device__ __forceinline__ void tile_pair_f64(int tb, int c, const double4* __re
             diffs_f64<IMG>(ty[u], s.y, L, dy);
             diffs_f64<IMG>(tz[u], s.z, L, dz);
             double pot, fx, fy, fz;
-            images_sum<double, IMG, FIELD, SELF, false, SELF>(dx, dy, dz, pot, fx, fy, fz);
+            images_sum<double, IMG, FIELD, SELF, false, SELF && IMG == IMG_PERIODIC>(
+                dx, dy, dz, pot, fx, fy, fz, nullptr, gamma);
             ap[u] = __builtin_fma(s.w, pot, ap[u]);
             if (FIELD) {
                 ax[u] = __builtin_fma(s.w, fx, ax[u]);
@@ -79,8 +81,73 @@ __device__ __forceinline__ void tile_pair_f64(int tb, int c, const double4* __re
 template <int IMG, bool FIELD, bool SELF, int T>
 __global__ void __launch_bounds__(WG)
 k_pair_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ src, int ns,
-           int chunk, double L, double* __restrict__ out, int nt_pad) {
-    tile_pair_f64<IMG, FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, L, out, nt_pad);
+           int chunk, double L, double* __restrict__ out, int nt_pad, double gamma) {
+    tile_pair_f64<IMG, FIELD, SELF, T>(blockIdx.x, blockIdx.y, tgt, nt, src, ns, chunk, L, out, nt_pad,
+                                       gamma);
+}
+
+// ---------------------------------------------------------------- far images (dielectric box)
+// The far part of the dielectric image series at the monitoring points: per
+// lane one point; per source of the chunk every image I_k(r) = (-1)^k o r + kL
+// with 2 <= max_a |k_a| <= S and weight gamma^|k|, in the order k_x, k_y, k_z
+// (the inner block, |k_a| <= 1 on every axis, is skipped).  The powers
+// gamma^m, m = 0..S, sit in LDS (every lane reads the same entry); the
+// weight of an (x, y) line is hoisted out of the z loop.  The negated sum goes
+// to the chunk's partial (the right-hand side is -Phi_far).
+constexpr int MAX_FAR_SHELLS = 400;
+
+__global__ void __launch_bounds__(WG)
+k_far_shells_f64(const double4* __restrict__ tgt, int nt, const double4* __restrict__ src, int ns,
+                 int chunk, double L, double gamma, int S, double* __restrict__ out, int nt_pad) {
+    __shared__ double pw[MAX_FAR_SHELLS + 1];
+    if (threadIdx.x == 0) {
+        double w = 1.0;
+        for (int m = 0; m <= S; ++m) {
+            pw[m] = w;
+            w *= gamma;
+        }
+    }
+    __syncthreads();
+    const int t = blockIdx.x * WG + threadIdx.x;
+    const double4 p = tgt[min(t, nt - 1)];
+    const int j0 = blockIdx.y * chunk;
+    const int j1 = min(j0 + chunk, ns);
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double4 r = src[j];
+        double sx = 0.0;
+        for (int kx = -S; kx <= S; ++kx) {
+            const int ax = kx < 0 ? -kx : kx;
+            const double dx = p.x - (((kx & 1) ? -r.x : r.x) + kx * L);
+            double sy = 0.0;
+            for (int ky = -S; ky <= S; ++ky) {
+                const int ay = ky < 0 ? -ky : ky;
+                const double dy = p.y - (((ky & 1) ? -r.y : r.y) + ky * L);
+                const double dxy = __builtin_fma(dy, dy, dx * dx);
+                const bool inner = ax <= 1 && ay <= 1;
+                double sz = 0.0;
+                for (int kz = -S; kz <= S; ++kz) {
+                    const int az = kz < 0 ? -kz : kz;
+                    if (inner && az <= 1) continue;
+                    const double dz = p.z - (((kz & 1) ? -r.z : r.z) + kz * L);
+                    sz = __builtin_fma(pw[az], rsqrt_f64(__builtin_fma(dz, dz, dxy)), sz);
+                }
+                sy = __builtin_fma(pw[ay], sz, sy);
+            }
+            sx = __builtin_fma(pw[ax], sy, sx);
+        }
+        acc = __builtin_fma(r.w, sx, acc);
+    }
+    if (t < nt) out[(size_t)blockIdx.y * nt_pad + t] = -acc;
+}
+
+hipError_t launch_far_shells(const double4* tgt, const double4* src, const PairGeom& g, double L,
+                             double gamma, int S, double* out, hipStream_t s) {
+    if (g.nt <= 0 || g.ns <= 0 || g.tpl != 1) return g.nt <= 0 ? hipSuccess : hipErrorInvalidValue;
+    if (S < 1 || S > MAX_FAR_SHELLS) return hipErrorInvalidValue;   // S = 1: no far images, zeros
+    hipLaunchKernelGGL(k_far_shells_f64, dim3(g.ntb, g.S), dim3(WG), 0, s, tgt, g.nt, src, g.ns,
+                       g.chunk, L, gamma, S, out, g.nt_pad);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- single precision
@@ -413,12 +480,15 @@ __global__ void k_make_rec32(const double4* __restrict__ p, int n, double L, Rec
 }
 
 // ---------------------------------------------------------------- grouped tiles
-// One launch over the tiles of many requests (continuous batching).  Work-group
-// g finds its group by a binary search over the groups' first-tile indices
-// (wave-uniform, so it runs on scalar loads), then runs the same tile function
-// as the single-request kernels with one target per lane.  Kind, image mode and
-// operands are uniform over the work-group, so each takes one branch.
-template <bool F32>
+// One launch over the tiles of many requests (continuous batching), all of one
+// kind and image mode, so that every launch compiles to the registers of its
+// own tile function.  Work-group g finds its group by a binary search over the
+// groups' first-tile indices (wave-uniform, so it runs on scalar loads), then
+// runs the same tile function as the single-request kernels with one target
+// per lane.  The operand pointers come from the descriptors in memory and are
+// marked as global memory, so that the wave-uniform source reads compile to
+// scalar loads as in the single-request kernels.
+template <bool F32, int KIND, int IMG>
 __global__ void __launch_bounds__(WG) k_group_tiles(const TileGroup* __restrict__ groups,
                                                    int ngroups) {
     const int g = blockIdx.x;
@@ -428,50 +498,56 @@ __global__ void __launch_bounds__(WG) k_group_tiles(const TileGroup* __restrict_
         if (groups[mid].first <= g) lo = mid;
         else hi = mid - 1;
     }
-    const TileGroup it = groups[lo];
-    const int i = g - it.first;
-    const int c = i / it.ntb;
-    const int tb = i - c * it.ntb;
-    if (it.kind == TILE_SURFACE) {
-        tile_surface_f64<1>(tb, c, (const double4*)it.tgt, it.nt, (const double*)it.src, it.ns,
-                            it.chunk, it.out, it.nt_pad);
-        return;
-    }
-    const bool near = it.kind == TILE_NEAR;
-    if (F32) {
-        const Rec32* t = (const Rec32*)it.tgt;
-        const Rec32* s = (const Rec32*)it.src;
-        const double iL = 1.0 / it.L;
-        if (it.img == IMG_PERIODIC) {
-            if (near) tile_pair_f32<IMG_PERIODIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
-            else tile_pair_f32<IMG_PERIODIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
-        } else {
-            if (near) tile_pair_f32<IMG_METALLIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
-            else tile_pair_f32<IMG_METALLIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.out, it.nt_pad, iL);
-        }
+    const TileGroup* it = groups + lo;
+    const int i = g - it->first;
+    const int ntb = it->ntb;
+    const int c = i / ntb;
+    const int tb = i - c * ntb;
+    const int nt = it->nt, ns = it->ns, chunk = it->chunk, nt_pad = it->nt_pad;
+    double* out = global_ptr(it->out);
+    if (KIND == TILE_SURFACE) {
+        tile_surface_f64<1>(tb, c, global_ptr((const double4*)it->tgt), nt,
+                            global_ptr((const double*)it->src), ns, chunk, out, nt_pad);
+    } else if (F32) {
+        constexpr bool NEAR = KIND == TILE_NEAR;
+        tile_pair_f32<IMG, NEAR, NEAR, 1>(tb, c, global_ptr((const Rec32*)it->tgt), nt,
+                                          global_ptr((const Rec32*)it->src), ns, chunk, out, nt_pad,
+                                          1.0 / it->L);
     } else {
-        const double4* t = (const double4*)it.tgt;
-        const double4* s = (const double4*)it.src;
-        if (it.img == IMG_PERIODIC) {
-            if (near) tile_pair_f64<IMG_PERIODIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
-            else tile_pair_f64<IMG_PERIODIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
-        } else {
-            if (near) tile_pair_f64<IMG_METALLIC, true, true, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
-            else tile_pair_f64<IMG_METALLIC, false, false, 1>(tb, c, t, it.nt, s, it.ns, it.chunk, it.L, it.out, it.nt_pad);
-        }
+        constexpr bool NEAR = KIND == TILE_NEAR;
+        tile_pair_f64<IMG, NEAR, NEAR, 1>(tb, c, global_ptr((const double4*)it->tgt), nt,
+                                          global_ptr((const double4*)it->src), ns, chunk, it->L, out,
+                                          nt_pad);
     }
 }
 
-hipError_t launch_group_tiles(bool f32, const TileGroup* groups, int ngroups, int ntiles,
-                              hipStream_t s) {
+template <bool F32>
+static void group_tiles(int kind, int img, const TileGroup* groups, int ngroups, int ntiles,
+                        hipStream_t s) {
+    const dim3 grid(ntiles), blk(WG);
+    if (kind == TILE_SURFACE)
+        hipLaunchKernelGGL((k_group_tiles<false, TILE_SURFACE, IMG_FREE>), grid, blk, 0, s, groups, ngroups);
+    else if (kind == TILE_NEAR && img == IMG_PERIODIC)
+        hipLaunchKernelGGL((k_group_tiles<F32, TILE_NEAR, IMG_PERIODIC>), grid, blk, 0, s, groups, ngroups);
+    else if (kind == TILE_NEAR)
+        hipLaunchKernelGGL((k_group_tiles<F32, TILE_NEAR, IMG_METALLIC>), grid, blk, 0, s, groups, ngroups);
+    else if (img == IMG_PERIODIC)
+        hipLaunchKernelGGL((k_group_tiles<F32, TILE_RHS, IMG_PERIODIC>), grid, blk, 0, s, groups, ngroups);
+    else
+        hipLaunchKernelGGL((k_group_tiles<F32, TILE_RHS, IMG_METALLIC>), grid, blk, 0, s, groups, ngroups);
+}
+
+hipError_t launch_group_tiles(bool f32, int kind, int img, const TileGroup* groups, int ngroups,
+                              int ntiles, hipStream_t s) {
     if (ntiles <= 0 || ngroups <= 0) return hipSuccess;
-    if (f32) hipLaunchKernelGGL(k_group_tiles<true>, dim3(ntiles), dim3(WG), 0, s, groups, ngroups);
-    else hipLaunchKernelGGL(k_group_tiles<false>, dim3(ntiles), dim3(WG), 0, s, groups, ngroups);
+    if (kind != TILE_SURFACE && img != IMG_PERIODIC && img != IMG_METALLIC) return hipErrorInvalidValue;
+    if (f32) group_tiles<true>(kind, img, groups, ngroups, ntiles, s);
+    else group_tiles<false>(kind, img, groups, ngroups, ntiles, s);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- launch
-PairGeom pair_geometry(int nt, int ns, int tpl, int ncu) {
+PairGeom pair_geometry(int nt, int ns, int tpl, int ncu, int min_chunk) {
     PairGeom g;
     g.nt = nt;
     g.ns = ns;
@@ -483,10 +559,12 @@ PairGeom pair_geometry(int nt, int ns, int tpl, int ncu) {
         g.chunk = 0;
         return g;
     }
-    // aim at about 20 resident waves per CU times 4 rounds, chunks of >= 64 sources
+    // aim at about 20 resident waves per CU times 4 rounds, chunks of at least
+    // min_chunk sources (64 for the block images)
     const long want_wg = 20L * ncu;
     long S = (want_wg + g.ntb - 1) / g.ntb;
-    long maxS = (ns + 63) / 64;
+    const long mc = min_chunk > 0 ? min_chunk : 1;
+    long maxS = (ns + mc - 1) / mc;
     if (S > maxS) S = maxS;
     if (S < 1) S = 1;
     g.chunk = (int)((ns + S - 1) / S);
@@ -496,14 +574,14 @@ PairGeom pair_geometry(int nt, int ns, int tpl, int ncu) {
 
 template <int IMG, bool FIELD, bool SELF>
 static hipError_t pair64(const double4* tgt, const double4* src, const PairGeom& g, double L,
-                         double* out, hipStream_t s) {
+                         double* out, hipStream_t s, double gamma = 0.0) {
     dim3 grid(g.ntb, g.S);
     if (g.tpl == 2)
         hipLaunchKernelGGL((k_pair_f64<IMG, FIELD, SELF, 2>), grid, dim3(WG), 0, s, tgt, g.nt, src,
-                           g.ns, g.chunk, L, out, g.nt_pad);
+                           g.ns, g.chunk, L, out, g.nt_pad, gamma);
     else
         hipLaunchKernelGGL((k_pair_f64<IMG, FIELD, SELF, 1>), grid, dim3(WG), 0, s, tgt, g.nt, src,
-                           g.ns, g.chunk, L, out, g.nt_pad);
+                           g.ns, g.chunk, L, out, g.nt_pad, gamma);
     return hipGetLastError();
 }
 
@@ -521,8 +599,10 @@ static hipError_t pair32(const Rec32* tgt, const Rec32* src, const PairGeom& g, 
 }
 
 hipError_t launch_pair_f64(int img, bool field, bool self, const double4* tgt, const double4* src,
-                           const PairGeom& g, double L, double* out, hipStream_t s) {
+                           const PairGeom& g, double L, double* out, hipStream_t s, double gamma) {
     if (g.nt <= 0) return hipSuccess;
+    if (img == IMG_DIELECTRIC && field && self)
+        return pair64<IMG_DIELECTRIC, true, true>(tgt, src, g, L, out, s, gamma);
     if (g.tpl != 1 && g.tpl != 2) return hipErrorInvalidValue;
     if (img == IMG_PERIODIC) {
         if (field) return self ? pair64<IMG_PERIODIC, true, true>(tgt, src, g, L, out, s)

@@ -263,13 +263,15 @@ static double unit_double(uint64_t z) { return (double)(z >> 11) * (1.0 / 900719
 
 // Monitoring points: Fibonacci spiral on the circumsphere (latitude
 // asin((2i-1)/K - 1), azimuth 2 pi i w, w the golden ratio conjugate) with
-// twins x - L floor(x/L + 1/2) (Sec. II.A, periodic); or points on the cube
+// twins x - L floor(x/L + 1/2) (Sec. II.A, periodic) or without (dielectric
+// box: the far images themselves are fitted there); or points on the cube
 // faces, point i on face i mod 6, tangential coordinates from SplitMix64.
 static void monitoring(hsma_plan_s* pl) {
     const int K = pl->K;
     const double L = pl->L;
-    if (pl->img == IMG_PERIODIC) {
-        pl->chk.assign((size_t)6 * K, 0.0);
+    if (pl->img == IMG_PERIODIC || pl->img == IMG_DIELECTRIC) {
+        const bool twins = pl->img == IMG_PERIODIC;
+        pl->chk.assign((size_t)(twins ? 6 : 3) * K, 0.0);
         const double w = (std::sqrt(5.0) - 1.0) / 2.0;
         for (int i = 1; i <= K; ++i) {
             const double s = (2.0 * i - 1.0) / K - 1.0;
@@ -279,6 +281,7 @@ static void monitoring(hsma_plan_s* pl) {
             x[0] = pl->R0 * std::cos(lat) * std::cos(az);
             x[1] = pl->R0 * std::cos(lat) * std::sin(az);
             x[2] = pl->R0 * std::sin(lat);
+            if (!twins) continue;
             double* t = &pl->chk[(size_t)3 * (K + i - 1)];
             for (int a = 0; a < 3; ++a) t[a] = x[a] - L * std::floor(x[a] / L + 0.5);
         }
@@ -338,6 +341,16 @@ static void surface_points(hsma_plan_s* pl) {
             pl->swts[2 * j + e] = wt;
         }
     }
+}
+
+int far_shell_count(double gamma, double tol) {
+    const double g = std::fabs(gamma);
+    if (g == 0.0) return 1;
+    const double c = 1.0 + 2.0 * g / (1.0 - g);
+    int S = 2;
+    while (S < 400 && 6.0 * c * c * std::pow(g, S + 1) / ((1.0 - g) * (S + 0.5 - std::sqrt(3.0) / 2.0)) > tol)
+        ++S;
+    return S;
 }
 
 // ---------------------------------------------------------------- plan build

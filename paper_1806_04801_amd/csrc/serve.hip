@@ -8,7 +8,10 @@
 //   3. enqueues, on its stream, one set of grouped launches in which every
 //      active request advances one stage:
 //        stage A (newly admitted): centring, single-precision records, and
-//          the right-hand-side and near-field tiles;
+//          the right-hand-side and near-field tiles, or for requests of 1024
+//          particles and more the pair-once near sum, each on one of a few
+//          side streams, so that the near sums of several requests and the
+//          grouped tiles run at the same time;
 //        stage B (admitted one tick earlier): right-hand-side reduction, least
 //          squares, surface mapping, surface tiles, finalization, energy,
 //          and the copy of the results to pinned host memory.
@@ -196,6 +199,14 @@ struct hsma_server_s {
     int ring = 0;
     std::deque<hipEvent_t> inflight;
     std::vector<hipEvent_t> evpool;
+    // side streams of the pair-once near sums (default priority), with the
+    // fork event on the server stream and one join event each
+    static constexpr int NSIDE = 8;
+    int nside = 3;
+    double tick_work = 1.5e11;   // pair-image budget of the requests a tick admits
+    hipStream_t side[NSIDE] = {};
+    hipEvent_t side_ev[NSIDE] = {};
+    hipEvent_t fork_ev = nullptr;
     hsma_server_stats_t stats{};
 };
 
@@ -275,7 +286,7 @@ static bool admit(hsma_server_s* sv, SrvReq* r) {
     d.M = pl->M;
     d.k0 = pl->nb - pl->nu;
     d.twins = pl->img == IMG_PERIODIC ? 1 : 0;
-    d.need_neutral = pl->bc != HSMA_BC_METALLIC ? 1 : 0;
+    d.need_neutral = needs_neutral(pl->bc) ? 1 : 0;
     d.L = pl->L;
     d.Rs = pl->Rs;
     d.P = pl->d_P;
@@ -465,6 +476,13 @@ static hsma_status start_refinements(hsma_server_s* sv, bool* blocked) {
     return HSMA_OK;
 }
 
+// Pair-image evaluations of a request: the near block (27 N_s per particle)
+// and the right-hand side (27 N_s per check point).
+static double request_work(const hsma_plan_s* pl, int N) {
+    const double ns = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? 2.0 * N : (double)N;
+    return 27.0 * ns * ((double)N + (double)pl->nchk);
+}
+
 static hsma_status tick(hsma_server_s* sv) {
     HSMA_HIP(hipSetDevice(sv->device));
     retire(sv);
@@ -484,16 +502,23 @@ static hsma_status tick(hsma_server_s* sv) {
         if (st != HSMA_OK) return st;
     }
     const bool refine_started = sv->refine.size() < refine_queued;
-    // admission
+    // admission: FIFO while a slot and arena memory are free and the tick's
+    // pair work stays within its budget (a request larger than the budget
+    // comes alone), so that ticks stay short, two of them keep the GPU busy
+    // and a finishing request frees its slot for the queue within a few ticks
     std::vector<SrvReq*> newA;
+    double tick_work = 0.0;
     while (!refine_blocked && !sv->pending.empty() &&
            (int)sv->active.size() < sv->desc.max_active) {
         SrvReq* r = sv->pending.front();
+        const double w = request_work(r->plan, r->N);
+        if (!newA.empty() && tick_work + w > sv->tick_work) break;
         if (!admit(sv, r)) break;
         sv->pending.pop_front();
         r->state = ST_STAGE_A;
         sv->active.push_back(r);
         newA.push_back(r);
+        tick_work += w;
     }
     std::vector<SrvReq*> stB;
     for (SrvReq* r : sv->active)
@@ -511,8 +536,14 @@ static hsma_status tick(hsma_server_s* sv) {
     }
     const bool f32 = sv->desc.precision == HSMA_FP32_COMP;
     std::vector<ReqDesc> da, db;
-    std::vector<TileGroup> tiles;
-    int ntiles = 0;
+    // tile groups in five lists, one launch each: near (periodic, grounded),
+    // right-hand side (periodic, grounded), surface
+    constexpr int NLIST = 5;
+    std::vector<TileGroup> lists[NLIST];
+    int nlist_tiles[NLIST] = {0, 0, 0, 0, 0};
+    auto list_of = [](int kind, int img) {
+        return kind == TILE_SURFACE ? 4 : 2 * (kind == TILE_RHS ? 1 : 0) + (img == IMG_PERIODIC ? 0 : 1);
+    };
     int maxA_blk = 1, maxA_ns = 1, maxB_K = 1, maxB_nu = 1, maxB_M = 1, maxB_e = 1;
     for (SrvReq* r : newA) {
         da.push_back(r->d);
@@ -532,17 +563,27 @@ static hsma_status tick(hsma_server_s* sv) {
     for (SrvReq* r : newA) {
         const ReqDesc& d = r->d;
         if (r->ly.sym) continue;
-        if (f32) add_group(tiles, &ntiles, TILE_NEAR, d.img, r->ly.g_near, d.src32, d.src32, d.near_part, d.L);
-        else add_group(tiles, &ntiles, TILE_NEAR, d.img, r->ly.g_near, d.src64, d.src64, d.near_part, d.L);
+        const int l = list_of(TILE_NEAR, d.img);
+        if (f32) add_group(lists[l], &nlist_tiles[l], TILE_NEAR, d.img, r->ly.g_near, d.src32, d.src32, d.near_part, d.L);
+        else add_group(lists[l], &nlist_tiles[l], TILE_NEAR, d.img, r->ly.g_near, d.src64, d.src64, d.near_part, d.L);
     }
     for (SrvReq* r : newA) {
         const hsma_plan_s* pl = r->plan;
         const ReqDesc& d = r->d;
-        if (f32) add_group(tiles, &ntiles, TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk32, d.src32, d.rhs_part, d.L);
-        else add_group(tiles, &ntiles, TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk64, d.src64, d.rhs_part, d.L);
+        const int l = list_of(TILE_RHS, d.img);
+        if (f32) add_group(lists[l], &nlist_tiles[l], TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk32, d.src32, d.rhs_part, d.L);
+        else add_group(lists[l], &nlist_tiles[l], TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk64, d.src64, d.rhs_part, d.L);
     }
     for (SrvReq* r : stB)
-        add_group(tiles, &ntiles, TILE_SURFACE, 0, r->ly.g_surf, r->d.src64, r->d.surf, r->d.surf_part, r->d.L);
+        add_group(lists[4], &nlist_tiles[4], TILE_SURFACE, 0, r->ly.g_surf, r->d.src64, r->d.surf, r->d.surf_part, r->d.L);
+    std::vector<TileGroup> tiles;
+    int list_at[NLIST];
+    int ntiles = 0;
+    for (int l = 0; l < NLIST; ++l) {
+        list_at[l] = (int)tiles.size();
+        tiles.insert(tiles.end(), lists[l].begin(), lists[l].end());
+        ntiles += nlist_tiles[l];
+    }
     ReqDesc *dA = nullptr, *dB = nullptr;
     TileGroup* dT = nullptr;
     hsma_status st = upload(sv, da, db, tiles, &dA, &dB, &dT);
@@ -565,17 +606,44 @@ static hsma_status tick(hsma_server_s* sv) {
         if (f32) hipLaunchKernelGGL(k_g_rec32, dim3(maxA_ns, nA), dim3(SWG), 0, s, dA);
     }
     HSMA_HIP(hipGetLastError());
-    // pair-once near sums of the large new requests (each round fills the GPU
-    // by itself), then all pair tiles of the tick in one launch
-    timing_begin(0, s);
-    for (SrvReq* r : newA) {
-        if (!r->ly.sym) continue;
-        if (f32)
-            HSMA_HIP(launch_sym_f32(r->ly.sym_img, r->d.src32, r->ly.g_sym, r->d.L, r->d.near_part, s));
-        else
-            HSMA_HIP(launch_sym_f64(r->ly.sym_img, r->d.src64, r->ly.g_sym, r->d.L, r->d.near_part, s));
+    // Pair-once near sums of the new requests at or above the threshold: each
+    // request's launches go to one of the side streams (the one with the least
+    // work so far, largest requests first), forked from the server stream after
+    // the records above, so that the near sums of several requests and the
+    // grouped tiles below run at the same time; the side streams join back
+    // at the end of the tick.
+    std::vector<SrvReq*> symr;
+    for (SrvReq* r : newA)
+        if (r->ly.sym) symr.push_back(r);
+    std::stable_sort(symr.begin(), symr.end(), [](const SrvReq* a, const SrvReq* b) { return a->N > b->N; });
+    bool side_used[hsma_server_s::NSIDE] = {};
+    if (!symr.empty()) {
+        HSMA_HIP(hipEventRecord(sv->fork_ev, s));
+        double load[hsma_server_s::NSIDE] = {};
+        for (SrvReq* r : symr) {
+            int w = 0;
+            for (int k = 1; k < sv->nside; ++k)
+                if (load[k] < load[w]) w = k;
+            load[w] += (double)r->N * r->N;
+            hipStream_t ss = sv->side[w];
+            if (!side_used[w]) {
+                HSMA_HIP(hipStreamWaitEvent(ss, sv->fork_ev, 0));
+                side_used[w] = true;
+            }
+            if (f32)
+                HSMA_HIP(launch_sym_f32(r->ly.sym_img, r->d.src32, r->ly.g_sym, r->d.L, r->d.near_part, ss));
+            else
+                HSMA_HIP(launch_sym_f64(r->ly.sym_img, r->d.src64, r->ly.g_sym, r->d.L, r->d.near_part, ss));
+        }
     }
-    HSMA_HIP(launch_group_tiles(f32, dT, (int)tiles.size(), ntiles, s));
+    // the pair tiles of the tick, one launch per kind
+    timing_begin(0, s);
+    for (int l = 0; l < NLIST; ++l) {
+        if (lists[l].empty()) continue;
+        const TileGroup& g0 = lists[l].front();
+        HSMA_HIP(launch_group_tiles(f32, g0.kind, g0.img, dT + list_at[l], (int)lists[l].size(),
+                                    nlist_tiles[l], s));
+    }
     timing_end(0, s);
     // stage B, part 2: finalize, energy, results to host
     if (nB) {
@@ -593,6 +661,13 @@ static hsma_status tick(hsma_server_s* sv) {
             r->state = ST_COPYING;
         }
     }
+    // join the side streams: the next tick's stage B of these requests reads
+    // their near sums
+    for (int w = 0; w < sv->nside; ++w)
+        if (side_used[w]) {
+            HSMA_HIP(hipEventRecord(sv->side_ev[w], sv->side[w]));
+            HSMA_HIP(hipStreamWaitEvent(s, sv->side_ev[w], 0));
+        }
     for (SrvReq* r : newA) r->state = ST_STAGE_B;
     hipEvent_t te = srv_event(sv);
     HSMA_HIP(hipEventRecord(te, s));
@@ -626,6 +701,13 @@ hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out) {
         hipFree(sv->arena_base);
         hipHostFree(sv->host_base);
         if (sv->stream) hipStreamDestroy(sv->stream);
+        for (int i = 0; i < hsma_server_s::RING; ++i)
+            if (sv->tabev[i]) hipEventDestroy(sv->tabev[i]);
+        for (int w = 0; w < hsma_server_s::NSIDE; ++w) {
+            if (sv->side[w]) hipStreamDestroy(sv->side[w]);
+            if (sv->side_ev[w]) hipEventDestroy(sv->side_ev[w]);
+        }
+        if (sv->fork_ev) hipEventDestroy(sv->fork_ev);
         delete sv;
         return fail(st, m);
     };
@@ -643,6 +725,26 @@ hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out) {
     for (int i = 0; i < hsma_server_s::RING; ++i)
         if (hipEventCreateWithFlags(&sv->tabev[i], hipEventDisableTiming) != hipSuccess)
             return bail(HSMA_E_DEVICE, "event creation failed");
+    // side streams of the pair-once near sums: HSMA_SRV_STREAMS (1 to 8,
+    // default 3) in the environment
+    {
+        const char* v = getenv("HSMA_SRV_STREAMS");
+        const int n = v != nullptr && *v ? atoi(v) : 3;
+        sv->nside = std::min(std::max(n, 1), hsma_server_s::NSIDE);
+    }
+    // pair-image budget of a tick's admissions: HSMA_SRV_TICK_WORK (default
+    // 1.5e11, about 17 ms of single-precision near sums)
+    {
+        const char* v = getenv("HSMA_SRV_TICK_WORK");
+        const double w = v != nullptr && *v ? atof(v) : 0.0;
+        if (w > 0.0) sv->tick_work = w;
+    }
+    if (hipEventCreateWithFlags(&sv->fork_ev, hipEventDisableTiming) != hipSuccess)
+        return bail(HSMA_E_DEVICE, "event creation failed");
+    for (int w = 0; w < sv->nside; ++w)
+        if (hipStreamCreateWithFlags(&sv->side[w], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sv->side_ev[w], hipEventDisableTiming) != hipSuccess)
+            return bail(HSMA_E_DEVICE, "side stream creation failed");
     *out = sv;
     return HSMA_OK;
 }
@@ -662,6 +764,12 @@ void hsma_server_destroy(hsma_server sv) {
         hipHostFree(sv->htab[i]);
         hipEventDestroy(sv->tabev[i]);
     }
+    for (int w = 0; w < sv->nside; ++w) {
+        hipStreamSynchronize(sv->side[w]);
+        hipStreamDestroy(sv->side[w]);
+        hipEventDestroy(sv->side_ev[w]);
+    }
+    hipEventDestroy(sv->fork_ev);
     hipFree(sv->arena_base);
     hipHostFree(sv->host_base);
     hipStreamDestroy(sv->stream);
@@ -674,8 +782,9 @@ static hsma_status submit_impl(hsma_server sv, hsma_plan plan, const double* x, 
         return fail(HSMA_E_INVALID, "NULL argument");
     if (N < 1 || N > ((int64_t)1 << 26)) return fail(HSMA_E_INVALID, "N out of range");
     if (plan->near_mode != HSMA_NEAR_BLOCK || plan->dipole_mode != HSMA_DIPOLE_EXACT ||
-        plan->far_mode != HSMA_FAR_SURFACE)
-        return fail(HSMA_E_INVALID, "the server runs block near-set, exact-dipole plans only");
+        plan->far_mode != HSMA_FAR_SURFACE || plan->bc == HSMA_BC_DIELECTRIC)
+        return fail(HSMA_E_INVALID, "the server runs block near-set, exact-dipole plans of the "
+                                    "periodic, grounded-cube and slab boxes only");
     Layout ly;
     if (req_device_bytes(plan, (int)N, sv->desc.precision, &ly) > sv->arena->cap() ||
         req_host_bytes((int)N) > sv->host_arena->cap()) {

@@ -54,7 +54,11 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     // partial buffers are sized for that bound
     ly.img_max = sphere ? (int64_t)ly.ns * pl->maxper : 0;
     const int ns_pairs = sphere ? (int)std::min<int64_t>(ly.img_max, INT32_MAX) : ly.ns;
-    ly.g_rhs = pair_geometry(pl->nchk, ns_pairs, tpl_rhs, pl->ncu);
+    const bool diel = pl->img == IMG_DIELECTRIC;
+    // the far images of a dielectric box: many images per source, so chunks
+    // of any size (the block images take at least 64 sources per chunk)
+    ly.g_rhs = diel ? pair_geometry(pl->nchk, ns_pairs, 1, pl->ncu, 1)
+                    : pair_geometry(pl->nchk, ns_pairs, tpl_rhs, pl->ncu);
     ly.g_near = pair_geometry(ly.N, ns_pairs, tpl_near, pl->ncu);
     // Pair-once near sum: faster than the tiles from 1024 particles in either
     // precision (measured; in the batched server too, where a request's rounds
@@ -64,7 +68,7 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     {
         const int mode = env_int("HSMA_SYM", -1);
         const int nmin = env_int("HSMA_SYM_MIN", 1024);
-        const bool eligible = !sphere && ly.N > 0;
+        const bool eligible = !sphere && !diel && ly.N > 0;
         ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
         ly.sym_img = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? IMG_SLAB : pl->img;
         if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 1), !f32, ly.sym_img, pl->ncu);
@@ -382,6 +386,8 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     if (sphere)
         CK(launch_explicit(f32, false, false, f32 ? (const void*)pl->d_chk32 : (const void*)pl->d_chk64,
                            f32 ? (const void*)img32 : (const void*)img64, g_rhs, pl->L, rhs_part, s1));
+    else if (pl->img == IMG_DIELECTRIC)
+        CK(launch_far_shells(pl->d_chk64, src64, g_rhs, pl->L, pl->gamma, pl->far_shells, rhs_part, s1));
     else if (f32)
         CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, g_rhs, pl->L, rhs_part, s1));
     else
@@ -415,7 +421,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     else if (f32)
         CK(launch_pair_f32(pl->img, true, true, src32, src32, g_near, pl->L, near_part, s));
     else
-        CK(launch_pair_f64(pl->img, true, true, src64, src64, g_near, pl->L, near_part, s));
+        CK(launch_pair_f64(pl->img, true, true, src64, src64, g_near, pl->L, near_part, s, pl->gamma));
     timing_end(0, s);
     // join, then the surface images at the particles
     if (aux != nullptr) {
@@ -440,7 +446,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
                        forces, dbg ? dbg->phi_near : nullptr, dbg ? dbg->field_near : nullptr,
                        dbg ? dbg->phi_out : nullptr, dbg ? dbg->field_out : nullptr, eblk);
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(WG), 0, s, eblk, ly.n_eblk,
-                       pl->bc != HSMA_BC_METALLIC ? 1 : 0, res);
+                       needs_neutral(pl->bc) ? 1 : 0, res);
     CK(hipGetLastError());
     if (dbg) {
         if (dbg->b) CK(hipMemcpyAsync(dbg->b, b, sizeof(double) * pl->K, hipMemcpyDeviceToDevice, s));

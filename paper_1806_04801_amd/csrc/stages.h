@@ -28,7 +28,7 @@ __device__ __forceinline__ void prep_body(int i, const double* __restrict__ x,
             v -= L * floor(v / L + 0.5);
             c[a] = v;
         }
-    } else if (bc == HSMA_BC_METALLIC) {
+    } else if (bc == HSMA_BC_METALLIC || bc == HSMA_BC_DIELECTRIC) {
         for (int a = 0; a < 3; ++a) {
             c[a] -= h;
             if (!(fabs(c[a]) < h)) bad |= 2;

@@ -118,11 +118,16 @@ struct SymItem {
     bool ok;
 };
 
-template <bool DIAG>
-__device__ __forceinline__ SymItem sym_item(const SymGeom& g, int round) {
-    SymItem it;
+// Work-group index in XCD order: the launch's grid is a multiple of 8 and
+// consecutive indices land on one XCD.
+__device__ __forceinline__ int xcd_order_id() {
     const int per_xcd = gridDim.x >> 3;
-    const int id = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    return (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+}
+
+template <bool DIAG>
+__device__ __forceinline__ SymItem sym_item_of(const SymGeom& g, int round, int id) {
+    SymItem it;
     const int per_pair = g.s * g.C;
     int pr;
     it.ok = false;
@@ -147,6 +152,11 @@ __device__ __forceinline__ SymItem sym_item(const SymGeom& g, int round) {
     it.part = rem - it.sig * g.C;
     it.ok = true;
     return it;
+}
+
+template <bool DIAG>
+__device__ __forceinline__ SymItem sym_item(const SymGeom& g, int round) {
+    return sym_item_of<DIAG>(g, round, xcd_order_id());
 }
 
 // Near terms of one pair per unit charges: potential p, field f at the row,
@@ -215,12 +225,11 @@ __device__ __forceinline__ void pair_terms(const double4& t, const double4& s, d
 // reloaded about once per 550 instructions): 1-2.5 % faster by measurement.
 // The periodic kernel runs best at its own 76 VGPRs and 6 waves.
 template <int IMG, int T, bool DIAG, int QC>
-__global__ void __launch_bounds__(SW, (IMG != IMG_PERIODIC && T == 1) ? 7 : 1)
-k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, double* __restrict__ acc) {
+__device__ __forceinline__ void sym_f32_body(const Rec32* __restrict__ pts, const SymGeom& g,
+                                             const SymItem& it, double invL,
+                                             double* __restrict__ acc, float* __restrict__ tab) {
     constexpr int NV = 4 * QC;   // reverse values per lane and group
     const int lane = threadIdx.x;
-    const SymItem it = sym_item<DIAG>(g, round);
-    if (!it.ok) return;
     const int I = it.I, J = it.J, sig = it.sig, part = it.part;
     const size_t cs = (size_t)4 * g.n_pad;
     double* __restrict__ fwd = acc + (size_t)part * cs;
@@ -252,8 +261,13 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
 
     const int c0 = min(J * g.B + (int)((long)part * g.B / g.C), g.n);
     const int c1 = min(J * g.B + (int)((long)(part + 1) * g.B / g.C), g.n);
+    // Columns are read with vector loads (every lane the same record, one
+    // cache line per load): the index carries a zero that the compiler cannot
+    // prove uniform, since scalar loads into SGPRs measured 8.6 % slower here
+    // (they share the wait counter of the LDS reduction).
+    int vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
     // reverse values: lane l owns value l / G of each group when l % G == 0
-    __shared__ float tab[RevTable<float, NV>::SIZE];
     constexpr int G = RevTable<float, NV>::G;
     const bool owner = lane % G == 0;
     const int kown = lane / G;
@@ -279,7 +293,7 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
             for (int q = 0; q < QC; ++q) {
                 float rp = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f;
                 if (q < nh) {
-                    const Rec32 rec = pts[jb + q];
+                    const Rec32 rec = pts[jb + q + vzero];
                     const Pt32 sj = load_pt32(rec);
                     const float qj = rec.v[0].w;
 #pragma unroll
@@ -340,16 +354,24 @@ k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, doub
     }
 }
 
+template <int IMG, int T, bool DIAG, int QC>
+__global__ void __launch_bounds__(SW, (IMG != IMG_PERIODIC && T == 1) ? 7 : 1)
+k_sym_f32(const Rec32* __restrict__ pts, SymGeom g, int round, double invL, double* __restrict__ acc) {
+    __shared__ float tab[RevTable<float, 4 * QC>::SIZE];
+    const SymItem it = sym_item<DIAG>(g, round);
+    if (!it.ok) return;
+    sym_f32_body<IMG, T, DIAG, QC>(pts, g, it, invL, acc, tab);
+}
+
 // Double precision: one row per lane, positions in physical units (centred
 // double4 x, y, z, q), plain FMA accumulation as in the double tile kernel;
 // reverse terms are reduced in double.
 template <int IMG, bool DIAG, int QC>
-__global__ void __launch_bounds__(SW)
-k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, double* __restrict__ acc) {
+__device__ __forceinline__ void sym_f64_body(const double4* __restrict__ pts, const SymGeom& g,
+                                             const SymItem& it, double L,
+                                             double* __restrict__ acc, double* __restrict__ tab) {
     constexpr int NV = 4 * QC;   // reverse values per lane and group
     const int lane = threadIdx.x;
-    const SymItem it = sym_item<DIAG>(g, round);
-    if (!it.ok) return;
     const size_t cs = (size_t)4 * g.n_pad;
     double* __restrict__ fwd = acc + (size_t)it.part * cs;
     double* __restrict__ rev = acc + (size_t)(g.C + it.sig) * cs;
@@ -367,7 +389,6 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
 
     const int c0 = min(it.J * g.B + (int)((long)it.part * g.B / g.C), g.n);
     const int c1 = min(it.J * g.B + (int)((long)(it.part + 1) * g.B / g.C), g.n);
-    __shared__ double tab[RevTable<double, NV>::SIZE];
     constexpr int G = RevTable<double, NV>::G;
     const bool owner = lane % G == 0;
     const int kown = lane / G;
@@ -425,6 +446,15 @@ k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, doubl
             }
         }
     }
+}
+
+template <int IMG, bool DIAG, int QC>
+__global__ void __launch_bounds__(SW)
+k_sym_f64(const double4* __restrict__ pts, SymGeom g, int round, double L, double* __restrict__ acc) {
+    __shared__ double tab[RevTable<double, 4 * QC>::SIZE];
+    const SymItem it = sym_item<DIAG>(g, round);
+    if (!it.ok) return;
+    sym_f64_body<IMG, DIAG, QC>(pts, g, it, L, acc, tab);
 }
 
 // Resident one-wave work-groups per CU of the round kernel of an image kind

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libhsma.so")
 BC_PERIODIC = 0
 BC_METALLIC = 1
 BC_SLAB = 2
+BC_DIELECTRIC = 3
 FP64 = 0
 FP32_COMP = 1
 NEAR_BLOCK = 0
@@ -39,7 +40,8 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double), ("bc", ctypes.c_int), ("p", ctypes.c_int),
                 ("M", ctypes.c_int), ("K", ctypes.c_int), ("R", ctypes.c_double),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("near_mode", ctypes.c_int),
-                ("dipole_mode", ctypes.c_int), ("dr", ctypes.c_double), ("far_mode", ctypes.c_int)]
+                ("dipole_mode", ctypes.c_int), ("dr", ctypes.c_double), ("far_mode", ctypes.c_int),
+                ("gamma", ctypes.c_double), ("far_shells", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                 ("precision", ctypes.c_int), ("bc", ctypes.c_int),
                 ("bytes_resident", ctypes.c_size_t), ("near_mode", ctypes.c_int),
                 ("max_images_per_source", ctypes.c_int), ("dipole_mode", ctypes.c_int),
-                ("dr", ctypes.c_double), ("far_mode", ctypes.c_int)]
+                ("dr", ctypes.c_double), ("far_mode", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("far_shells", ctypes.c_int)]
 
 
 class Intermediates(ctypes.Structure):
@@ -160,11 +163,12 @@ class Plan:
     """An HSMA plan (preparation step) resident on the current GPU."""
 
     def __init__(self, L, bc, p, M, K, R, precision=FP64, seed=DEFAULT_SEED, near_mode=NEAR_BLOCK,
-                 dipole_mode=DIPOLE_EXACT, dr=0.0, far_mode=FAR_SURFACE):
+                 dipole_mode=DIPOLE_EXACT, dr=0.0, far_mode=FAR_SURFACE, gamma=0.0, far_shells=0):
         lib = load()
         d = PlanDesc(L=float(L), bc=int(bc), p=int(p), M=int(M), K=int(K), R=float(R),
                      precision=int(precision), seed=int(seed), near_mode=int(near_mode),
-                     dipole_mode=int(dipole_mode), dr=float(dr), far_mode=int(far_mode))
+                     dipole_mode=int(dipole_mode), dr=float(dr), far_mode=int(far_mode),
+                     gamma=float(gamma), far_shells=int(far_shells))
         h = ctypes.c_void_p()
         _check(lib.hsma_plan_create_ex(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

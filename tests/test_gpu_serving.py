@@ -293,3 +293,47 @@ def test_serving_stream_at_its_stated_parameters(hs):
                            xs[int(i)], qs[int(i)])
         assert rel_err(e64[int(i)], ref["energy"]) <= 1e-10
         assert rel_err(e32[int(i)], ref["energy"]) <= GATE
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pair_once_side_streams_match_single_requests(hs, precision):
+    """Requests of 1024 particles and more run their pair-once near sums on
+    the server's side streams, several at the same time (periodic,
+    grounded-cube and slab requests with different round counts).  Each
+    result equals the single-request path to rounding (1e-12 of
+    1/2 sum |q phi|: same schedule and arithmetic), and is bitwise the same
+    alone and in the mix."""
+    announce("server pair-once side streams precision=%d" % precision)
+    plans = {bc: hs.Plan(1.0, bc, 8, 640, 640, 2.7, precision=precision) for bc in (0, 1, 2)}
+    sizes = [(0, 1030), (1, 2050), (2, 3000), (0, 4100), (1, 5000), (2, 6100), (0, 12000), (1, 1500),
+             (2, 2500)]
+    reqs = []
+    for i, (bc, n) in enumerate(sizes):
+        x, q = W.slab_charges(n, 1.0, 60 + i) if bc == 2 else W.uniform_neutral(n, 1.0, 60 + i)
+        reqs.append((bc, x, q))
+    rounds = {plans[bc].near_schedule(len(q))["blocks"] for bc, _, q in reqs}
+    assert all(plans[bc].near_schedule(len(q))["kind"] == 1 for bc, _, q in reqs)
+    assert len(rounds) >= 3
+    srv = hs.Server(memory_bytes=4 << 30, max_active=16, precision=precision, refine_below=0.0)
+    ids = [srv.submit(plans[bc], x, q) for bc, x, q in reqs]
+    mixed = []
+    for rid, (bc, x, q) in zip(ids, reqs):
+        srv.wait(rid)
+        done, e, phi, F, _ = srv.result(rid, len(q))
+        assert done
+        mixed.append((e, phi, F))
+    for (bc, x, q), (e, phi, F) in zip(reqs, mixed):
+        e1, phi1, F1 = plans[bc].energy_forces(torch.tensor(x, device="cuda"),
+                                               torch.tensor(q, device="cuda"))
+        phi1 = phi1.cpu().numpy()
+        scale = 0.5 * float(np.sum(np.abs(q * phi1)))
+        assert abs(e - e1) <= 1e-12 * scale
+        assert rel_max(phi, phi1, np.abs(phi1).max()) <= 1e-12
+        assert rel_max(F, F1.cpu().numpy()) <= 1e-11
+    for i in (2, 6):
+        bc, x, q = reqs[i]
+        rid = srv.submit(plans[bc], x, q)
+        srv.wait(rid)
+        done, e, phi, F, _ = srv.result(rid, len(q))
+        assert e == mixed[i][0] and np.array_equal(phi, mixed[i][1]) and np.array_equal(F, mixed[i][2])
+    srv.close()
