@@ -58,8 +58,10 @@ def parse():
                     help="serving: recompute in double precision the requests whose FP32 energy "
                          "is below this fraction of 1/2 sum |q phi| (0: never)")
     ap.add_argument("--grad", action="store_true", help="time energy + exact gradient (adjoint)")
-    ap.add_argument("--near", default="block", choices=["block", "sphere"],
-                    help="near set: 27-image block or every image inside the auxiliary sphere")
+    ap.add_argument("--near", default="block", choices=["block", "sphere", "tree"],
+                    help="near set: 27-image block (direct), every image inside the auxiliary "
+                         "sphere, or the block summed by the tree code (FP64)")
+    ap.add_argument("--tree-order", type=int, default=0, help="multipole order of --near tree")
     ap.add_argument("--dipole", default="exact", choices=["exact", "layers"],
                     help="surface dipoles exact, or the paper's two charge layers (dr = 1e-5 R_s)")
     ap.add_argument("--far", default="surface", choices=["surface", "direct"],
@@ -246,8 +248,10 @@ def serving_measure(n_requests, refine, log=sys.stderr):
     """Serving stream (seeded trace): N log-uniform in [1e3, 1e5] (even),
     periodic or grounded cube with probability 1/2, p in {12, 16, 20},
     K = M = 10 p^2, R = 2.7L.  Closed loop (all requests at t = 0) gives
-    solves/s of four paths: the batched server and one solve per request, each
-    in FP32-comp and in FP64 (equal-precision comparisons).  Open loop
+    solves/s of five paths: the served path (batched FP32-comp with
+    ill-conditioned energies refined in FP64), and the batched server and one
+    solve per request, each in FP32-comp and in FP64 without refinement
+    (equal-precision comparisons).  Open loop
     (Poisson arrivals at 0.8 of a path's closed-loop rate) gives p50/p99
     latency.  Energies of the FP32 paths are compared with the FP64
     per-request path."""
@@ -274,47 +278,52 @@ def serving_measure(n_requests, refine, log=sys.stderr):
     for r in trace:
         nchk = (2 if r["bc"] == 0 else 1) * 10 * r["p"] ** 2
         pairs += 27.0 * r["n"] * r["n"] + 27.0 * nchk * r["n"]
-    srv = {hsma.FP32_COMP: hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
-                                       refine_below=refine),
+    # the served path (single precision, ill-conditioned energies refined in
+    # double precision), and the batched paths at one precision each
+    srv = {"served": hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
+                                 refine_below=refine),
+           hsma.FP32_COMP: hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
+                                       refine_below=0.0),
            hsma.FP64: hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP64)}
     zero = np.zeros(n)
     k = min(8, n)
-    for prec in (hsma.FP32_COMP, hsma.FP64):   # warm-up of every path
-        srv[prec].run_trace(zero[:k], pl[prec][:k], xs[:k], qs[:k])
+    for key, prec in (("served", hsma.FP32_COMP), (hsma.FP32_COMP, hsma.FP32_COMP), (hsma.FP64, hsma.FP64)):
+        srv[key].run_trace(zero[:k], pl[prec][:k], xs[:k], qs[:k])   # warm-up of every path
         hsma.run_trace_sequential(zero[:k], pl[prec][:k], xs[:k], qs[:k])
     closed = {}
     energies = {}
-    refined0 = srv[hsma.FP32_COMP].stats()["refined"]
-    for name, prec, batched in (("batched_fp32", hsma.FP32_COMP, True),
-                                ("sequential_fp64", hsma.FP64, False),
-                                ("sequential_fp32", hsma.FP32_COMP, False),
-                                ("batched_fp64", hsma.FP64, True)):
+    refined0 = srv["served"].stats()["refined"]
+    for name, prec, key in (("served_fp32_refined", hsma.FP32_COMP, "served"),
+                            ("sequential_fp64", hsma.FP64, None),
+                            ("batched_fp32", hsma.FP32_COMP, hsma.FP32_COMP),
+                            ("sequential_fp32", hsma.FP32_COMP, None),
+                            ("batched_fp64", hsma.FP64, hsma.FP64)):
         print("serving: closed loop, %s" % name, file=log, flush=True)
-        if batched:
-            e, _, wall = srv[prec].run_trace(zero, pl[prec], xs, qs)
+        if key is not None:
+            e, _, wall = srv[key].run_trace(zero, pl[prec], xs, qs)
         else:
             e, _, wall = hsma.run_trace_sequential(zero, pl[prec], xs, qs)
         closed[name] = n / wall
         energies[name] = e
-        if name == "batched_fp32":
-            refined = srv[hsma.FP32_COMP].stats()["refined"] - refined0
-    mu32, mu64 = closed["batched_fp32"], closed["sequential_fp64"]
+        if name == "served_fp32_refined":
+            refined = srv["served"].stats()["refined"] - refined0
+    mu32, mu64 = closed["served_fp32_refined"], closed["sequential_fp64"]
     gaps = np.random.default_rng(44).exponential(1.0, n)
     pct = lambda a, q_: float(np.percentile(a, q_)) * 1e3
     lat = {}
-    for name, rate_of, prec, batched in (("batched_fp32_at_0.8_own", mu32, hsma.FP32_COMP, True),
-                                         ("sequential_fp64_at_0.8_own", mu64, hsma.FP64, False),
-                                         ("batched_fp32_at_0.8_fp64_sequential", mu64, hsma.FP32_COMP, True)):
+    for name, rate_of, prec, key in (("served_fp32_at_0.8_own", mu32, hsma.FP32_COMP, "served"),
+                                     ("sequential_fp64_at_0.8_own", mu64, hsma.FP64, None),
+                                     ("served_fp32_at_0.8_fp64_sequential", mu64, hsma.FP32_COMP, "served")):
         print("serving: open loop, %s" % name, file=log, flush=True)
         arr = np.cumsum(gaps) / (0.8 * rate_of)
-        if batched:
-            _, l_, _ = srv[prec].run_trace(arr, pl[prec], xs, qs)
+        if key is not None:
+            _, l_, _ = srv[key].run_trace(arr, pl[prec], xs, qs)
         else:
             _, l_, _ = hsma.run_trace_sequential(arr, pl[prec], xs, qs)
         lat[name] = {"p50_ms": pct(l_, 50), "p99_ms": pct(l_, 99), "offered_per_s": 0.8 * rate_of}
     e64 = energies["sequential_fp64"]
     err = {}
-    for name in ("batched_fp32", "sequential_fp32", "batched_fp64"):
+    for name in ("served_fp32_refined", "batched_fp32", "sequential_fp32", "batched_fp64"):
         rel = np.abs(energies[name] - e64) / np.abs(e64)
         err[name] = {"p50": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
                      "max": float(rel.max()), "frac_le_1e-5": float(np.mean(rel <= 1e-5))}
@@ -324,9 +333,13 @@ def serving_measure(n_requests, refine, log=sys.stderr):
                 "K=M=10p^2, R=2.7L; seeded Poisson trace (seed 4)",
         "pair_interactions": pairs,
         "solves_per_s": closed,
+        # equal precision: the batched server against one solve per request,
+        # neither refining
         "gain_batched_vs_sequential": {"fp32": closed["batched_fp32"] / closed["sequential_fp32"],
                                        "fp64": closed["batched_fp64"] / closed["sequential_fp64"]},
-        "gain_batched_fp32_vs_sequential_fp64": mu32 / mu64,
+        # the served single-precision path (every energy within 1e-5) against
+        # the plain double-precision path
+        "gain_served_fp32_vs_sequential_fp64": mu32 / mu64,
         "latency": lat,
         "refine_below": refine,
         "refined_in_fp64": {"requests": int(refined), "fraction": refined / n},
@@ -337,7 +350,7 @@ def serving_measure(n_requests, refine, log=sys.stderr):
 def serving(args):
     """--workload serving: the serving measurement as its own JSON line."""
     sv = serving_measure(args.requests, args.refine)
-    mu = sv["solves_per_s"]["batched_fp32"]
+    mu = sv["solves_per_s"]["served_fp32_refined"]
     rec = {
         "metric": "solves/s", "value": mu, "unit": "solves/s", "n_gpus": 1,
         "steps": sv["requests"], "warmup": 8, "ms_per_step": 1e3 / mu, "higher_is_better": True,
@@ -411,11 +424,14 @@ def main():
     torch.cuda.set_device(dev)
     if args.grad:
         return adjoint_bench(args, cfg, x, q, prec)
-    near_mode = hsma.NEAR_SPHERE if args.near == "sphere" else hsma.NEAR_BLOCK
+    near_mode = {"sphere": hsma.NEAR_SPHERE, "tree": hsma.NEAR_TREE}.get(args.near, hsma.NEAR_BLOCK)
+    if near_mode == hsma.NEAR_TREE:
+        prec = hsma.FP64
     plan = hsma.Plan(cfg["L"], cfg["bc"], cfg["p"], cfg["M"], cfg["K"], cfg["R"], precision=prec,
                      near_mode=near_mode,
                      dipole_mode=hsma.DIPOLE_LAYERS if args.dipole == "layers" else hsma.DIPOLE_EXACT,
-                     far_mode=hsma.FAR_DIRECT if args.far == "direct" else hsma.FAR_SURFACE)
+                     far_mode=hsma.FAR_DIRECT if args.far == "direct" else hsma.FAR_SURFACE,
+                     tree_order=args.tree_order)
     info = plan.info
     xd = torch.tensor(x, dtype=torch.float64, device=dev)
     qd = torch.tensor(q, dtype=torch.float64, device=dev)
@@ -469,9 +485,12 @@ def main():
     near_avg_s = near_ms / max(near_launches, 1) / 1e3
     sched = plan.near_schedule(n)
     kind = "pair-once" if sched["kind"] == 1 else "tiles"
+    if near_mode == hsma.NEAR_TREE:
+        kind = "tree"
     ptag = "f32" if prec == hsma.FP32_COMP else "f64"
     peak = FP32_PEAK_TFLOPS if prec == hsma.FP32_COMP else FP64_PEAK_TFLOPS
-    if near_mode == hsma.NEAR_SPHERE:
+    if near_mode in (hsma.NEAR_SPHERE, hsma.NEAR_TREE):
+        # tree: the pair interactions of the direct sum it replaces
         evaluated = near_pairs
     else:
         evaluated = near_evaluated_pairs(n, cfg, sched)

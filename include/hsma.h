@@ -63,9 +63,16 @@ typedef enum {
 
 typedef enum {
     HSMA_NEAR_BLOCK = 0,   /* near set: the 27 images of every source in the 3x3x3 block of boxes */
-    HSMA_NEAR_SPHERE = 1   /* near set: every image inside the auxiliary sphere |r| < R_s (the
+    HSMA_NEAR_SPHERE = 1,  /* near set: every image inside the auxiliary sphere |r| < R_s (the
                               paper's literal near set, Sec. II.A); images generated per call;
                               no adjoint and no serving in this mode */
+    HSMA_NEAR_TREE = 2     /* near set of HSMA_NEAR_BLOCK, summed by a tree code instead of
+                              directly (the O(N log N) acceleration of the near sum, Sec. II.C):
+                              multipoles of order hsma_plan_desc.tree_order about the cells of a
+                              uniform octree over the 27 boxes, direct sums between neighbouring
+                              leaf cells; about 1e-6 of the rms potential at order 14; double
+                              precision; periodic, grounded cube and slab; no adjoint and no
+                              serving in this mode */
 } hsma_near_mode;
 
 typedef enum {
@@ -119,6 +126,7 @@ typedef struct {
     int far_shells;    /* HSMA_BC_DIELECTRIC: far image shells S, images with
                           2 <= max_a |k_a| <= S; 0 picks the smallest S whose omitted tail is
                           below 1e-13 sum|q|/L at the monitoring points */
+    int tree_order;    /* HSMA_NEAR_TREE: multipole order, 1..20 (0 selects 14) */
 } hsma_plan_desc;
 
 typedef struct {
@@ -140,6 +148,7 @@ typedef struct {
     int far_mode;
     double gamma;      /* dielectric box: image weight */
     int far_shells;    /* dielectric box: far image shells in use */
+    int tree_order;    /* tree near sum: multipole order in use */
 } hsma_plan_info_t;
 
 /* Optional device outputs of the intermediate stages (any pointer may be NULL). */
@@ -158,7 +167,8 @@ typedef struct {
    is the version of this interface; it changes whenever a declaration or a
    struct layout in this header changes (2: the near-schedule query and the
    server's double-precision refinement; 3: HSMA_E_COINCIDENT; 4:
-   HSMA_E_NONFINITE; 5: the dielectric box). */
+   HSMA_E_NONFINITE; 5: the dielectric box; 6: the tree-code near sum and
+   hsma_energy_forces_device_typed). */
 const char* hsma_status_string(int status);
 const char* hsma_last_error(void);
 int hsma_version(void);
@@ -258,6 +268,24 @@ hsma_status hsma_energy_forces_device(hsma_plan plan, const double* x, const dou
                                       void* stream, void* workspace, size_t workspace_bytes,
                                       double* energy, double* phi, double* forces,
                                       const hsma_intermediates* dbg);
+
+/*
+ * The update step of hsma_energy_forces_device on device arrays of either
+ * precision (the interface's dtype argument): dtype HSMA_DTYPE_F64 (double)
+ * or HSMA_DTYPE_F32 (float) is the element type of x (N x 3 row-major), q
+ * (N), phi (N or NULL) and forces (N x 3 or NULL).  Single-precision inputs
+ * are widened to double on the device before anything else (the arithmetic
+ * is then the plan's, Sec. II.C); phi and forces are rounded to single
+ * precision on output, the energy is a host double.  Workspace, stream,
+ * ownership and errors as in hsma_energy_forces_device (HSMA_E_INVALID for
+ * any other dtype).
+ */
+#define HSMA_DTYPE_F64 0
+#define HSMA_DTYPE_F32 1
+hsma_status hsma_energy_forces_device_typed(hsma_plan plan, const void* x, const void* q, int64_t N,
+                                            int dtype, void* stream, void* workspace,
+                                            size_t workspace_bytes, double* energy, void* phi,
+                                            void* forces);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

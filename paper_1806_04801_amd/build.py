@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libhsma.so")
 SOURCES = ["pairs.hip", "sym.hip", "plan.hip", "solve.hip", "adjoint.hip", "api.hip", "serve.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "tree.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

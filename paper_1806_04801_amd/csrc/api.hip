@@ -82,7 +82,7 @@ const char* hsma_status_string(int st) {
 
 const char* hsma_last_error(void) { return g_last_error.c_str(); }
 
-int hsma_version(void) { return 5; }
+int hsma_version(void) { return 6; }
 
 hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     if (d == nullptr || out == nullptr) return fail(HSMA_E_INVALID, "NULL argument");
@@ -109,8 +109,17 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     const int nu = (d->bc == HSMA_BC_METALLIC || diel) ? nb : nb - 1;
     if (d->K < nu || d->K > (1 << 24)) return fail(HSMA_E_INVALID, "K must be >= number of unknowns");
     if (d->M < 4 || d->M > (1 << 22)) return fail(HSMA_E_INVALID, "M out of range");
-    if (d->near_mode != HSMA_NEAR_BLOCK && d->near_mode != HSMA_NEAR_SPHERE)
+    if (d->near_mode != HSMA_NEAR_BLOCK && d->near_mode != HSMA_NEAR_SPHERE &&
+        d->near_mode != HSMA_NEAR_TREE)
         return fail(HSMA_E_INVALID, "unknown near mode");
+    if (d->near_mode == HSMA_NEAR_TREE) {
+        if (d->precision != HSMA_FP64)
+            return fail(HSMA_E_INVALID, "the tree near sum runs in double precision only");
+        if (d->bc == HSMA_BC_DIELECTRIC)
+            return fail(HSMA_E_INVALID, "the tree near sum serves the periodic, grounded and slab boxes");
+        if (d->tree_order < 0 || d->tree_order > 20)
+            return fail(HSMA_E_INVALID, "tree_order must be in [0, 20]");
+    }
     if (d->far_mode != HSMA_FAR_SURFACE && d->far_mode != HSMA_FAR_DIRECT)
         return fail(HSMA_E_INVALID, "unknown far-field mode");
     if (d->dipole_mode != HSMA_DIPOLE_EXACT && d->dipole_mode != HSMA_DIPOLE_LAYERS)
@@ -140,6 +149,7 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     pl->dipole_mode = d->dipole_mode;
     pl->far_mode = d->far_mode;
     pl->dr = d->dr > 0.0 ? d->dr : 1e-5 * d->R;
+    pl->tree_order = d->near_mode == HSMA_NEAR_TREE ? (d->tree_order > 0 ? d->tree_order : 14) : 0;
     if (pl->near_mode == HSMA_NEAR_SPHERE) {
         // candidates |k_a| <= kr; a source has at most as many images inside the
         // sphere as there are shifted boxes that reach it
@@ -214,6 +224,7 @@ hsma_status hsma_plan_info(hsma_plan pl, hsma_plan_info_t* info) {
     info->far_mode = pl->far_mode;
     info->gamma = pl->gamma;
     info->far_shells = pl->far_shells;
+    info->tree_order = pl->tree_order;
     return HSMA_OK;
 }
 
@@ -282,7 +293,26 @@ hsma_status hsma_energy_forces_device(hsma_plan pl, const double* x, const doubl
     if (workspace_bytes < ly.total) return fail(HSMA_E_NOMEM, "workspace too small");
     HSMA_HIP(hipSetDevice(pl->device));
     hipStream_t s = (hipStream_t)stream;
-    st = forward(pl, ly, x, q, (char*)workspace, s, phi, forces, dbg);
+    st = forward(pl, ly, x, q, HSMA_DTYPE_F64, (char*)workspace, s, phi, forces, dbg);
+    if (st != HSMA_OK) return st;
+    return read_result(ly, (char*)workspace, s, energy);
+}
+
+hsma_status hsma_energy_forces_device_typed(hsma_plan pl, const void* x, const void* q, int64_t N,
+                                            int dtype, void* stream, void* workspace,
+                                            size_t workspace_bytes, double* energy, void* phi,
+                                            void* forces) {
+    hsma_status st = check_sizes(pl, N);
+    if (st != HSMA_OK) return st;
+    if (x == nullptr || q == nullptr || workspace == nullptr || energy == nullptr)
+        return fail(HSMA_E_INVALID, "NULL argument");
+    if (dtype != HSMA_DTYPE_F64 && dtype != HSMA_DTYPE_F32)
+        return fail(HSMA_E_INVALID, "dtype must be HSMA_DTYPE_F64 or HSMA_DTYPE_F32");
+    const Layout ly = make_layout(pl, N, false);
+    if (workspace_bytes < ly.total) return fail(HSMA_E_NOMEM, "workspace too small");
+    HSMA_HIP(hipSetDevice(pl->device));
+    hipStream_t s = (hipStream_t)stream;
+    st = forward(pl, ly, x, q, dtype, (char*)workspace, s, phi, forces, nullptr);
     if (st != HSMA_OK) return st;
     return read_result(ly, (char*)workspace, s, energy);
 }
@@ -299,13 +329,16 @@ hsma_status hsma_energy_grad_device(hsma_plan pl, const double* x, const double*
         return fail(HSMA_E_INVALID, "the adjoint needs the block near set (the sphere set moves "
                                     "images in and out as charges move)");
     if (pl->bc == HSMA_BC_DIELECTRIC) return fail(HSMA_E_INVALID, "no adjoint for the dielectric box");
+    if (pl->near_mode == HSMA_NEAR_TREE)
+        return fail(HSMA_E_INVALID, "no adjoint for the tree near sum (an approximation whose "
+                                    "gradient is not that of the computed energy)");
     if (pl->dipole_mode != HSMA_DIPOLE_EXACT || pl->far_mode != HSMA_FAR_SURFACE)
         return fail(HSMA_E_INVALID, "the adjoint needs the surface mapping with exact dipoles");
     const Layout ly = make_layout(pl, N, true);
     if (workspace_bytes < ly.total) return fail(HSMA_E_NOMEM, "workspace too small");
     HSMA_HIP(hipSetDevice(pl->device));
     hipStream_t s = (hipStream_t)stream;
-    st = forward(pl, ly, x, q, (char*)workspace, s, nullptr, nullptr, nullptr);
+    st = forward(pl, ly, x, q, HSMA_DTYPE_F64, (char*)workspace, s, nullptr, nullptr, nullptr);
     if (st != HSMA_OK) return st;
     st = backward(pl, ly, (char*)workspace, s, dEdx, dEdq);
     if (st != HSMA_OK) return st;
@@ -350,7 +383,7 @@ hsma_status hsma_energy_forces(hsma_plan pl, const double* x, const double* q, i
     if (hipMemcpy(base + off_x, x, nx, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + off_q, q, nq, hipMemcpyHostToDevice) != hipSuccess)
         return done(fail(HSMA_E_DEVICE, "host to device copy failed"));
-    st = forward(pl, ly, (double*)(base + off_x), (double*)(base + off_q), base + off_ws, s,
+    st = forward(pl, ly, base + off_x, base + off_q, HSMA_DTYPE_F64, base + off_ws, s,
                  (double*)(base + off_phi), (double*)(base + off_f), nullptr);
     if (st != HSMA_OK) return done(st);
     st = read_result(ly, base + off_ws, s, energy);

@@ -153,6 +153,7 @@ struct hsma_plan_s {
     int far_mode = 0;     // HSMA_FAR_SURFACE or HSMA_FAR_DIRECT
     double gamma = 0.0;   // dielectric box: image weight
     int far_shells = 0;   // dielectric box: far image shells
+    int tree_order = 0;   // tree near sum: multipole order
     // host geometry (centred)
     std::vector<double> chk;    // nchk x 3: monitoring points then twins
     std::vector<double> spts;   // M x 3

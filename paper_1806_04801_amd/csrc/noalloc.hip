@@ -57,7 +57,7 @@ extern "C" hsma_status hsma_energy_forces_noalloc(hsma_plan pl, const double* x,
     st = scratch_on(pl->device, &ws);
     if (st != HSMA_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    st = forward(pl, ly, x, q, ws, s, phi, forces, nullptr);
+    st = forward(pl, ly, x, q, HSMA_DTYPE_F64, ws, s, phi, forces, nullptr);
     if (st != HSMA_OK) return st;
     return read_result(ly, ws, s, energy);
 }

@@ -207,6 +207,8 @@ struct hsma_server_s {
     hipStream_t side[NSIDE] = {};
     hipEvent_t side_ev[NSIDE] = {};
     hipEvent_t fork_ev = nullptr;
+    // double-precision refinements run on a stream of their own, beside the ticks
+    hipStream_t rstream = nullptr;
     hsma_server_stats_t stats{};
 };
 
@@ -443,7 +445,7 @@ static void retire(hsma_server_s* sv) {
 // arena, in queue order; false when the head must wait for memory.
 static hsma_status start_refinements(hsma_server_s* sv, bool* blocked) {
     *blocked = false;
-    hipStream_t s = sv->stream;
+    hipStream_t s = sv->rstream;
     while (!sv->refine.empty()) {
         SrvReq* r = sv->refine.front();
         Layout ly64;
@@ -461,7 +463,8 @@ static hsma_status start_refinements(hsma_server_s* sv, bool* blocked) {
         const double* hq = r->ext_q ? r->ext_q : r->hq.data();
         HSMA_HIP(hipMemcpyAsync(blk.x, hx, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
         HSMA_HIP(hipMemcpyAsync(blk.q, hq, sizeof(double) * N, hipMemcpyHostToDevice, s));
-        hsma_status st = forward(r->plan, ly64, blk.x, blk.q, blk.ws, s, blk.phi, blk.F, nullptr);
+        hsma_status st = forward(r->plan, ly64, blk.x, blk.q, HSMA_DTYPE_F64, blk.ws, s, blk.phi, blk.F,
+                                 nullptr);
         if (st != HSMA_OK) return st;
         HSMA_HIP(hipMemcpyAsync(r->h_out, blk.ws + ly64.off_result, sizeof(Result),
                                 hipMemcpyDeviceToHost, s));
@@ -528,7 +531,7 @@ static hsma_status tick(hsma_server_s* sv) {
             // the refinements are this tick's work: track them like a tick
             hipEvent_t te = srv_event(sv);
             if (te == nullptr) return fail(HSMA_E_DEVICE, "event creation failed");
-            HSMA_HIP(hipEventRecord(te, sv->stream));
+            HSMA_HIP(hipEventRecord(te, sv->rstream));
             sv->inflight.push_back(te);
             sv->stats.ticks += 1;
         }
@@ -708,6 +711,7 @@ hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out) {
             if (sv->side_ev[w]) hipEventDestroy(sv->side_ev[w]);
         }
         if (sv->fork_ev) hipEventDestroy(sv->fork_ev);
+        if (sv->rstream) hipStreamDestroy(sv->rstream);
         delete sv;
         return fail(st, m);
     };
@@ -745,6 +749,8 @@ hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out) {
         if (hipStreamCreateWithFlags(&sv->side[w], hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sv->side_ev[w], hipEventDisableTiming) != hipSuccess)
             return bail(HSMA_E_DEVICE, "side stream creation failed");
+    if (hipStreamCreateWithFlags(&sv->rstream, hipStreamNonBlocking) != hipSuccess)
+        return bail(HSMA_E_DEVICE, "refinement stream creation failed");
     *out = sv;
     return HSMA_OK;
 }
@@ -753,6 +759,7 @@ void hsma_server_destroy(hsma_server sv) {
     if (sv == nullptr) return;
     hipSetDevice(sv->device);
     hipStreamSynchronize(sv->stream);
+    hipStreamSynchronize(sv->rstream);
     for (auto& kv : sv->all) {
         if (kv.second->ev) hipEventDestroy(kv.second->ev);
         delete kv.second;
@@ -770,6 +777,7 @@ void hsma_server_destroy(hsma_server sv) {
         hipEventDestroy(sv->side_ev[w]);
     }
     hipEventDestroy(sv->fork_ev);
+    hipStreamDestroy(sv->rstream);
     hipFree(sv->arena_base);
     hipHostFree(sv->host_base);
     hipStreamDestroy(sv->stream);
@@ -782,7 +790,8 @@ static hsma_status submit_impl(hsma_server sv, hsma_plan plan, const double* x, 
         return fail(HSMA_E_INVALID, "NULL argument");
     if (N < 1 || N > ((int64_t)1 << 26)) return fail(HSMA_E_INVALID, "N out of range");
     if (plan->near_mode != HSMA_NEAR_BLOCK || plan->dipole_mode != HSMA_DIPOLE_EXACT ||
-        plan->far_mode != HSMA_FAR_SURFACE || plan->bc == HSMA_BC_DIELECTRIC)
+        plan->far_mode != HSMA_FAR_SURFACE || plan->bc == HSMA_BC_DIELECTRIC ||
+        plan->near_mode != HSMA_NEAR_BLOCK)
         return fail(HSMA_E_INVALID, "the server runs block near-set, exact-dipole plans of the "
                                     "periodic, grounded-cube and slab boxes only");
     Layout ly;

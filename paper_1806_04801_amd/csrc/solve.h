@@ -2,6 +2,7 @@
 #pragma once
 
 #include "hsma_internal.h"
+#include "tree.h"
 
 namespace hsma {
 
@@ -39,6 +40,10 @@ struct Layout {
     // every stage on the caller's stream (no auxiliary stream or events are
     // created): the allocation-free entry point
     bool single_stream = false;
+    // tree-code near sum (HSMA_NEAR_TREE): its own workspace at off_tree
+    bool tree = false;
+    TreeLayout tl;
+    size_t off_tree = 0;
 };
 
 // What the finalize stages add to the near potential of particle i:
@@ -55,8 +60,9 @@ NearFix near_fix(const hsma_plan_s* pl, bool f32);
 
 Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_override = 0,
                    int precision_override = -1);
-hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, const double* q,
-                    char* ws, hipStream_t s, double* phi, double* forces,
+// dtype (HSMA_DTYPE_F64 or HSMA_DTYPE_F32) is the type of x, q, phi and forces.
+hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, const void* q,
+                    int dtype, char* ws, hipStream_t s, void* phi, void* forces,
                     const hsma_intermediates* dbg);
 hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStream_t s,
                      double* dEdx, double* dEdq);

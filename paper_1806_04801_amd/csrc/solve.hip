@@ -40,6 +40,7 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     const bool f32 = prec == HSMA_FP32_COMP;
     ly.f32 = f32;
     const bool sphere = pl->near_mode == HSMA_NEAR_SPHERE;
+    const bool tree = pl->near_mode == HSMA_NEAR_TREE;
     // targets per lane of the near tiles: the image-block kernels run best
     // with one, the explicit-image tiles with two (measured); an override other
     // than 1 or 2 is ignored
@@ -68,7 +69,7 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     {
         const int mode = env_int("HSMA_SYM", -1);
         const int nmin = env_int("HSMA_SYM_MIN", 1024);
-        const bool eligible = !sphere && !diel && ly.N > 0;
+        const bool eligible = !sphere && !diel && !tree && ly.N > 0;
         ly.sym = eligible && (mode == 1 || (mode < 0 && ly.N >= nmin));
         ly.sym_img = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? IMG_SLAB : pl->img;
         if (ly.sym) ly.g_sym = sym_geometry(ly.N, env_int("HSMA_SYM_T", 1), !f32, ly.sym_img, pl->ncu);
@@ -83,6 +84,12 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.off_b = take(sizeof(double) * (size_t)pl->K);
     ly.off_A = take(sizeof(double) * (size_t)pl->nb);
     ly.off_surf = take(sizeof(double) * 12 * (size_t)pl->M);   // 8 per point, or 3 charges
+    if (tree) {
+        // the tree writes one copy of phi and E: one chunk of the tile layout
+        ly.tree = true;
+        ly.g_near.S = 1;
+        ly.tl = tree_layout(ly.ns, pl->tree_order);
+    }
     {
         size_t near_doubles = 4 * (size_t)ly.g_near.S * ly.g_near.nt_pad;
         if (ly.sym)
@@ -103,6 +110,7 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
         ly.off_img64 = take(sizeof(double4) * (size_t)ly.img_max);
         ly.off_img32 = f32 ? take(sizeof(Rec32) * (size_t)ly.img_max) : 0;
     }
+    if (tree) ly.off_tree = take(ly.tl.total);
     if (grad) {
         ly.g_u = pair_geometry(pl->M, ly.N, 1, pl->ncu);
         ly.g_G = pair_geometry(ly.ns, pl->nchk, tpl_near, pl->ncu);
@@ -118,7 +126,8 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
 }
 
 // ---------------------------------------------------------------- kernels
-__global__ void k_prep(const double* __restrict__ x, const double* __restrict__ q, int N, int bc,
+template <typename TI>
+__global__ void k_prep(const TI* __restrict__ x, const TI* __restrict__ q, int N, int bc,
                        double L, double4* __restrict__ src, int* __restrict__ status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) prep_body(i, x, q, N, bc, L, src, status);
@@ -177,10 +186,11 @@ __global__ void __launch_bounds__(WG) k_map_layers(const double* __restrict__ Wq
     if (j < M) map_layers_body(j, threadIdx.x & 63, M, Wq, Wp, nb, A, spos, Rs, dr, chg);
 }
 
+template <typename TO>
 __global__ void __launch_bounds__(WG)
 k_finalize(const double* __restrict__ near, int Sn, int npad, const double* __restrict__ surfp,
            int Ss, int spad, const double4* __restrict__ src, int N, NearFix fix,
-           const double* __restrict__ qnet, double* __restrict__ phi, double* __restrict__ forces,
+           const double* __restrict__ qnet, TO* __restrict__ phi, TO* __restrict__ forces,
            double* __restrict__ dbg_pn, double* __restrict__ dbg_fn, double* __restrict__ dbg_po,
            double* __restrict__ dbg_fo, double* __restrict__ eblk) {
     finalize_body(blockIdx.x, near, Sn, npad, surfp, Ss, spad, src, N, fix, qnet, phi, forces,
@@ -297,9 +307,12 @@ static bool overlap_enabled() {
             return fail(HSMA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));  \
     } while (0)
 
-hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, const double* q,
-                    char* ws, hipStream_t s, double* phi, double* forces,
+hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, const void* q,
+                    int dtype, char* ws, hipStream_t s, void* phi, void* forces,
                     const hsma_intermediates* dbg) {
+    if (dtype != HSMA_DTYPE_F64 && dtype != HSMA_DTYPE_F32)
+        return fail(HSMA_E_INVALID, "dtype must be HSMA_DTYPE_F64 or HSMA_DTYPE_F32");
+    const bool in32 = dtype == HSMA_DTYPE_F32;
     const int N = ly.N;
     const bool f32 = ly.f32;
     double4* src64 = (double4*)(ws + ly.off_src64);
@@ -314,8 +327,12 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     Result* res = (Result*)(ws + ly.off_result);
 
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, s, res);
-    hipLaunchKernelGGL(k_prep, dim3((N + WG - 1) / WG), dim3(WG), 0, s, x, q, N, pl->bc, pl->L,
-                       src64, &res->status);
+    if (in32)
+        hipLaunchKernelGGL(k_prep<float>, dim3((N + WG - 1) / WG), dim3(WG), 0, s, (const float*)x,
+                           (const float*)q, N, pl->bc, pl->L, src64, &res->status);
+    else
+        hipLaunchKernelGGL(k_prep<double>, dim3((N + WG - 1) / WG), dim3(WG), 0, s, (const double*)x,
+                           (const double*)q, N, pl->bc, pl->L, src64, &res->status);
     {
         // two charges at the same position (their interaction is infinite)
         int* dup = (int*)(ws + ly.off_dup);
@@ -411,7 +428,10 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     if (aux != nullptr) CK(hipEventRecord(aux->join, s1));
     // near field at the particles: the sources and their 27 images, self excluded
     timing_begin(0, s);
-    if (sphere)
+    if (ly.tree)
+        CK(launch_tree_near(pl->img, src64, ly.ns, N, pl->L, ly.tl, ws + ly.off_tree, near_part,
+                            g_near.nt_pad, s));
+    else if (sphere)
         CK(launch_explicit(f32, true, true, f32 ? (const void*)src32 : (const void*)src64,
                            f32 ? (const void*)img32 : (const void*)img64, g_near, pl->L, near_part, s));
     else if (ly.sym && f32)
@@ -441,10 +461,18 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const double* x, co
     timing_end(2, s);
     const int near_S = ly.sym ? ly.g_sym.C + ly.g_sym.s : g_near.S;
     const int near_pad = ly.sym ? ly.g_sym.n_pad : g_near.nt_pad;
-    hipLaunchKernelGGL(k_finalize, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, near_S,
-                       near_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, fix, &res->qnet, phi,
-                       forces, dbg ? dbg->phi_near : nullptr, dbg ? dbg->field_near : nullptr,
-                       dbg ? dbg->phi_out : nullptr, dbg ? dbg->field_out : nullptr, eblk);
+    if (in32)
+        hipLaunchKernelGGL(k_finalize<float>, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, near_S,
+                           near_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, fix, &res->qnet,
+                           (float*)phi, (float*)forces, dbg ? dbg->phi_near : nullptr,
+                           dbg ? dbg->field_near : nullptr, dbg ? dbg->phi_out : nullptr,
+                           dbg ? dbg->field_out : nullptr, eblk);
+    else
+        hipLaunchKernelGGL(k_finalize<double>, dim3(ly.n_eblk), dim3(WG), 0, s, near_part, near_S,
+                           near_pad, surf_part, g_surf.S, g_surf.nt_pad, src64, N, fix, &res->qnet,
+                           (double*)phi, (double*)forces, dbg ? dbg->phi_near : nullptr,
+                           dbg ? dbg->field_near : nullptr, dbg ? dbg->phi_out : nullptr,
+                           dbg ? dbg->field_out : nullptr, eblk);
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(WG), 0, s, eblk, ly.n_eblk,
                        needs_neutral(pl->bc) ? 1 : 0, res);
     CK(hipGetLastError());

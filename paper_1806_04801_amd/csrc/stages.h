@@ -14,11 +14,13 @@ constexpr int SWG = 256;
 // Centre (and wrap) particle i; grounded slab: also write its mirror charge
 // -q at z -> -z (mirror reflections plus periodic extension turn the slab into
 // a periodic cube of side L).
-__device__ __forceinline__ void prep_body(int i, const double* __restrict__ x,
-                                          const double* __restrict__ q, int N, int bc, double L,
+// Inputs in double or single precision (TI), widened to double here.
+template <typename TI = double>
+__device__ __forceinline__ void prep_body(int i, const TI* __restrict__ x,
+                                          const TI* __restrict__ q, int N, int bc, double L,
                                           double4* __restrict__ src, int* __restrict__ status) {
-    double c[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
-    const double qi = q[i];
+    double c[3] = {(double)x[3 * i], (double)x[3 * i + 1], (double)x[3 * i + 2]};
+    const double qi = (double)q[i];
     int bad = 0;
     if (!isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2]) || !isfinite(qi)) bad |= 1;
     const double h = 0.5 * L;
@@ -222,13 +224,16 @@ __device__ __forceinline__ void net_charge_body(const double4* __restrict__ src,
 
 // phi = near + surface (chunk sums in fixed order) + q * fix.own + Q * fix.qc
 // (NearFix; Q = *qnet, read only when fix.qc != 0), F = q E, block partial
-// sums of q phi, q and |q| (block blk, all SWG threads participate).
+// sums of q phi, q and |q| (block blk, all SWG threads participate).  phi and
+// F are stored in TO (double, or rounded to single precision); the energy
+// sums use the double values.
+template <typename TO = double>
 __device__ __forceinline__ void finalize_body(int blk, const double* __restrict__ near, int Sn,
                                               int npad, const double* __restrict__ surfp, int Ss,
                                               int spad, const double4* __restrict__ src, int N,
                                               NearFix fix, const double* __restrict__ qnet,
-                                              double* __restrict__ phi,
-                                              double* __restrict__ forces,
+                                              TO* __restrict__ phi,
+                                              TO* __restrict__ forces,
                                               double* __restrict__ dbg_pn, double* __restrict__ dbg_fn,
                                               double* __restrict__ dbg_po, double* __restrict__ dbg_fo,
                                               double* __restrict__ eblk) {
@@ -248,11 +253,11 @@ __device__ __forceinline__ void finalize_body(int blk, const double* __restrict_
         vn[0] += qi * fix.own;
         if (fix.qc != 0.0) vn[0] += *qnet * fix.qc;
         const double p = vn[0] + vo[0];
-        if (phi) phi[i] = p;
+        if (phi) phi[i] = (TO)p;
         if (forces) {
-            forces[3 * i] = qi * (vn[1] + vo[1]);
-            forces[3 * i + 1] = qi * (vn[2] + vo[2]);
-            forces[3 * i + 2] = qi * (vn[3] + vo[3]);
+            forces[3 * i] = (TO)(qi * (vn[1] + vo[1]));
+            forces[3 * i + 1] = (TO)(qi * (vn[2] + vo[2]));
+            forces[3 * i + 2] = (TO)(qi * (vn[3] + vo[3]));
         }
         if (dbg_pn) dbg_pn[i] = vn[0];
         if (dbg_po) dbg_po[i] = vo[0];

@@ -21,10 +21,13 @@ FP64 = 0
 FP32_COMP = 1
 NEAR_BLOCK = 0
 NEAR_SPHERE = 1
+NEAR_TREE = 2
 DIPOLE_EXACT = 0
 DIPOLE_LAYERS = 1
 FAR_SURFACE = 0
 FAR_DIRECT = 1
+DTYPE_F64 = 0     # element type of the arrays of hsma_energy_forces_device_typed
+DTYPE_F32 = 1
 DEFAULT_SEED = 12345
 
 _lib = None
@@ -41,7 +44,7 @@ class PlanDesc(ctypes.Structure):
                 ("M", ctypes.c_int), ("K", ctypes.c_int), ("R", ctypes.c_double),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("near_mode", ctypes.c_int),
                 ("dipole_mode", ctypes.c_int), ("dr", ctypes.c_double), ("far_mode", ctypes.c_int),
-                ("gamma", ctypes.c_double), ("far_shells", ctypes.c_int)]
+                ("gamma", ctypes.c_double), ("far_shells", ctypes.c_int), ("tree_order", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -52,7 +55,7 @@ class PlanInfo(ctypes.Structure):
                 ("bytes_resident", ctypes.c_size_t), ("near_mode", ctypes.c_int),
                 ("max_images_per_source", ctypes.c_int), ("dipole_mode", ctypes.c_int),
                 ("dr", ctypes.c_double), ("far_mode", ctypes.c_int), ("gamma", ctypes.c_double),
-                ("far_shells", ctypes.c_int)]
+                ("far_shells", ctypes.c_int), ("tree_order", ctypes.c_int)]
 
 
 class Intermediates(ctypes.Structure):
@@ -102,6 +105,11 @@ EXPORTS = {
                                                  ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
                                                  ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.POINTER(Intermediates)]),
+    "hsma_energy_forces_device_typed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                       ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                                       ctypes.c_void_p, ctypes.c_size_t,
+                                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                                       ctypes.c_void_p]),
     "hsma_energy_forces_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                   ctypes.c_int64, ctypes.c_void_p,
                                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
@@ -163,12 +171,13 @@ class Plan:
     """An HSMA plan (preparation step) resident on the current GPU."""
 
     def __init__(self, L, bc, p, M, K, R, precision=FP64, seed=DEFAULT_SEED, near_mode=NEAR_BLOCK,
-                 dipole_mode=DIPOLE_EXACT, dr=0.0, far_mode=FAR_SURFACE, gamma=0.0, far_shells=0):
+                 dipole_mode=DIPOLE_EXACT, dr=0.0, far_mode=FAR_SURFACE, gamma=0.0, far_shells=0,
+                 tree_order=0):
         lib = load()
         d = PlanDesc(L=float(L), bc=int(bc), p=int(p), M=int(M), K=int(K), R=float(R),
                      precision=int(precision), seed=int(seed), near_mode=int(near_mode),
                      dipole_mode=int(dipole_mode), dr=float(dr), far_mode=int(far_mode),
-                     gamma=float(gamma), far_shells=int(far_shells))
+                     gamma=float(gamma), far_shells=int(far_shells), tree_order=int(tree_order))
         h = ctypes.c_void_p()
         _check(lib.hsma_plan_create_ex(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -238,14 +247,29 @@ class Plan:
 
     # ------------------------------------------------------------ device path
     def energy_forces(self, x, q, phi=None, forces=None, intermediates=False):
-        """x (N x 3), q (N): float64 CUDA tensors.  Returns (energy, phi, forces)
-        and, if intermediates, a dict of the stage outputs."""
+        """x (N x 3), q (N): CUDA tensors, both float64 or both float32 (phi
+        and forces then come back in the same type).  Returns (energy, phi,
+        forces) and, if intermediates (float64 only), a dict of the stage
+        outputs."""
         import torch
-        assert x.is_cuda and q.is_cuda and x.dtype == torch.float64 and q.dtype == torch.float64
+        assert x.is_cuda and q.is_cuda and x.dtype == q.dtype
+        assert x.dtype in (torch.float64, torch.float32)
         x = x.contiguous()
         q = q.contiguous()
         n = q.numel()
         dev = x.device
+        if x.dtype == torch.float32:
+            assert not intermediates, "intermediates need float64 inputs"
+            if phi is None:
+                phi = torch.empty(n, dtype=torch.float32, device=dev)
+            if forces is None:
+                forces = torch.empty((n, 3), dtype=torch.float32, device=dev)
+            ws = self.workspace(n, dev)
+            e = ctypes.c_double()
+            _check(load().hsma_energy_forces_device_typed(
+                self._h, _ptr(x), _ptr(q), n, DTYPE_F32, _stream_handle(torch, dev), _ptr(ws), ws.numel(),
+                ctypes.byref(e), _ptr(phi), _ptr(forces)))
+            return e.value, phi, forces
         if phi is None:
             phi = torch.empty(n, dtype=torch.float64, device=dev)
         if forces is None:

@@ -39,7 +39,7 @@ def test_status_strings_without_gpu():
     assert lib.hsma_status_string(0) == b"ok"
     assert lib.hsma_status_string(-2) == b"system not neutral"
     assert lib.hsma_status_string(-4) == b"two charges at the same position"
-    assert lib.hsma_version() == 5
+    assert lib.hsma_version() == 6
 
 
 def test_plan_argument_validation_without_gpu():

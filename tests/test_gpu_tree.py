@@ -1,0 +1,130 @@
+"""The tree-code near sum (HSMA_NEAR_TREE) against the oracle's direct near sum
+over the 3x3x3 image block: element-wise at every particle for small systems,
+on sampled particles at 1e5 and 1e6, for the periodic cube, the grounded cube
+and the slab, in double precision."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import announce, rel_max, rms
+from paper_1806_04801_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# tolerances of the tree near sum at multipole order 14, relative to the rms
+# near potential, the largest near field and 1/2 sum |q phi_near|
+TOL_PHI, TOL_E, TOL_EN = 5e-6, 1e-6, 1e-7
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04801_amd import hsma
+    hsma.load()
+    return hsma
+
+
+def system(bc, n, seed):
+    if bc == 2:
+        return W.slab_charges(n, 1.0, seed)
+    return W.uniform_neutral(n, 1.0, seed)
+
+
+def near_parts(hs, plan, x, q):
+    e, phi, F, inter = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"),
+                                          intermediates=True)
+    torch.cuda.synchronize()
+    return e, inter["phi_near"].cpu().numpy(), inter["field_near"].cpu().numpy()
+
+
+def direct_near(bc, x, q, idx):
+    """The oracle's near sum (27 images, bare self term left out) at idx."""
+    r = oracle.solve(oracle.make_plan(1.0, bc, 4, 400, 100, 2.7), x, q, targets=idx)
+    return r["phi_near"], r["field_near"]
+
+
+def check(tag, q, idx, pn, fn, ref_p, ref_f, order=14):
+    errs = dict(phi=rel_max(pn[idx], ref_p, rms(ref_p)), E=rel_max(fn[idx], ref_f),
+                En=abs(0.5 * np.sum(q[idx] * (pn[idx] - ref_p))) / (0.5 * np.sum(np.abs(q[idx] * ref_p))))
+    print("tree %s order %d: %s" % (tag, order, " ".join("%s %.2e" % kv for kv in errs.items())))
+    return errs
+
+
+@pytest.mark.parametrize("bc,n", [(0, 3000), (1, 2000), (2, 1500), (0, 778), (1, 2)])
+def test_tree_near_sum_vs_direct_every_particle(hs, bc, n):
+    announce("tree near bc=%d n=%d" % (bc, n))
+    x, q = system(bc, n, 50 + n)
+    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
+    assert plan.info["tree_order"] == 14
+    _, pn, fn = near_parts(hs, plan, x, q)
+    idx = np.arange(n)
+    ref_p, ref_f = direct_near(bc, x, q, idx)
+    e = check("bc=%d n=%d" % (bc, n), q, idx, pn, fn, ref_p, ref_f)
+    assert e["phi"] <= TOL_PHI and e["E"] <= TOL_E and e["En"] <= TOL_EN
+
+
+def test_tree_order_controls_the_error(hs):
+    """The error falls geometrically with the multipole order."""
+    announce("tree order sweep")
+    x, q = W.uniform_neutral(4000, 1.0, 71)
+    idx = np.arange(0, 4000, 7)
+    ref_p, ref_f = direct_near(0, x, q, idx)
+    errs = []
+    for order in (6, 10, 14):
+        plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=order)
+        _, pn, fn = near_parts(hs, plan, x, q)
+        errs.append(check("order sweep", q, idx, pn, fn, ref_p, ref_f, order))
+    assert errs[2]["phi"] < 0.1 * errs[1]["phi"] < 0.01 * errs[0]["phi"]
+    assert errs[2]["E"] < 0.1 * errs[0]["E"]
+
+
+@pytest.mark.parametrize("bc,n,ns", [(0, 100_000, 512), (1, 100_000, 512), (0, 1_000_000, 256)])
+def test_tree_near_sum_sampled_at_size(hs, bc, n, ns):
+    announce("tree near bc=%d n=%d sampled" % (bc, n))
+    x, q = system(bc, n, 80)
+    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
+    near_parts(hs, plan, x, q)   # warm
+    t0 = time.perf_counter()
+    e, pn, fn = near_parts(hs, plan, x, q)
+    dt = time.perf_counter() - t0
+    idx = np.sort(np.random.default_rng(5).choice(n, ns, replace=False))
+    ref_p, ref_f = direct_near(bc, x, q, idx)
+    errs = check("bc=%d n=%d (%.1f ms per step)" % (bc, n, 1e3 * dt), q, idx, pn, fn, ref_p, ref_f)
+    assert errs["phi"] <= TOL_PHI and errs["E"] <= TOL_E and errs["En"] <= TOL_EN
+
+
+def test_tree_whole_step_vs_direct_step(hs):
+    """The whole update step with the tree near sum against the direct
+    (pair-once) step: energy, potentials and forces to the tree's tolerance."""
+    announce("tree whole step")
+    x, q = W.uniform_neutral(10000, 1.0, 91)
+    xd, qd = torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda")
+    p_tree = hs.Plan(1.0, 0, 12, 1440, 1440, 2.7, near_mode=hs.NEAR_TREE)
+    p_dir = hs.Plan(1.0, 0, 12, 1440, 1440, 2.7)
+    e1, phi1, F1 = p_tree.energy_forces(xd, qd)
+    e0, phi0, F0 = p_dir.energy_forces(xd, qd)
+    phi0, phi1 = phi0.cpu().numpy(), phi1.cpu().numpy()
+    scale = 0.5 * np.sum(np.abs(q * phi0))
+    assert abs(e1 - e0) <= TOL_EN * scale
+    assert rel_max(phi1, phi0, rms(phi0)) <= TOL_PHI
+    assert rel_max(F1.cpu().numpy(), F0.cpu().numpy()) <= TOL_E
+
+
+def test_tree_rejections(hs):
+    announce("tree rejections")
+    with pytest.raises(hs.HsmaError):
+        hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, precision=hs.FP32_COMP)
+    with pytest.raises(hs.HsmaError):
+        hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=25)
+    plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
+    x, q = W.uniform_neutral(100, 1.0, 3)
+    with pytest.raises(hs.HsmaError):
+        plan.energy_grad(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+    srv = hs.Server(memory_bytes=64 << 20, max_active=2, precision=hs.FP64)
+    with pytest.raises(hs.HsmaError):
+        srv.submit(plan, x, q)
+    srv.close()
