@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="default workload: also run this many requests of the serving stream "
                          "(object 'serving' of the line; 0 skips it)")
+    ap.add_argument("--n", type=int, default=0,
+                    help="particles (default: the workload's own count); the same seeded recipe at "
+                         "another size")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB device buffer (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -418,7 +421,7 @@ def main():
     cfg = dict(workloads.CONFIGS[args.workload])
     prec_name = args.precision or ("fp32" if args.workload in ("periodic1m", "slab200k") else "fp64")
     prec = hsma.FP32_COMP if prec_name == "fp32" else hsma.FP64
-    x, q = workloads.make_inputs(args.workload)
+    x, q = workloads.make_inputs(args.workload, n=args.n if args.n > 0 else None)
     n = len(q)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -500,7 +503,9 @@ def main():
         # unordered cross-block pairs with both directions at 28 flops
         both = NEAR_FLOPS_PER_UNORDERED_PAIR_BOTH_DIRECTIONS * (near_pairs / 2.0)
         other_fracs["flops_28_per_unordered_pair_image_both_directions"] = both / near_avg_s / 1e12 / peak
-    counted = profiled_field(args.workload, ptag, kind, "counter_tflops")
+    # the workload's name, or name and size when --n resizes it (profiles are per name)
+    wtag = args.workload if args.n <= 0 else "%s_n%d" % (args.workload, n)
+    counted = profiled_field(wtag, ptag, kind, "counter_tflops")
     if counted is not None:
         other_fracs["valu_flops_counted_by_rocprof"] = counted / peak
     rec = {
@@ -517,7 +522,7 @@ def main():
         "dtype": "f32" if prec == hsma.FP32_COMP else "f64",
         "data": "synthetic",
         "config": {
-            "workload": args.workload,
+            "workload": wtag,
             "near_set": args.near,
             "surface_dipole": args.dipole,
             "far_field": args.far,
@@ -540,7 +545,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": profiled_traffic(args.workload, ptag, kind),
+            "traffic": profiled_traffic(wtag, ptag, kind),
         },
     }
     if host_entry is not None:
@@ -550,7 +555,7 @@ def main():
     plan.close()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(x, q, cfg, args.cpu_targets)
-    if args.serving_requests > 0 and args.workload == "periodic1m":
+    if args.serving_requests > 0 and args.workload == "periodic1m" and args.n <= 0:
         # the serving half of the metric (solves/s and p99 latency at 1e-5)
         torch.cuda.empty_cache()
         rec["serving"] = serving_measure(args.serving_requests, args.refine)

@@ -66,11 +66,12 @@ typedef enum {
     HSMA_NEAR_SPHERE = 1,  /* near set: every image inside the auxiliary sphere |r| < R_s (the
                               paper's literal near set, Sec. II.A); images generated per call;
                               no adjoint and no serving in this mode */
-    HSMA_NEAR_TREE = 2     /* near set of HSMA_NEAR_BLOCK, summed by a tree code instead of
-                              directly (the O(N log N) acceleration of the near sum, Sec. II.C):
-                              multipoles of order hsma_plan_desc.tree_order about the cells of a
-                              uniform octree over the 27 boxes, direct sums between neighbouring
-                              leaf cells; about 1e-6 of the rms potential at order 14; double
+    HSMA_NEAR_TREE = 2     /* near set of HSMA_NEAR_BLOCK, summed by the fast multipole method
+                              instead of directly (the O(N) acceleration of the near sum,
+                              Sec. II.C, Table I): multipole and local expansions of order
+                              hsma_plan_desc.tree_order about the cells of a uniform octree over
+                              the 27 boxes (at most HSMA_TREE_LEAF images per leaf cell, 320 by
+                              default), direct sums between neighbouring leaf cells; double
                               precision; periodic, grounded cube and slab; no adjoint and no
                               serving in this mode */
 } hsma_near_mode;
@@ -126,7 +127,7 @@ typedef struct {
     int far_shells;    /* HSMA_BC_DIELECTRIC: far image shells S, images with
                           2 <= max_a |k_a| <= S; 0 picks the smallest S whose omitted tail is
                           below 1e-13 sum|q|/L at the monitoring points */
-    int tree_order;    /* HSMA_NEAR_TREE: multipole order, 1..20 (0 selects 14) */
+    int tree_order;    /* HSMA_NEAR_TREE: expansion order, 1..20 (0 selects 16) */
 } hsma_plan_desc;
 
 typedef struct {

@@ -149,7 +149,7 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     pl->dipole_mode = d->dipole_mode;
     pl->far_mode = d->far_mode;
     pl->dr = d->dr > 0.0 ? d->dr : 1e-5 * d->R;
-    pl->tree_order = d->near_mode == HSMA_NEAR_TREE ? (d->tree_order > 0 ? d->tree_order : 14) : 0;
+    pl->tree_order = d->near_mode == HSMA_NEAR_TREE ? (d->tree_order > 0 ? d->tree_order : 16) : 0;
     if (pl->near_mode == HSMA_NEAR_SPHERE) {
         // candidates |k_a| <= kr; a source has at most as many images inside the
         // sphere as there are shifted boxes that reach it

@@ -85,10 +85,14 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.off_A = take(sizeof(double) * (size_t)pl->nb);
     ly.off_surf = take(sizeof(double) * 12 * (size_t)pl->M);   // 8 per point, or 3 charges
     if (tree) {
-        // the tree writes one copy of phi and E: one chunk of the tile layout
+        // the tree writes eval_split copies of phi and E: chunks of the tile layout
+        // the right-hand side comes from the same tree (one chunk), on the
+        // caller's stream after the tree is built
         ly.tree = true;
-        ly.g_near.S = 1;
         ly.tl = tree_layout(ly.ns, pl->tree_order);
+        ly.g_near.S = ly.tl.eval_split;
+        ly.g_rhs.S = 1;
+        ly.single_stream = true;
     }
     {
         size_t near_doubles = 4 * (size_t)ly.g_near.S * ly.g_near.nt_pad;
@@ -376,6 +380,14 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
             CK(launch_make_rec32(img64, n_img, pl->L, img32, s));
         }
     }
+    if (ly.tree) {
+        // the tree (images, sort, multipoles) serves the near sum here and the
+        // right-hand side below; the near sum's timing covers the build
+        timing_begin(0, s);
+        CK(launch_tree_build(pl->img, src64, ly.ns, pl->L, ly.tl, ws + ly.off_tree, s));
+        CK(launch_tree_near(N, pl->L, ly.tl, ws + ly.off_tree, near_part, g_near.nt_pad, s));
+        timing_end(0, s);
+    }
     // fork: the right-hand-side chain goes to the auxiliary stream; the
     // caller's stream waits for it again before the surface stage, and on
     // every early return (a failed launch), so that no work of this call on
@@ -400,7 +412,9 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
     }
     // right-hand side at the monitoring points (and twins)
     timing_begin(1, s1);
-    if (sphere)
+    if (ly.tree)
+        CK(launch_tree_points(pl->d_chk64, pl->nchk, pl->L, ly.tl, ws + ly.off_tree, rhs_part, s1));
+    else if (sphere)
         CK(launch_explicit(f32, false, false, f32 ? (const void*)pl->d_chk32 : (const void*)pl->d_chk64,
                            f32 ? (const void*)img32 : (const void*)img64, g_rhs, pl->L, rhs_part, s1));
     else if (pl->img == IMG_DIELECTRIC)
@@ -427,11 +441,10 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
     CK(hipGetLastError());
     if (aux != nullptr) CK(hipEventRecord(aux->join, s1));
     // near field at the particles: the sources and their 27 images, self excluded
-    timing_begin(0, s);
-    if (ly.tree)
-        CK(launch_tree_near(pl->img, src64, ly.ns, N, pl->L, ly.tl, ws + ly.off_tree, near_part,
-                            g_near.nt_pad, s));
-    else if (sphere)
+    if (!ly.tree) timing_begin(0, s);
+    if (ly.tree) {
+        // computed above
+    } else if (sphere)
         CK(launch_explicit(f32, true, true, f32 ? (const void*)src32 : (const void*)src64,
                            f32 ? (const void*)img32 : (const void*)img64, g_near, pl->L, near_part, s));
     else if (ly.sym && f32)
@@ -442,7 +455,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
         CK(launch_pair_f32(pl->img, true, true, src32, src32, g_near, pl->L, near_part, s));
     else
         CK(launch_pair_f64(pl->img, true, true, src64, src64, g_near, pl->L, near_part, s, pl->gamma));
-    timing_end(0, s);
+    if (!ly.tree) timing_end(0, s);
     // join, then the surface images at the particles
     if (aux != nullptr) {
         CK(hipStreamWaitEvent(s, aux->join, 0));

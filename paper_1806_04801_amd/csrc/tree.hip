@@ -1,7 +1,7 @@
-// Near-field sum over the 3x3x3 image block by a tree code (the O(N log N)
-// acceleration of the near sum that Sec. II.C and Table I leave to the FMM):
-// the same quantity as the direct near kernels, phi_i and E_i from every
-// image of every source in the block except the bare self term, to a
+// Near-field sum over the 3x3x3 image block by the fast multipole method (the
+// O(N) acceleration of the near sum that Sec. II.C and Table I leave to the
+// FMM): the same quantity as the direct near kernels, phi_i and E_i from
+// every image of every source in the block except the bare self term, to a
 // tolerance set by the expansion order.
 //
 // Sources are the explicit images (27 per source: periodic r + kL, grounded
@@ -12,7 +12,7 @@
 // are sorted by leaf cell (box index, then the Morton code of the cell in its
 // box), so that every cell at every level is a contiguous range.
 //
-// Multipoles about cell centres in complex solid harmonics,
+// Expansions about cell centres in complex solid harmonics,
 //   R_n^m(r) = r^n P_n^m(cos t) e^{i m phi} / (n + m)!,
 //   I_n^m(r) = (n - m)! P_n^m(cos t) e^{i m phi} / r^{n + 1}       (m >= 0),
 // with 1/|x - y| = sum_{n,m} conj(R_n^m(y)) I_n^m(x) for |y| < |x| (negative m
@@ -21,23 +21,26 @@
 //   (n^2 - m^2) R_n^m = (2n - 1) z R_{n-1}^m - r^2 R_{n-2}^m,
 //   I_m^m = (2m - 1) (x + iy) / r^2 I_{m-1}^{m-1},
 //   r^2 I_n^m = (2n - 1) z I_{n-1}^m - ((n - 1)^2 - m^2) I_{n-2}^m.
-// Leaf moments M_n^m = sum_j q_j conj(R_n^m(y_j - c)) are summed per cell;
-// coarser ones by translation to the parent centre,
-//   M~_n^m(P) = sum_{j,k} conj(R~_j^k(c_C - c_P)) M~_{n-j}^{m-k}(C),
-// with R~_n^m = R_n^m for m >= 0 and (-1)^m R_n^m for m < 0 (the convention
-// in which the addition theorem of the regular harmonics is a plain
-// convolution).  A target evaluates, at every level, the cells that are
-// children of its parent cell's neighbours but not its own cell's neighbours
-// (up to 189 per level), from their moments:
-//   phi = sum M_n^m I_n^m,   E_z = sum M_n^m I_{n+1}^m,
-//   E_x + i E_y = sum_{m >= 0} M_n^m I_{n+1}^{m+1} - sum_{m >= 1} conj(M_n^m I_{n+1}^{m-1})
-// (d/dz I_n^m = -I_{n+1}^m and (d/dx + i d/dy) I_n^m = -I_{n+1}^{m+1} for
-// m >= 0), and the sources of the 27 neighbouring leaf cells directly.  Every
-// sum runs in a fixed order: results are bitwise reproducible.
+// In the signed convention X~_n^m = X_n^m for m >= 0 and (-1)^m X_n^m for
+// m < 0 the translation theorems are plain convolutions:
+//   R~_n^m(a + b) = sum_{j,k} R~_j^k(a) R~_{n-j}^{m-k}(b),
+//   I~_n^m(D + d) = sum_{j,k} (-1)^{j+k} R~_j^k(d) I~_{n+j}^{m-k}(D)  (|d| < |D|),
+// the second from the Taylor series of a harmonic function with
+// d/dz I~_n^m = -I~_{n+1}^m, (d/dx + i d/dy) I~_n^m = -I~_{n+1}^{m+1} and
+// (d/dx - i d/dy) I~_n^m = I~_{n+1}^{m-1}.
+// Upward pass: leaf multipoles M_n^m = sum_j q_j conj(R_n^m(y_j - c)), coarser
+// ones by translation to the parent centre.  Downward pass, for the cells of
+// the central box only (they hold the targets): local expansions from the
+// multipoles of the interaction list (children of the parent's neighbours that
+// are not the cell's own neighbours, up to 189 per level) plus the parent's
+// local expansion shifted to the cell.  Targets evaluate their leaf cell's
+// local expansion and the sources of the 27 neighbouring leaf cells directly.
+// Every sum runs in a fixed order: results are bitwise reproducible.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "hsma_internal.h"
@@ -49,6 +52,10 @@ namespace hsma {
 constexpr int TWG = 64;   // one wave per work-group
 
 __host__ __device__ __forceinline__ int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+
+struct MomPtrs {
+    const double2* lev[TREE_MAX_LEVEL + 1];   // multipoles of each level 0..L
+};
 
 // Interleaved bits of (ix, iy, iz), 3 x 7 bits.
 __device__ __forceinline__ uint32_t morton3(uint32_t ix, uint32_t iy, uint32_t iz) {
@@ -123,29 +130,42 @@ __global__ void k_tree_gather(const double4* __restrict__ img, const int* __rest
     owner[i] = (s / ns == 13) ? s % ns : -1;
 }
 
-__global__ void k_tree_count(const uint32_t* __restrict__ keys, int64_t n, int* __restrict__ cnt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[keys[i]], 1);
-}
-
-__global__ void k_tree_zero_int(int* __restrict__ a, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = 0;
+// offs[c] = the first sorted position whose key is >= c, c = 0..ncell (the
+// sorted keys do not decrease): leaf cell c holds positions [offs[c], offs[c+1]).
+__global__ void k_tree_offsets(const uint32_t* __restrict__ keys, int64_t n, int64_t ncell,
+                               int* __restrict__ offs) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > ncell) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    offs[c] = (int)lo;
 }
 
 // ---------------------------------------------------------------- leaf moments
-// Thread (cell, m): column m of the moments of leaf cell `cell`, summed over
-// its sources in sorted order.
-__global__ void k_tree_p2m(const double4* __restrict__ srt, const int* __restrict__ offs, int lev,
-                           int ncell, int p, double L, double2* __restrict__ mom) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = (int)(t % (p + 1));
-    const int64_t cell = t / (p + 1);
-    if (cell >= ncell) return;
+// Thread (cell, m), m = blockIdx.y uniform over the wave: column m of the
+// moments of leaf cell `cell`, summed over its sources in sorted order.  The
+// loops over n are unrolled to the largest order (guards n <= p are uniform),
+// so the accumulators stay in registers; the recurrence's reciprocals depend
+// on (n, m) only and are formed once per thread.
+__global__ void __launch_bounds__(64)
+k_tree_p2m(const double4* __restrict__ srt, const int* __restrict__ offs, int lev, int ncell, int p,
+           double L, double2* __restrict__ mom) {
+    const int m = blockIdx.y;
+    const int64_t cell = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (cell >= ncell || m > p) return;
     const int b = offs[cell], e = offs[cell + 1];
     double2* out = mom + (size_t)cell * tri(p + 1, 0);
-    double ar[TREE_MAX_ORDER + 1], ai[TREE_MAX_ORDER + 1];
-    for (int n = 0; n <= p; ++n) ar[n] = ai[n] = 0.0;
+    constexpr int P = TREE_MAX_ORDER;
+    double ar[P + 1], ai[P + 1], rinv[P + 1];
+#pragma unroll
+    for (int n = 0; n <= P; ++n) {
+        ar[n] = ai[n] = 0.0;
+        rinv[n] = (n > m) ? 1.0 / ((double)(n + m) * (double)(n - m)) : 0.0;
+    }
     if (b < e) {
         // cell centre from its key: box index and Morton code within the box
         const uint32_t key = (uint32_t)cell;
@@ -166,18 +186,23 @@ __global__ void k_tree_p2m(const double4* __restrict__ srt, const int* __restric
             const double r2 = x * x + yy * yy + z * z;
             // R_m^m = (x + iy)^m / (2^m m!)
             double dr = 1.0, di = 0.0;
-            for (int k = 1; k <= m; ++k) {
-                const double nr = (dr * x - di * yy) / (2.0 * k);
-                const double ni = (dr * yy + di * x) / (2.0 * k);
-                dr = nr;
-                di = ni;
+#pragma unroll
+            for (int k = 1; k <= P; ++k) {
+                if (k <= m) {
+                    const double c = 0.5 / (double)k;
+                    const double nr = (dr * x - di * yy) * c;
+                    const double ni = (dr * yy + di * x) * c;
+                    dr = nr;
+                    di = ni;
+                }
             }
             double pr = 0.0, pi = 0.0, cr = dr, ci = di;   // R_{n-2}, R_{n-1}
-            for (int n = m; n <= p; ++n) {
+#pragma unroll
+            for (int n = 0; n <= P; ++n) {
+                if (n < m || n > p) continue;
                 if (n > m) {
-                    const double inv = 1.0 / ((double)(n + m) * (double)(n - m));
-                    const double nr = ((2 * n - 1) * z * cr - r2 * pr) * inv;
-                    const double ni = ((2 * n - 1) * z * ci - r2 * pi) * inv;
+                    const double nr = ((2 * n - 1) * z * cr - r2 * pr) * rinv[n];
+                    const double ni = ((2 * n - 1) * z * ci - r2 * pi) * rinv[n];
                     pr = cr; pi = ci; cr = nr; ci = ni;
                 }
                 // M += q conj(R)
@@ -186,7 +211,9 @@ __global__ void k_tree_p2m(const double4* __restrict__ srt, const int* __restric
             }
         }
     }
-    for (int n = m; n <= p; ++n) out[tri(n, m)] = make_double2(ar[n], ai[n]);
+#pragma unroll
+    for (int n = 0; n <= P; ++n)
+        if (n >= m && n <= p) out[tri(n, m)] = make_double2(ar[n], ai[n]);
 }
 
 // ---------------------------------------------------------------- translation
@@ -236,16 +263,21 @@ __global__ void k_tree_m2m(const double2* __restrict__ child, const int* __restr
     parent[(size_t)cell * nt + idx] = make_double2(sr, si);
 }
 
-// ---------------------------------------------------------------- evaluation
-// phi and E at a target displaced d from a cell centre, from the cell's
-// moments M (m >= 0, row-packed by tri): columns m of I_n^m, n = m..p+1, in
-// turn, each combined with the moments of rows n and n - 1.
-__device__ __forceinline__ void m2p(const double2* __restrict__ M, int p, double x, double y,
-                                    double z, double& phi, double& ez, double& wr, double& wi) {
-    const double r2 = x * x + y * y + z * z;
-    const double ir2 = 1.0 / r2;
-    double dr = rsqrt_f64(r2), di = 0.0;   // I_m^m
-    for (int m = 0; m <= p + 1; ++m) {
+// ---------------------------------------------------------------- downward pass
+// Irregular harmonics I~_n^m(D) at the integer offsets D in [-3, 3]^3 (unit
+// cell side; offset index (Dx+3)*49 + (Dy+3)*7 + (Dz+3)), orders n <= p2,
+// full layout n*n + n + m for m in [-n, n] with I~_n^-m = (-1)^m conj(I_n^m).
+// Offsets of neighbouring cells (|D_a| <= 1) are never used and left unset.
+__global__ void k_fmm_itab(int p2, double2* __restrict__ tab) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= 343) return;
+    const int dx = o / 49 - 3, dy = (o / 7) % 7 - 3, dz = o % 7 - 3;
+    if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) return;
+    const double x = dx, y = dy, z = dz;
+    const double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
+    double2* T = tab + (size_t)o * (p2 + 1) * (p2 + 1);
+    double dr = 1.0 / sqrt(r2), di = 0.0;   // I_m^m
+    for (int m = 0; m <= p2; ++m) {
         if (m > 0) {
             const double f = (2 * m - 1) * ir2;
             const double nr = f * (x * dr - y * di);
@@ -253,53 +285,216 @@ __device__ __forceinline__ void m2p(const double2* __restrict__ M, int p, double
             dr = nr;
             di = ni;
         }
-        const double wm = m == 0 ? 1.0 : 2.0;
         double pr = 0.0, pi = 0.0, cr = dr, ci = di;
-        for (int n = m; n <= p + 1; ++n) {
+        for (int n = m; n <= p2; ++n) {
             if (n > m) {
                 const double c2 = (double)((n - 1) * (n - 1) - m * m);
                 const double nr = ((2 * n - 1) * z * cr - c2 * pr) * ir2;
                 const double ni = ((2 * n - 1) * z * ci - c2 * pi) * ir2;
                 pr = cr; pi = ci; cr = nr; ci = ni;
             }
-            if (n <= p) {   // phi: M_n^m I_n^m
-                const double2 a = M[tri(n, m)];
-                phi += wm * (a.x * cr - a.y * ci);
-            }
-            if (n >= 1 && m <= n - 1 && n - 1 <= p) {   // E_z: M_{n-1}^m I_n^m
-                const double2 a = M[tri(n - 1, m)];
-                ez += wm * (a.x * cr - a.y * ci);
-            }
-            if (m >= 1 && n - 1 <= p) {   // M_{n-1}^{m-1} I_n^m
-                const double2 a = M[tri(n - 1, m - 1)];
-                wr += a.x * cr - a.y * ci;
-                wi += a.x * ci + a.y * cr;
-            }
-            if (m + 1 <= n - 1 && n - 1 <= p) {   // -conj(M_{n-1}^{m+1} I_n^m)
-                const double2 a = M[tri(n - 1, m + 1)];
-                wr -= a.x * cr - a.y * ci;
-                wi += a.x * ci + a.y * cr;
+            T[n * n + n + m] = make_double2(cr, ci);
+            if (m > 0) {
+                const double sg = (m & 1) ? -1.0 : 1.0;
+                T[n * n + n - m] = make_double2(sg * cr, -sg * ci);
             }
         }
     }
 }
 
-// One wave per leaf cell of the central box: its targets (central images of
-// real particles) get the far cells of every level and the direct sum over
-// the 27 neighbouring leaf cells.  out[(comp) * npad + i], comp 0 = phi,
-// 1..3 = E, for target i.
-struct MomPtrs {
-    const double2* lev[TREE_MAX_LEVEL + 1];   // moments of each level (index 1..L)
-};
+constexpr int FWG = 256;   // threads of a downward-pass work-group (>= outputs (p+1)(p+2)/2)
+constexpr int NF = (TREE_MAX_ORDER + 1) * (TREE_MAX_ORDER + 1);
+constexpr int NI = (2 * TREE_MAX_ORDER + 1) * (2 * TREE_MAX_ORDER + 1);
 
+// Target cell of the central box at level l from its Morton index.
+__device__ __forceinline__ void central_cell(int cid, int l, int& tx, int& ty, int& tz) {
+    uint32_t ix = 0, iy = 0, iz = 0;
+    for (int b = 0; b < l; ++b) {
+        ix |= ((cid >> (3 * b + 2)) & 1u) << b;
+        iy |= ((cid >> (3 * b + 1)) & 1u) << b;
+        iz |= ((cid >> (3 * b)) & 1u) << b;
+    }
+    const int side = 1 << l;
+    tx = side + (int)ix;
+    ty = side + (int)iy;
+    tz = side + (int)iz;
+}
+
+// Output (j, k) of thread t of a downward-pass work-group (t = tri(j, k)).
+__device__ __forceinline__ void coef_of(int t, int& j, int& k) {
+    j = 0;
+    while (tri(j + 1, 0) <= t) ++j;
+    k = t - tri(j, 0);
+}
+
+// Full signed table X~_n^m, m in [-n, n] (index n*n + n + m), of expansion
+// coefficients stored for m >= 0 (row-packed by tri), times scale^n.
+__device__ __forceinline__ void stage_signed(const double2* __restrict__ X, int p, const double* sc,
+                                             double2* __restrict__ dst) {
+    for (int idx = threadIdx.x; idx < (p + 1) * (p + 1); idx += FWG) {
+        int n = 0;
+        while ((n + 1) * (n + 1) <= idx) ++n;
+        const int m = idx - n * n - n;
+        double2 v = X[tri(n, m < 0 ? -m : m)];
+        if (m < 0) {
+            v.y = -v.y;
+            if ((-m) & 1) { v.x = -v.x; v.y = -v.y; }
+        }
+        const double f = sc ? sc[n] : 1.0;
+        dst[idx] = make_double2(v.x * f, v.y * f);
+    }
+}
+
+// M2L of the cells of the central box at level l: work-group (cell, g), one
+// thread per coefficient L_j^k (k >= 0), takes the entries g, g + G, g + 2G,
+// ... of the cell's interaction list (children of the parent's neighbours
+// that are not neighbours of the cell, non-empty, in a fixed order), D =
+// c_T - c_S:
+//   part_g L_j^k = (-1)^{j+k} sum_S sum_{n <= p, m} M~_n^m(S) I~_{n+j}^{m-k}(D).
+// The source moments (scaled by h^-n) and the irregular harmonics of the
+// offset (unit side; the remaining h^-(j+1) is applied at the end) are staged
+// in LDS per source cell; the LDS is sized by the order (dynamic), so that
+// low orders keep more work-groups resident to hide the staging.
+__global__ void __launch_bounds__(FWG)
+k_fmm_m2l(const double2* __restrict__ mom, const int* __restrict__ offs, int l, int L, int p,
+          double Lbox, const double2* __restrict__ itab, int G, double2* __restrict__ part) {
+    extern __shared__ double2 lds[];
+    double2* Mt = lds;                              // (p+1)^2
+    double2* It = lds + (p + 1) * (p + 1);          // (2p+1)^2
+    double* hpow = (double*)(It + (2 * p + 1) * (2 * p + 1));
+    const int t = threadIdx.x;
+    const int nc = tri(p + 1, 0);
+    const int p2 = 2 * p;
+    const int ni = (p2 + 1) * (p2 + 1);
+    const bool out = t < nc;
+    int j = 0, k = 0;
+    if (out) coef_of(t, j, k);
+    const int cid = blockIdx.x, g = blockIdx.y;
+    int tx, ty, tz;
+    central_cell(cid, l, tx, ty, tz);
+    const double h = Lbox / (double)(1 << l);
+    if (t <= p) {
+        double v = 1.0;
+        for (int n = 0; n < t; ++n) v /= h;
+        hpow[t] = v;   // h^-t
+    }
+    __syncthreads();
+    const int GG = 3 << l;
+    const int shift = 3 * (L - l);
+    const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
+    double br = 0.0, bi = 0.0;
+    int item = 0;
+    for (int cx = 2 * px - 2; cx <= 2 * px + 3; ++cx) {
+        if (cx < 0 || cx >= GG) continue;
+        for (int cy = 2 * py - 2; cy <= 2 * py + 3; ++cy) {
+            if (cy < 0 || cy >= GG) continue;
+            for (int cz = 2 * pz - 2; cz <= 2 * pz + 3; ++cz) {
+                if (cz < 0 || cz >= GG) continue;
+                if (abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1) continue;
+                const uint32_t ck = cell_key(cx, cy, cz, l);
+                if (offs[(size_t)(ck + 1) << shift] == offs[(size_t)ck << shift]) continue;
+                if ((item++) % G != g) continue;
+                stage_signed(mom + (size_t)ck * nc, p, hpow, Mt);
+                const int o = (tx - cx + 3) * 49 + (ty - cy + 3) * 7 + (tz - cz + 3);
+                const double2* I = itab + (size_t)o * ni;
+                for (int idx = t; idx < ni; idx += FWG) It[idx] = I[idx];
+                __syncthreads();
+                if (out) {
+                    for (int n = 0; n <= p; ++n) {
+                        const int nn = n + j;
+                        const double2* Irow = It + nn * nn + nn - k;
+                        const double2* Mrow = Mt + n * n + n;
+                        for (int m = -n; m <= n; ++m) {
+                            const double2 a = Mrow[m];
+                            const double2 c = Irow[m];
+                            br += a.x * c.x - a.y * c.y;
+                            bi += a.x * c.y + a.y * c.x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (out) {
+        double f = ((j + k) & 1) ? -1.0 : 1.0;
+        f *= hpow[j] / h;   // h^-(j+1)
+        part[((size_t)g * gridDim.x + cid) * nc + t] = make_double2(f * br, f * bi);
+    }
+}
+
+// Local expansions of the cells of the central box at level l: the G M2L
+// parts in order, plus (l >= 2) the parent's expansion shifted to the cell,
+//   L~_j^k += sum_{n >= j, m} L~_n^m(P) R~_{n-j}^{m-k}(c_T - c_P),
+// with R~ from the child-offset table (conj(R~) at unit parent side).
+__global__ void __launch_bounds__(FWG)
+k_fmm_l2l(const double2* __restrict__ part, int G, int l, int p, double Lbox,
+          const double2* __restrict__ m2m_tab, const double2* __restrict__ parent_loc,
+          double2* __restrict__ loc) {
+    __shared__ double2 Lt[NF];
+    const int t = threadIdx.x;
+    const int nc = tri(p + 1, 0);
+    const int nf = (p + 1) * (p + 1);
+    const bool out = t < nc;
+    int j = 0, k = 0;
+    if (out) coef_of(t, j, k);
+    const int cid = blockIdx.x;
+    double ar = 0.0, ai = 0.0;
+    if (out)
+        for (int g = 0; g < G; ++g) {
+            const double2 v = part[((size_t)g * gridDim.x + cid) * nc + t];
+            ar += v.x;
+            ai += v.y;
+        }
+    if (l >= 2) {
+        stage_signed(parent_loc + (size_t)(cid >> 3) * nc, p, nullptr, Lt);
+        __syncthreads();
+        if (out) {
+            const double2* T = m2m_tab + (size_t)(cid & 7) * nf;
+            const double sp = 2.0 * Lbox / (double)(1 << l);   // parent side
+            double sd = 1.0;                                    // sp^(n - j)
+            double cr = 0.0, ci = 0.0;
+            for (int n = j; n <= p; ++n) {
+                const int d = n - j;
+                double er = 0.0, ei = 0.0;
+                for (int m = -n; m <= n; ++m) {
+                    const int mu = m - k;
+                    if (mu < -d || mu > d) continue;
+                    const double2 a = Lt[n * n + n + m];
+                    const double2 r = T[d * d + d + mu];   // conj(R~)
+                    er += a.x * r.x + a.y * r.y;
+                    ei += a.y * r.x - a.x * r.y;
+                }
+                cr += sd * er;
+                ci += sd * ei;
+                sd *= sp;
+            }
+            ar += cr;
+            ai += ci;
+        }
+    }
+    if (out) loc[(size_t)cid * nc + t] = make_double2(ar, ai);
+}
+
+// ---------------------------------------------------------------- evaluation
+// Wave (leaf cell of the central box, chunk g of Gs), a lane per target
+// (central images of real particles): chunk 0 evaluates the cell's local
+// expansion at the target,
+//   phi = sum L_n^m R_n^m(d),  E_z = -sum L_n^m R_{n-1}^m(d),
+//   E_x + i E_y = sum_{m >= 0} L_n^m R_{n-1}^{m+1}(d) - sum_{m >= 1} conj(L_n^m R_{n-1}^{m-1}(d))
+// (d = target - cell centre; d/dz R_n^m = R_{n-1}^m, (d/dx + i d/dy) R_n^m =
+// -R_{n-1}^{m+1}), and every chunk sums the sources of the neighbouring leaf
+// cells g, g + Gs, ... of the 27 directly.  out[(g * 4 + comp) * npad + i],
+// comp 0 = phi, 1..3 = E, for target i.
 __global__ void __launch_bounds__(TWG)
 k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
-            const int* __restrict__ offs, MomPtrs moms, int L, int p, double Lbox, int nt,
-            double* __restrict__ out, int npad) {
+            const int* __restrict__ offs, const double2* __restrict__ loc, int L, int p, double Lbox,
+            int nt, double* __restrict__ out, int npad) {
+    const int g = blockIdx.y, Gs = gridDim.y;
+    out += (size_t)g * 4 * npad;
     const int lane = threadIdx.x;
     const int side = 1 << L;
     const int cid = blockIdx.x;   // Morton index within the central box
-    // leaf coordinates of the cell (central box: global offset side)
     uint32_t ix = 0, iy = 0, iz = 0;
     for (int b = 0; b < L; ++b) {
         ix |= ((cid >> (3 * b + 2)) & 1u) << b;
@@ -309,52 +504,65 @@ k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
     const int gx = side + (int)ix, gy = side + (int)iy, gz = side + (int)iz;
     const uint32_t key = cell_key(gx, gy, gz, L);
     const int b0 = offs[key], b1 = offs[key + 1];
+    const double h = Lbox / (double)side;
+    const double ccx = -1.5 * Lbox + (gx + 0.5) * h;
+    const double ccy = -1.5 * Lbox + (gy + 0.5) * h;
+    const double ccz = -1.5 * Lbox + (gz + 0.5) * h;
+    const double2* LL = loc + (size_t)cid * tri(p + 1, 0);
     for (int base = b0; base < b1; base += TWG) {
         const int s = base + lane;
         const bool act = s < b1;
         const int me = act ? owner[s] : -1;
         const bool tgt = act && me >= 0 && me < nt;
-        double4 t = srt[act ? s : b0];
+        const double4 t = srt[act ? s : b0];
         double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-        // far cells, level by level
-        for (int l = 1; l <= L; ++l) {
-            const int G = 3 << l;
-            const double h = Lbox / (double)(1 << l);
-            const int tx = gx >> (L - l), ty = gy >> (L - l), tz = gz >> (L - l);
-            const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
-            const double2* M = moms.lev[l];
-            const int nc = tri(p + 1, 0);
-            const int shift = 3 * (L - l);
-            for (int cx = 2 * px - 2; cx <= 2 * px + 3; ++cx) {
-                if (cx < 0 || cx >= G) continue;
-                for (int cy = 2 * py - 2; cy <= 2 * py + 3; ++cy) {
-                    if (cy < 0 || cy >= G) continue;
-                    for (int cz = 2 * pz - 2; cz <= 2 * pz + 3; ++cz) {
-                        if (cz < 0 || cz >= G) continue;
-                        if (abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1) continue;
-                        const uint32_t ck = cell_key(cx, cy, cz, l);
-                        if (offs[(size_t)(ck + 1) << shift] == offs[(size_t)ck << shift]) continue;
-                        const double ccx = -1.5 * Lbox + (cx + 0.5) * h;
-                        const double ccy = -1.5 * Lbox + (cy + 0.5) * h;
-                        const double ccz = -1.5 * Lbox + (cz + 0.5) * h;
-                        double f = 0.0, fz = 0.0, wr = 0.0, wi = 0.0;
-                        m2p(M + (size_t)ck * nc, p, t.x - ccx, t.y - ccy, t.z - ccz, f, fz, wr, wi);
-                        phi += f;
-                        ex += wr;
-                        ey += wi;
-                        ez += fz;
+        if (g == 0) {
+            // columns m of R_n^m(d), n = m..p, each combined with the
+            // coefficients of rows n and n + 1
+            const double x = t.x - ccx, y = t.y - ccy, z = t.z - ccz;
+            const double r2 = x * x + y * y + z * z;
+            double dr = 1.0, di = 0.0;   // R_m^m
+            for (int m = 0; m <= p; ++m) {
+                if (m > 0) {
+                    const double nr = (dr * x - di * y) / (2.0 * m);
+                    const double ni = (dr * y + di * x) / (2.0 * m);
+                    dr = nr;
+                    di = ni;
+                }
+                const double wm = m == 0 ? 1.0 : 2.0;
+                double pr = 0.0, pi = 0.0, cr = dr, ci = di;
+                for (int n = m; n <= p; ++n) {
+                    if (n > m) {
+                        const double inv = 1.0 / ((double)(n + m) * (double)(n - m));
+                        const double nr = ((2 * n - 1) * z * cr - r2 * pr) * inv;
+                        const double ni = ((2 * n - 1) * z * ci - r2 * pi) * inv;
+                        pr = cr; pi = ci; cr = nr; ci = ni;
+                    }
+                    const double2 a = LL[tri(n, m)];
+                    phi += wm * (a.x * cr - a.y * ci);
+                    if (n + 1 <= p) {
+                        const double2 b = LL[tri(n + 1, m)];       // E_z: L_{n+1}^m R_n^m
+                        ez -= wm * (b.x * cr - b.y * ci);
+                        const double2 c = LL[tri(n + 1, m + 1)];   // -conj(L_{n+1}^{m+1} R_n^m)
+                        ex -= c.x * cr - c.y * ci;
+                        ey += c.x * ci + c.y * cr;
+                        if (m >= 1) {                              // L_{n+1}^{m-1} R_n^m
+                            const double2 e = LL[tri(n + 1, m - 1)];
+                            ex += e.x * cr - e.y * ci;
+                            ey += e.x * ci + e.y * cr;
+                        }
                     }
                 }
             }
         }
-        // neighbouring leaf cells, directly
+        // neighbouring leaf cells of this chunk, directly
         const int G = 3 << L;
+        int item = 0;
         for (int cx = gx - 1; cx <= gx + 1; ++cx) {
-            if (cx < 0 || cx >= G) continue;
             for (int cy = gy - 1; cy <= gy + 1; ++cy) {
-                if (cy < 0 || cy >= G) continue;
                 for (int cz = gz - 1; cz <= gz + 1; ++cz) {
-                    if (cz < 0 || cz >= G) continue;
+                    if ((item++) % Gs != g) continue;
+                    if (cx < 0 || cx >= G || cy < 0 || cy >= G || cz < 0 || cz >= G) continue;
                     const uint32_t ck = cell_key(cx, cy, cz, L);
                     const int e0 = offs[ck], e1 = offs[ck + 1];
                     for (int j = e0; j < e1; ++j) {
@@ -382,12 +590,167 @@ k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
     }
 }
 
+// ---------------------------------------------------------------- points
+// Potential at a point displaced (x, y, z) from a cell centre, from the
+// cell's multipoles (m >= 0, row-packed): phi = sum_{n,m} M_n^m I_n^m.
+__device__ double m2p_phi(const double2* __restrict__ M, int p, double x, double y, double z) {
+    const double r2 = x * x + y * y + z * z;
+    const double ir2 = 1.0 / r2;
+    double dr = 1.0 / sqrt(r2), di = 0.0;   // I_m^m
+    double phi = 0.0;
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const double f = (2 * m - 1) * ir2;
+            const double nr = f * (x * dr - y * di);
+            const double ni = f * (x * di + y * dr);
+            dr = nr;
+            di = ni;
+        }
+        const double wm = m == 0 ? 1.0 : 2.0;
+        double pr = 0.0, pi = 0.0, cr = dr, ci = di;
+        double acc = 0.0;
+        for (int n = m; n <= p; ++n) {
+            if (n > m) {
+                const double c2 = (double)((n - 1) * (n - 1) - m * m);
+                const double nr = ((2 * n - 1) * z * cr - c2 * pr) * ir2;
+                const double ni = ((2 * n - 1) * z * ci - c2 * pi) * ir2;
+                pr = cr; pi = ci; cr = nr; ci = ni;
+            }
+            const double2 a = M[tri(n, m)];
+            acc += a.x * cr - a.y * ci;
+        }
+        phi += wm * acc;
+    }
+    return phi;
+}
+
+constexpr int PT_MAX_ITEMS = 27 + 189 * TREE_MAX_LEVEL;   // far cells of one point, all levels
+
+// One wave per point (monitoring points and twins, centred coordinates):
+// the potential of every image in the 3x3x3 block, from the multipoles of
+// the point's far cells at every level and the images of its 27 neighbouring
+// leaf cells directly.  Far cells: at level 0 the boxes not adjacent to the
+// point's box (a point outside the central box has such boxes), at level
+// l >= 1 the children of the neighbours of the point's level-(l - 1) cell
+// that are not neighbours of its level-l cell.  The far cells are listed in
+// LDS first and then shared out over the lanes; the lane sums are combined
+// by a fixed butterfly.
+__global__ void __launch_bounds__(64)
+k_tree_points(const double4* __restrict__ pts, const double4* __restrict__ srt,
+              const int* __restrict__ offs, MomPtrs moms, int L, int p, double Lbox,
+              double* __restrict__ out) {
+    __shared__ int item_key[PT_MAX_ITEMS];
+    __shared__ char item_lev[PT_MAX_ITEMS];
+    const int lane = threadIdx.x;
+    const double4 P = pts[blockIdx.x];
+    const int GL = 3 << L;
+    const double hL = Lbox / (double)(1 << L);
+    int g[3];
+    const double v[3] = {P.x, P.y, P.z};
+    for (int a = 0; a < 3; ++a) {
+        const int c = (int)floor((v[a] + 1.5 * Lbox) / hL);
+        g[a] = c < 0 ? 0 : (c >= GL ? GL - 1 : c);
+    }
+    // list the far cells (every lane walks the same list and writes its share)
+    int nitem = 0;
+    {
+        const int bx = g[0] >> L, by = g[1] >> L, bz = g[2] >> L;
+        for (int cx = 0; cx < 3; ++cx)
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cz = 0; cz < 3; ++cz) {
+                    if (abs(cx - bx) <= 1 && abs(cy - by) <= 1 && abs(cz - bz) <= 1) continue;
+                    const uint32_t ck = (uint32_t)(cx * 9 + cy * 3 + cz);
+                    if (offs[(size_t)(ck + 1) << (3 * L)] == offs[(size_t)ck << (3 * L)]) continue;
+                    if (nitem % 64 == lane) { item_key[nitem] = (int)ck; item_lev[nitem] = 0; }
+                    ++nitem;
+                }
+    }
+    for (int l = 1; l <= L; ++l) {
+        const int G = 3 << l;
+        const int shift = 3 * (L - l);
+        const int tx = g[0] >> (L - l), ty = g[1] >> (L - l), tz = g[2] >> (L - l);
+        const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
+        for (int cx = 2 * px - 2; cx <= 2 * px + 3; ++cx) {
+            if (cx < 0 || cx >= G) continue;
+            for (int cy = 2 * py - 2; cy <= 2 * py + 3; ++cy) {
+                if (cy < 0 || cy >= G) continue;
+                for (int cz = 2 * pz - 2; cz <= 2 * pz + 3; ++cz) {
+                    if (cz < 0 || cz >= G) continue;
+                    if (abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1) continue;
+                    const uint32_t ck = cell_key(cx, cy, cz, l);
+                    if (offs[(size_t)(ck + 1) << shift] == offs[(size_t)ck << shift]) continue;
+                    if (nitem % 64 == lane) { item_key[nitem] = (int)ck; item_lev[nitem] = (char)l; }
+                    ++nitem;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int nc = tri(p + 1, 0);
+    double acc = 0.0;
+    for (int i = lane; i < nitem; i += 64) {
+        const int l = item_lev[i];
+        const uint32_t ck = (uint32_t)item_key[i];
+        // centre of cell ck of level l
+        const uint32_t box = ck >> (3 * l), mc = ck & ((1u << (3 * l)) - 1u);
+        uint32_t ix = 0, iy = 0, iz = 0;
+        for (int bb = 0; bb < l; ++bb) {
+            ix |= ((mc >> (3 * bb + 2)) & 1u) << bb;
+            iy |= ((mc >> (3 * bb + 1)) & 1u) << bb;
+            iz |= ((mc >> (3 * bb)) & 1u) << bb;
+        }
+        const double h = Lbox / (double)(1 << l);
+        const double cx = -1.5 * Lbox + ((double)((box / 9) * (1u << l) + ix) + 0.5) * h;
+        const double cy = -1.5 * Lbox + ((double)(((box / 3) % 3) * (1u << l) + iy) + 0.5) * h;
+        const double cz = -1.5 * Lbox + ((double)((box % 3) * (1u << l) + iz) + 0.5) * h;
+        acc += m2p_phi(moms.lev[l] + (size_t)ck * nc, p, P.x - cx, P.y - cy, P.z - cz);
+    }
+    // neighbouring leaf cells, directly
+    for (int cx = g[0] - 1; cx <= g[0] + 1; ++cx) {
+        if (cx < 0 || cx >= GL) continue;
+        for (int cy = g[1] - 1; cy <= g[1] + 1; ++cy) {
+            if (cy < 0 || cy >= GL) continue;
+            for (int cz = g[2] - 1; cz <= g[2] + 1; ++cz) {
+                if (cz < 0 || cz >= GL) continue;
+                const uint32_t ck = cell_key(cx, cy, cz, L);
+                const int e1 = offs[ck + 1];
+                for (int j = offs[ck] + lane; j < e1; j += 64) {
+                    const double4 r = srt[j];
+                    const double dx = P.x - r.x, dy = P.y - r.y, dz = P.z - r.z;
+                    acc += r.w / sqrt(dx * dx + dy * dy + dz * dz);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) out[blockIdx.x] = acc;
+}
+
 // ---------------------------------------------------------------- host
+// Work-groups per cell of the M2L at level l: enough that a level of few
+// cells (8^l) still spreads over the GPU.
+static int fmm_split(int l) {
+    const int cells = 1 << (3 * l);
+    return std::max(1, std::min(16, 2048 / cells));
+}
+
 int tree_leaf_level(int64_t ns) {
-    // about 32 sources per leaf cell of the central box
+    // at most tree_leaf_images() images per leaf cell (ns / 8^L: the 27 ns
+    // images fill the 27 boxes alike)
+    const double cap = tree_leaf_images();
     int L = 1;
-    while (L < TREE_MAX_LEVEL && (double)ns / (double)(1LL << (3 * L)) > 45.0) ++L;
+    while (L < TREE_MAX_LEVEL && (double)ns / (double)(1LL << (3 * L)) > cap) ++L;
     return L;
+}
+
+double tree_leaf_images() {
+    static const double v = [] {
+        const char* e = getenv("HSMA_TREE_LEAF");
+        const double d = e ? atof(e) : 0.0;
+        return d >= 1.0 ? d : 320.0;
+    }();
+    return v;
 }
 
 TreeLayout tree_layout(int64_t ns, int p) {
@@ -397,6 +760,8 @@ TreeLayout tree_layout(int64_t ns, int p) {
     t.ns = ns;
     t.nimg = 27 * ns;
     t.ncell_leaf = (int64_t)27 << (3 * t.L);
+    // enough evaluation work-groups to spread few leaf cells over the GPU
+    t.eval_split = std::max(1, std::min(27, 16384 >> (3 * t.L)));
     const int nc = tri(p + 1, 0);
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o = (o + b + 255) & ~(size_t)255; return r; };
@@ -407,17 +772,19 @@ TreeLayout tree_layout(int64_t ns, int p) {
     t.off_vals = take(sizeof(int) * (size_t)t.nimg);
     t.off_vals2 = take(sizeof(int) * (size_t)t.nimg);
     t.off_owner = take(sizeof(int) * (size_t)t.nimg);
-    t.off_cnt = take(sizeof(int) * (size_t)(t.ncell_leaf + 1));
     t.off_offs = take(sizeof(int) * (size_t)(t.ncell_leaf + 1));
-    for (int l = 1; l <= t.L; ++l) t.off_mom[l] = take(sizeof(double2) * (size_t)nc * ((size_t)27 << (3 * l)));
+    for (int l = 0; l <= t.L; ++l) t.off_mom[l] = take(sizeof(double2) * (size_t)nc * ((size_t)27 << (3 * l)));
+    for (int l = 1; l <= t.L; ++l) t.off_loc[l] = take(sizeof(double2) * (size_t)nc * ((size_t)1 << (3 * l)));
     t.off_tab = take(sizeof(double2) * 8 * (size_t)(p + 1) * (p + 1));
-    // hipCUB temporary storage of the sort and the scan
-    size_t sort_bytes = 0, scan_bytes = 0;
+    t.off_itab = take(sizeof(double2) * 343 * (size_t)(2 * p + 1) * (2 * p + 1));
+    size_t part_cells = 0;
+    for (int l = 1; l <= t.L; ++l) part_cells = std::max(part_cells, (size_t)fmm_split(l) << (3 * l));
+    t.off_part = take(sizeof(double2) * (size_t)nc * part_cells);
+    // hipCUB temporary storage of the sort
+    size_t sort_bytes = 0;
     hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
                                        (int*)nullptr, (int*)nullptr, (int)t.nimg, 0, 32);
-    hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int*)nullptr, (int*)nullptr,
-                                     (int)(t.ncell_leaf + 1));
-    t.cub_bytes = std::max(sort_bytes, scan_bytes);
+    t.cub_bytes = sort_bytes;
     t.off_cub = take(t.cub_bytes);
     t.total = o;
     return t;
@@ -460,9 +827,9 @@ __global__ void k_tree_m2m_table(int p, double2* __restrict__ tab) {
     }
 }
 
-hipError_t launch_tree_near(int img, const double4* src, int ns, int nt, double L, const TreeLayout& t,
-                            char* ws, double* out, int npad, hipStream_t s) {
-    if (ns <= 0 || nt <= 0) return hipSuccess;
+hipError_t launch_tree_build(int img, const double4* src, int ns, double L, const TreeLayout& t, char* ws,
+                             hipStream_t s) {
+    if (ns <= 0) return hipSuccess;
     if (t.p < 1 || t.p > TREE_MAX_ORDER || t.L < 1 || t.L > TREE_MAX_LEVEL) return hipErrorInvalidValue;
     double4* img4 = (double4*)(ws + t.off_img);
     double4* srt = (double4*)(ws + t.off_srt);
@@ -471,7 +838,6 @@ hipError_t launch_tree_near(int img, const double4* src, int ns, int nt, double 
     int* vals = (int*)(ws + t.off_vals);
     int* vals2 = (int*)(ws + t.off_vals2);
     int* owner = (int*)(ws + t.off_owner);
-    int* cnt = (int*)(ws + t.off_cnt);
     int* offs = (int*)(ws + t.off_offs);
     const int64_t n = t.nimg;
     hipLaunchKernelGGL(k_tree_images, dim3((ns + 255) / 256, 27), dim3(256), 0, s, src, ns, img, L, t.L,
@@ -483,32 +849,59 @@ hipError_t launch_tree_near(int img, const double4* src, int ns, int nt, double 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tree_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, img4, vals2,
                        n, ns, srt, owner);
-    hipLaunchKernelGGL(k_tree_zero_int, dim3(1024), dim3(256), 0, s, cnt, t.ncell_leaf + 1);
-    hipLaunchKernelGGL(k_tree_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys2, n, cnt);
-    cub = t.cub_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(ws + t.off_cub, cub, cnt, offs, (int)(t.ncell_leaf + 1), s);
-    if (e != hipSuccess) return e;
-    // moments: leaf level directly, coarser levels by translation
+    hipLaunchKernelGGL(k_tree_offsets, dim3((unsigned)((t.ncell_leaf + 1 + 255) / 256)), dim3(256), 0, s, keys2,
+                       n, t.ncell_leaf, offs);
+    // multipoles: leaf level directly, coarser levels (down to the 27 boxes
+    // of level 0) by translation
     const int nc = tri(t.p + 1, 0);
-    double2* mom[TREE_MAX_LEVEL + 1] = {};
-    for (int l = 1; l <= t.L; ++l) mom[l] = (double2*)(ws + t.off_mom[l]);
-    {
-        const int64_t threads = t.ncell_leaf * (t.p + 1);
-        hipLaunchKernelGGL(k_tree_p2m, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, srt, offs,
-                           t.L, (int)t.ncell_leaf, t.p, L, mom[t.L]);
-    }
+    hipLaunchKernelGGL(k_tree_p2m, dim3((unsigned)((t.ncell_leaf + 63) / 64), t.p + 1), dim3(64), 0, s, srt,
+                       offs, t.L, (int)t.ncell_leaf, t.p, L, (double2*)(ws + t.off_mom[t.L]));
     double2* dtab = (double2*)(ws + t.off_tab);
     hipLaunchKernelGGL(k_tree_m2m_table, dim3(1), dim3(64), 0, s, t.p, dtab);
-    for (int l = t.L - 1; l >= 1; --l) {
+    for (int l = t.L - 1; l >= 0; --l) {
         const int64_t ncell = (int64_t)27 << (3 * l);
         const int64_t threads = ncell * nc;
-        hipLaunchKernelGGL(k_tree_m2m, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, mom[l + 1],
-                           offs, l, t.L, (int)ncell, t.p, L / (double)(1 << l), dtab, mom[l]);
+        hipLaunchKernelGGL(k_tree_m2m, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                           (const double2*)(ws + t.off_mom[l + 1]), offs, l, t.L, (int)ncell, t.p,
+                           L / (double)(1 << l), dtab, (double2*)(ws + t.off_mom[l]));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_points(const double4* pts, int npts, double L, const TreeLayout& t, char* ws,
+                              double* out, hipStream_t s) {
+    if (npts <= 0) return hipSuccess;
     MomPtrs mp;
-    for (int l = 0; l <= TREE_MAX_LEVEL; ++l) mp.lev[l] = mom[l];
-    hipLaunchKernelGGL(k_tree_eval, dim3(1u << (3 * t.L)), dim3(TWG), 0, s, srt, owner, offs, mp, t.L,
-                       t.p, L, nt, out, npad);
+    for (int l = 0; l <= TREE_MAX_LEVEL; ++l)
+        mp.lev[l] = l <= t.L ? (const double2*)(ws + t.off_mom[l]) : nullptr;
+    hipLaunchKernelGGL(k_tree_points, dim3(npts), dim3(64), 0, s, pts, (const double4*)(ws + t.off_srt),
+                       (const int*)(ws + t.off_offs), mp, t.L, t.p, L, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_near(int nt, double L, const TreeLayout& t, char* ws, double* out, int npad,
+                            hipStream_t s) {
+    if (nt <= 0) return hipSuccess;
+    const int* offs = (const int*)(ws + t.off_offs);
+    const double2* dtab = (const double2*)(ws + t.off_tab);
+    // local expansions of the central box, level by level
+    double2* itab = (double2*)(ws + t.off_itab);
+    hipLaunchKernelGGL(k_fmm_itab, dim3(2), dim3(256), 0, s, 2 * t.p, itab);
+    double2* part = (double2*)(ws + t.off_part);
+    for (int l = 1; l <= t.L; ++l) {
+        double2* loc = (double2*)(ws + t.off_loc[l]);
+        const double2* ploc = l >= 2 ? (const double2*)(ws + t.off_loc[l - 1]) : nullptr;
+        const int G = fmm_split(l);
+        const size_t lds = sizeof(double2) * ((size_t)(t.p + 1) * (t.p + 1) + (size_t)(2 * t.p + 1) * (2 * t.p + 1)) +
+                           sizeof(double) * (t.p + 1);
+        hipLaunchKernelGGL(k_fmm_m2l, dim3(1u << (3 * l), G), dim3(FWG), lds, s,
+                           (const double2*)(ws + t.off_mom[l]), offs, l, t.L, t.p, L, itab, G, part);
+        hipLaunchKernelGGL(k_fmm_l2l, dim3(1u << (3 * l)), dim3(FWG), 0, s, part, G, l, t.p, L, dtab, ploc,
+                           loc);
+    }
+    hipLaunchKernelGGL(k_tree_eval, dim3(1u << (3 * t.L), t.eval_split), dim3(TWG), 0, s,
+                       (const double4*)(ws + t.off_srt), (const int*)(ws + t.off_owner), offs,
+                       (const double2*)(ws + t.off_loc[t.L]), t.L, t.p, L, nt, out, npad);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
-"""The tree-code near sum (HSMA_NEAR_TREE) against the oracle's direct near sum
-over the 3x3x3 image block: element-wise at every particle for small systems,
-on sampled particles at 1e5 and 1e6, for the periodic cube, the grounded cube
-and the slab, in double precision."""
+"""The fast-multipole near sum (HSMA_NEAR_TREE) against the oracle's direct
+near sum over the 3x3x3 image block: element-wise at every particle for small
+systems, on sampled particles at 1e5 and 1e6, for the periodic cube, the
+grounded cube and the slab, in double precision."""
 import time
 
 import numpy as np
@@ -14,9 +14,17 @@ from paper_1806_04801_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-# tolerances of the tree near sum at multipole order 14, relative to the rms
-# near potential, the largest near field and 1/2 sum |q phi_near|
+# tolerances of the near sum at the default expansion order 16, relative to
+# the rms near potential, the largest near field and 1/2 sum |q phi_near|;
+# the right-hand side (potential of all images at the monitoring points and
+# twins, from the same tree) relative to its largest entry.  On the faces of
+# the grounded cube every charge and its mirror image cancel, so b is a small
+# remainder of the image potentials and the tree's error (set by the far
+# cells' potentials) is larger relative to it: measured 8e-6 to 3e-5 there,
+# against 1e-7 to 3e-7 at the circumsphere points of the periodic cube and
+# the slab.
 TOL_PHI, TOL_E, TOL_EN = 5e-6, 1e-6, 1e-7
+TOL_B = {0: 1e-6, 1: 1e-4, 2: 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -34,11 +42,21 @@ def system(bc, n, seed):
     return W.uniform_neutral(n, 1.0, seed)
 
 
-def near_parts(hs, plan, x, q):
+def near_parts(hs, plan, x, q, with_b=False):
     e, phi, F, inter = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"),
                                           intermediates=True)
     torch.cuda.synchronize()
-    return e, inter["phi_near"].cpu().numpy(), inter["field_near"].cpu().numpy()
+    out = (e, inter["phi_near"].cpu().numpy(), inter["field_near"].cpu().numpy())
+    return out + (inter["b"].cpu().numpy(),) if with_b else out
+
+
+def rhs_error(hs, bc, x, q, b_tree):
+    """The tree's right-hand side against the direct kernels' (same plan)."""
+    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7)
+    e, phi, F, inter = plan.energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"),
+                                          intermediates=True)
+    b = inter["b"].cpu().numpy()
+    return float(np.max(np.abs(b_tree - b)) / np.max(np.abs(b)))
 
 
 def direct_near(bc, x, q, idx):
@@ -47,7 +65,7 @@ def direct_near(bc, x, q, idx):
     return r["phi_near"], r["field_near"]
 
 
-def check(tag, q, idx, pn, fn, ref_p, ref_f, order=14):
+def check(tag, q, idx, pn, fn, ref_p, ref_f, order=16):
     errs = dict(phi=rel_max(pn[idx], ref_p, rms(ref_p)), E=rel_max(fn[idx], ref_f),
                 En=abs(0.5 * np.sum(q[idx] * (pn[idx] - ref_p))) / (0.5 * np.sum(np.abs(q[idx] * ref_p))))
     print("tree %s order %d: %s" % (tag, order, " ".join("%s %.2e" % kv for kv in errs.items())))
@@ -59,12 +77,15 @@ def test_tree_near_sum_vs_direct_every_particle(hs, bc, n):
     announce("tree near bc=%d n=%d" % (bc, n))
     x, q = system(bc, n, 50 + n)
     plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
-    assert plan.info["tree_order"] == 14
-    _, pn, fn = near_parts(hs, plan, x, q)
+    assert plan.info["tree_order"] == 16
+    _, pn, fn, b = near_parts(hs, plan, x, q, with_b=True)
     idx = np.arange(n)
     ref_p, ref_f = direct_near(bc, x, q, idx)
     e = check("bc=%d n=%d" % (bc, n), q, idx, pn, fn, ref_p, ref_f)
+    eb = rhs_error(hs, bc, x, q, b)
+    print("tree bc=%d n=%d rhs %.2e" % (bc, n, eb))
     assert e["phi"] <= TOL_PHI and e["E"] <= TOL_E and e["En"] <= TOL_EN
+    assert eb <= TOL_B[bc]
 
 
 def test_tree_order_controls_the_error(hs):
@@ -74,7 +95,7 @@ def test_tree_order_controls_the_error(hs):
     idx = np.arange(0, 4000, 7)
     ref_p, ref_f = direct_near(0, x, q, idx)
     errs = []
-    for order in (6, 10, 14):
+    for order in (8, 12, 16):
         plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=order)
         _, pn, fn = near_parts(hs, plan, x, q)
         errs.append(check("order sweep", q, idx, pn, fn, ref_p, ref_f, order))
@@ -89,26 +110,34 @@ def test_tree_near_sum_sampled_at_size(hs, bc, n, ns):
     plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
     near_parts(hs, plan, x, q)   # warm
     t0 = time.perf_counter()
-    e, pn, fn = near_parts(hs, plan, x, q)
+    e, pn, fn, b = near_parts(hs, plan, x, q, with_b=True)
     dt = time.perf_counter() - t0
     idx = np.sort(np.random.default_rng(5).choice(n, ns, replace=False))
     ref_p, ref_f = direct_near(bc, x, q, idx)
     errs = check("bc=%d n=%d (%.1f ms per step)" % (bc, n, 1e3 * dt), q, idx, pn, fn, ref_p, ref_f)
+    eb = rhs_error(hs, bc, x, q, b)
+    print("tree bc=%d n=%d rhs %.2e" % (bc, n, eb))
     assert errs["phi"] <= TOL_PHI and errs["E"] <= TOL_E and errs["En"] <= TOL_EN
+    assert eb <= TOL_B[bc]
 
 
-def test_tree_whole_step_vs_direct_step(hs):
-    """The whole update step with the tree near sum against the direct
-    (pair-once) step: energy, potentials and forces to the tree's tolerance."""
-    announce("tree whole step")
-    x, q = W.uniform_neutral(10000, 1.0, 91)
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_tree_whole_step_vs_direct_step(hs, bc):
+    """The whole update step in tree mode (near sum and right-hand side from
+    the tree) against the direct (pair-once) step: energy, potentials and
+    forces to the tree's tolerance."""
+    announce("tree whole step bc=%d" % bc)
+    x, q = system(bc, 10000, 91)
     xd, qd = torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda")
-    p_tree = hs.Plan(1.0, 0, 12, 1440, 1440, 2.7, near_mode=hs.NEAR_TREE)
-    p_dir = hs.Plan(1.0, 0, 12, 1440, 1440, 2.7)
+    p_tree = hs.Plan(1.0, bc, 12, 1440, 1440, 2.7, near_mode=hs.NEAR_TREE)
+    p_dir = hs.Plan(1.0, bc, 12, 1440, 1440, 2.7)
     e1, phi1, F1 = p_tree.energy_forces(xd, qd)
     e0, phi0, F0 = p_dir.energy_forces(xd, qd)
     phi0, phi1 = phi0.cpu().numpy(), phi1.cpu().numpy()
     scale = 0.5 * np.sum(np.abs(q * phi0))
+    print("tree whole step bc=%d: dE/scale %.2e dE/E %.2e phi %.2e F %.2e" % (
+        bc, abs(e1 - e0) / scale, abs(e1 - e0) / abs(e0), rel_max(phi1, phi0, rms(phi0)),
+        rel_max(F1.cpu().numpy(), F0.cpu().numpy())))
     assert abs(e1 - e0) <= TOL_EN * scale
     assert rel_max(phi1, phi0, rms(phi0)) <= TOL_PHI
     assert rel_max(F1.cpu().numpy(), F0.cpu().numpy()) <= TOL_E
