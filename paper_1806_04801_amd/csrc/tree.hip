@@ -146,14 +146,99 @@ __global__ void k_tree_offsets(const uint32_t* __restrict__ keys, int64_t n, int
 }
 
 // ---------------------------------------------------------------- leaf moments
-// Thread (cell, m), m = blockIdx.y uniform over the wave: column m of the
-// moments of leaf cell `cell`, summed over its sources in sorted order.  The
-// loops over n are unrolled to the largest order (guards n <= p are uniform),
-// so the accumulators stay in registers; the recurrence's reciprocals depend
-// on (n, m) only and are formed once per thread.
+// For few leaf cells: one wave per leaf cell, a lane per image (the cell's
+// images in turns of 64): for each column m in turn every lane accumulates q
+// conj(R_n^m) of its images, n = m..p, then the lanes' sums are combined by a
+// fixed butterfly. The loops over n are unrolled to the largest order (guards
+// uniform), so the accumulators stay in registers; the recurrence's
+// reciprocals depend on (n, m) only.  The lanes read consecutive images, and a
+// cell's images are re-read from cache for every m.
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __global__ void __launch_bounds__(64)
-k_tree_p2m(const double4* __restrict__ srt, const int* __restrict__ offs, int lev, int ncell, int p,
-           double L, double2* __restrict__ mom) {
+k_tree_p2m_wave(const double4* __restrict__ srt, const int* __restrict__ offs, int lev, int p, double L,
+                double2* __restrict__ mom) {
+    const int64_t cell = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int b = offs[cell], e = offs[cell + 1];
+    double2* out = mom + (size_t)cell * tri(p + 1, 0);
+    if (b == e) {
+        for (int idx = lane; idx < tri(p + 1, 0); idx += 64) out[idx] = make_double2(0.0, 0.0);
+        return;
+    }
+    // cell centre from its key: box index and Morton code within the box
+    const uint32_t key = (uint32_t)cell;
+    const uint32_t box = key >> (3 * lev), mc = key & ((1u << (3 * lev)) - 1u);
+    uint32_t ix = 0, iy = 0, iz = 0;
+    for (int bb = 0; bb < lev; ++bb) {
+        ix |= ((mc >> (3 * bb + 2)) & 1u) << bb;
+        iy |= ((mc >> (3 * bb + 1)) & 1u) << bb;
+        iz |= ((mc >> (3 * bb)) & 1u) << bb;
+    }
+    const double h = L / (double)(1 << lev);
+    const double cx = -1.5 * L + ((double)((box / 9) * (1u << lev) + ix) + 0.5) * h;
+    const double cy = -1.5 * L + ((double)(((box / 3) % 3) * (1u << lev) + iy) + 0.5) * h;
+    const double cz = -1.5 * L + ((double)((box % 3) * (1u << lev) + iz) + 0.5) * h;
+    constexpr int P = TREE_MAX_ORDER;
+    for (int m = 0; m <= p; ++m) {
+        double ar[P + 1], ai[P + 1], rinv[P + 1];
+#pragma unroll
+        for (int n = 0; n <= P; ++n) {
+            ar[n] = ai[n] = 0.0;
+            rinv[n] = (n > m) ? 1.0 / ((double)(n + m) * (double)(n - m)) : 0.0;
+        }
+        for (int s = b + lane; s < e; s += 64) {
+            const double4 y = srt[s];
+            const double x = y.x - cx, yy = y.y - cy, z = y.z - cz;
+            const double r2 = x * x + yy * yy + z * z;
+            // R_m^m = (x + iy)^m / (2^m m!)
+            double dr = 1.0, di = 0.0;
+#pragma unroll
+            for (int k = 1; k <= P; ++k) {
+                if (k <= m) {
+                    const double c = 0.5 / (double)k;
+                    const double nr = (dr * x - di * yy) * c;
+                    const double ni = (dr * yy + di * x) * c;
+                    dr = nr;
+                    di = ni;
+                }
+            }
+            double pr = 0.0, pi = 0.0, cr = dr, ci = di;   // R_{n-2}, R_{n-1}
+#pragma unroll
+            for (int n = 0; n <= P; ++n) {
+                if (n < m || n > p) continue;
+                if (n > m) {
+                    const double nr = ((2 * n - 1) * z * cr - r2 * pr) * rinv[n];
+                    const double ni = ((2 * n - 1) * z * ci - r2 * pi) * rinv[n];
+                    pr = cr; pi = ci; cr = nr; ci = ni;
+                }
+                // M += q conj(R)
+                ar[n] = __builtin_fma(y.w, cr, ar[n]);
+                ai[n] = __builtin_fma(-y.w, ci, ai[n]);
+            }
+        }
+#pragma unroll
+        for (int n = 0; n <= P; ++n) {
+            if (n < m || n > p) continue;
+            const double vr = wave_sum64(ar[n]);
+            const double vi = wave_sum64(ai[n]);
+            if (lane == 0) out[tri(n, m)] = make_double2(vr, vi);
+        }
+    }
+}
+
+// For many leaf cells: thread (cell, m), m = blockIdx.y uniform over the wave:
+// column m of the moments of leaf cell `cell`, summed over its sources in
+// sorted order.  The loops over n are unrolled to the largest order (guards n
+// <= p are uniform), so the accumulators stay in registers; the recurrence's
+// reciprocals depend on (n, m) only and are formed once per thread.
+__global__ void __launch_bounds__(64)
+k_tree_p2m_cols(const double4* __restrict__ srt, const int* __restrict__ offs, int lev, int ncell, int p,
+                double L, double2* __restrict__ mom) {
     const int m = blockIdx.y;
     const int64_t cell = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (cell >= ncell || m > p) return;
@@ -217,14 +302,74 @@ k_tree_p2m(const double4* __restrict__ srt, const int* __restrict__ offs, int le
 }
 
 // ---------------------------------------------------------------- translation
-// Thread (parent cell, n, m >= 0) of level l: the moment M_n^m of the parent
-// from its 8 children at level l + 1 (children with no source skipped).
-// tab holds conj(R~_j^k(d_o)) of the 8 child offsets d_o (per axis +-1/4 of
-// the parent's side, octant o = Morton digit) for the unit side, 8 x (p+1)^2
-// entries (index j*j + j + k), scaled here by side^j.
-__global__ void k_tree_m2m(const double2* __restrict__ child, const int* __restrict__ offs, int l,
-                           int L, int ncell, int p, double side, const double2* __restrict__ tab,
-                           double2* __restrict__ parent) {
+// For few parents: a work-group per parent cell of level l, a thread per
+// moment M_n^m (m >= 0) of the parent, from its 8 children at level l + 1
+// (children with no source skipped), whose moments are staged in LDS in the
+// full signed layout.  tab holds conj(R~_j^k(d_o)) of the 8 child offsets d_o
+// (per axis +-1/4 of the parent's side, octant o = Morton digit) for the unit
+// side, 8 x (p+1)^2 entries (index j*j + j + k), scaled here by side^j.
+__global__ void __launch_bounds__(256)
+k_tree_m2m_group(const double2* __restrict__ child, const int* __restrict__ offs, int l, int L, int p,
+                 double side, const double2* __restrict__ tab, double2* __restrict__ parent) {
+    extern __shared__ double2 Ct[];   // 8 (p+1)^2
+    __shared__ int full[8];
+    const int nc = tri(p + 1, 0);
+    const int nf = (p + 1) * (p + 1);
+    const int64_t cell = blockIdx.x;
+    const int t = threadIdx.x;
+    const int shift = 3 * (L - l - 1);
+    if (t < 8) {
+        const int64_t c = cell * 8 + t;
+        full[t] = offs[(c + 1) << shift] != offs[c << shift];
+    }
+    for (int idx = t; idx < 8 * nf; idx += 256) {
+        const int o = idx / nf, r = idx - o * nf;
+        int n = 0;
+        while ((n + 1) * (n + 1) <= r) ++n;
+        const int m = r - n * n - n;
+        double2 v = child[(size_t)(cell * 8 + o) * nc + tri(n, m < 0 ? -m : m)];
+        if (m < 0) {
+            v.y = -v.y;
+            if ((-m) & 1) { v.x = -v.x; v.y = -v.y; }
+        }
+        Ct[idx] = v;
+    }
+    __syncthreads();
+    if (t >= nc) return;
+    int n = 0;
+    while (tri(n + 1, 0) <= t) ++n;
+    const int m = t - tri(n, 0);
+    double sr = 0.0, si = 0.0;
+    for (int o = 0; o < 8; ++o) {
+        if (!full[o]) continue;
+        const double2* M = Ct + (size_t)o * nf;
+        const double2* T = tab + (size_t)o * nf;
+        double sj = 1.0;
+        for (int j = 0; j <= n; ++j) {
+            const int nn = n - j;
+            for (int k = -j; k <= j; ++k) {
+                const int mm = m - k;
+                if (mm > nn || -mm > nn) continue;
+                const double2 a = T[j * j + j + k];
+                const double2 bb = M[nn * nn + nn + mm];
+                const double ar = a.x * sj, ai = a.y * sj;
+                sr += ar * bb.x - ai * bb.y;
+                si += ar * bb.y + ai * bb.x;
+            }
+            sj *= side;
+        }
+    }
+    parent[(size_t)cell * nc + t] = make_double2(sr, si);
+}
+
+// For many parents: thread (parent cell, n, m >= 0) of level l: the moment
+// M_n^m of the parent from its 8 children at level l + 1 (children with no
+// source skipped). tab holds conj(R~_j^k(d_o)) of the 8 child offsets d_o (per
+// axis +-1/4 of the parent's side, octant o = Morton digit) for the unit side,
+// 8 x (p+1)^2 entries (index j*j + j + k), scaled here by side^j.
+__global__ void k_tree_m2m_coef(const double2* __restrict__ child, const int* __restrict__ offs, int l,
+                                int L, int ncell, int p, double side, const double2* __restrict__ tab,
+                                double2* __restrict__ parent) {
     const int nt = tri(p + 1, 0);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = t / nt;
@@ -853,17 +998,31 @@ hipError_t launch_tree_build(int img, const double4* src, int ns, double L, cons
                        n, t.ncell_leaf, offs);
     // multipoles: leaf level directly, coarser levels (down to the 27 boxes
     // of level 0) by translation
-    const int nc = tri(t.p + 1, 0);
-    hipLaunchKernelGGL(k_tree_p2m, dim3((unsigned)((t.ncell_leaf + 63) / 64), t.p + 1), dim3(64), 0, s, srt,
-                       offs, t.L, (int)t.ncell_leaf, t.p, L, (double2*)(ws + t.off_mom[t.L]));
+    // leaf multipoles: a wave per cell while the cells are few, a thread per
+    // (cell, m) for many (measured faster at each end)
+    if (t.ncell_leaf <= 32768)
+        hipLaunchKernelGGL(k_tree_p2m_wave, dim3((unsigned)t.ncell_leaf), dim3(64), 0, s, srt, offs, t.L, t.p,
+                           L, (double2*)(ws + t.off_mom[t.L]));
+    else
+        hipLaunchKernelGGL(k_tree_p2m_cols, dim3((unsigned)((t.ncell_leaf + 63) / 64), t.p + 1), dim3(64), 0, s,
+                           srt, offs, t.L, (int)t.ncell_leaf, t.p, L, (double2*)(ws + t.off_mom[t.L]));
     double2* dtab = (double2*)(ws + t.off_tab);
     hipLaunchKernelGGL(k_tree_m2m_table, dim3(1), dim3(64), 0, s, t.p, dtab);
+    const size_t lds_m2m = sizeof(double2) * 8 * (size_t)(t.p + 1) * (t.p + 1);
+    const int nc = tri(t.p + 1, 0);
     for (int l = t.L - 1; l >= 0; --l) {
+        // a work-group per parent while the parents are few, a thread per
+        // coefficient for many (measured faster at each end)
         const int64_t ncell = (int64_t)27 << (3 * l);
-        const int64_t threads = ncell * nc;
-        hipLaunchKernelGGL(k_tree_m2m, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                           (const double2*)(ws + t.off_mom[l + 1]), offs, l, t.L, (int)ncell, t.p,
-                           L / (double)(1 << l), dtab, (double2*)(ws + t.off_mom[l]));
+        const double side = L / (double)(1 << l);
+        if (ncell <= 512)
+            hipLaunchKernelGGL(k_tree_m2m_group, dim3((unsigned)ncell), dim3(256), lds_m2m, s,
+                               (const double2*)(ws + t.off_mom[l + 1]), offs, l, t.L, t.p, side, dtab,
+                               (double2*)(ws + t.off_mom[l]));
+        else
+            hipLaunchKernelGGL(k_tree_m2m_coef, dim3((unsigned)((ncell * nc + 255) / 256)), dim3(256), 0, s,
+                               (const double2*)(ws + t.off_mom[l + 1]), offs, l, t.L, (int)ncell, t.p, side, dtab,
+                               (double2*)(ws + t.off_mom[l]));
     }
     return hipGetLastError();
 }
