@@ -251,10 +251,11 @@ def serving_measure(n_requests, refine, log=sys.stderr):
     """Serving stream (seeded trace): N log-uniform in [1e3, 1e5] (even),
     periodic or grounded cube with probability 1/2, p in {12, 16, 20},
     K = M = 10 p^2, R = 2.7L.  Closed loop (all requests at t = 0) gives
-    solves/s of five paths: the served path (batched FP32-comp with
-    ill-conditioned energies refined in FP64), and the batched server and one
-    solve per request, each in FP32-comp and in FP64 without refinement
-    (equal-precision comparisons).  Open loop
+    solves/s of six paths: the served path (batched FP32-comp with
+    ill-conditioned energies refined in FP64), the same with tree plans
+    (requests of 32768 particles and more on the fast multipole method), and
+    the batched server and one solve per request, each in FP32-comp and in
+    FP64 without refinement (equal-precision comparisons).  Open loop
     (Poisson arrivals at 0.8 of a path's closed-loop rate) gives p50/p99
     latency.  Energies of the FP32 paths are compared with the FP64
     per-request path."""
@@ -270,12 +271,16 @@ def serving_measure(n_requests, refine, log=sys.stderr):
         for bc in (0, 1):
             for p in (12, 16, 20):
                 plans[(prec, bc, p)] = hsma.Plan(1.0, bc, p, 10 * p * p, 10 * p * p, 2.7, precision=prec)
+    for bc in (0, 1):
+        for p in (12, 16, 20):
+            plans[("fmm", bc, p)] = hsma.Plan(1.0, bc, p, 10 * p * p, 10 * p * p, 2.7, precision=hsma.FP32_COMP,
+                                              near_mode=hsma.NEAR_TREE)
     xs, qs = [], []
     for r in trace:
         x, q = workloads.uniform_neutral(r["n"], 1.0, seed=r["seed"])
         xs.append(x)
         qs.append(q)
-    pl = {prec: [plans[(prec, r["bc"], r["p"])] for r in trace] for prec in (hsma.FP64, hsma.FP32_COMP)}
+    pl = {prec: [plans[(prec, r["bc"], r["p"])] for r in trace] for prec in (hsma.FP64, hsma.FP32_COMP, "fmm")}
     n = len(trace)
     pairs = 0.0
     for r in trace:
@@ -285,18 +290,23 @@ def serving_measure(n_requests, refine, log=sys.stderr):
     # double precision), and the batched paths at one precision each
     srv = {"served": hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
                                  refine_below=refine),
+           "fmm": hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
+                              refine_below=refine),
            hsma.FP32_COMP: hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP32_COMP,
                                        refine_below=0.0),
            hsma.FP64: hsma.Server(memory_bytes=16 << 30, max_active=64, precision=hsma.FP64)}
     zero = np.zeros(n)
     k = min(8, n)
-    for key, prec in (("served", hsma.FP32_COMP), (hsma.FP32_COMP, hsma.FP32_COMP), (hsma.FP64, hsma.FP64)):
+    for key, prec in (("served", hsma.FP32_COMP), ("fmm", "fmm"), (hsma.FP32_COMP, hsma.FP32_COMP),
+                      (hsma.FP64, hsma.FP64)):
         srv[key].run_trace(zero[:k], pl[prec][:k], xs[:k], qs[:k])   # warm-up of every path
         hsma.run_trace_sequential(zero[:k], pl[prec][:k], xs[:k], qs[:k])
     closed = {}
     energies = {}
     refined0 = srv["served"].stats()["refined"]
+    refined0_fmm = srv["fmm"].stats()["refined"]
     for name, prec, key in (("served_fp32_refined", hsma.FP32_COMP, "served"),
+                            ("served_fmm_refined", "fmm", "fmm"),
                             ("sequential_fp64", hsma.FP64, None),
                             ("batched_fp32", hsma.FP32_COMP, hsma.FP32_COMP),
                             ("sequential_fp32", hsma.FP32_COMP, None),
@@ -310,11 +320,15 @@ def serving_measure(n_requests, refine, log=sys.stderr):
         energies[name] = e
         if name == "served_fp32_refined":
             refined = srv["served"].stats()["refined"] - refined0
+        if name == "served_fmm_refined":
+            refined_fmm = srv["fmm"].stats()["refined"] - refined0_fmm
     mu32, mu64 = closed["served_fp32_refined"], closed["sequential_fp64"]
     gaps = np.random.default_rng(44).exponential(1.0, n)
     pct = lambda a, q_: float(np.percentile(a, q_)) * 1e3
     lat = {}
+    mufmm = closed["served_fmm_refined"]
     for name, rate_of, prec, key in (("served_fp32_at_0.8_own", mu32, hsma.FP32_COMP, "served"),
+                                     ("served_fmm_at_0.8_own", mufmm, "fmm", "fmm"),
                                      ("sequential_fp64_at_0.8_own", mu64, hsma.FP64, None),
                                      ("served_fp32_at_0.8_fp64_sequential", mu64, hsma.FP32_COMP, "served")):
         print("serving: open loop, %s" % name, file=log, flush=True)
@@ -326,7 +340,8 @@ def serving_measure(n_requests, refine, log=sys.stderr):
         lat[name] = {"p50_ms": pct(l_, 50), "p99_ms": pct(l_, 99), "offered_per_s": 0.8 * rate_of}
     e64 = energies["sequential_fp64"]
     err = {}
-    for name in ("served_fp32_refined", "batched_fp32", "sequential_fp32", "batched_fp64"):
+    for name in ("served_fp32_refined", "served_fmm_refined", "batched_fp32", "sequential_fp32",
+                 "batched_fp64"):
         rel = np.abs(energies[name] - e64) / np.abs(e64)
         err[name] = {"p50": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
                      "max": float(rel.max()), "frac_le_1e-5": float(np.mean(rel <= 1e-5))}
@@ -343,9 +358,13 @@ def serving_measure(n_requests, refine, log=sys.stderr):
         # the served single-precision path (every energy within 1e-5) against
         # the plain double-precision path
         "gain_served_fp32_vs_sequential_fp64": mu32 / mu64,
+        # the served path with tree plans (fast multipole method from 32768
+        # particles on, same refinement) against the plain double-precision path
+        "gain_served_fmm_vs_sequential_fp64": mufmm / mu64,
         "latency": lat,
         "refine_below": refine,
         "refined_in_fp64": {"requests": int(refined), "fraction": refined / n},
+        "refined_in_fp64_fmm_path": {"requests": int(refined_fmm), "fraction": refined_fmm / n},
         "rel_energy_err_vs_sequential_fp64": err,
     }
 

@@ -66,14 +66,16 @@ typedef enum {
     HSMA_NEAR_SPHERE = 1,  /* near set: every image inside the auxiliary sphere |r| < R_s (the
                               paper's literal near set, Sec. II.A); images generated per call;
                               no adjoint and no serving in this mode */
-    HSMA_NEAR_TREE = 2     /* near set of HSMA_NEAR_BLOCK, summed by the fast multipole method
-                              instead of directly (the O(N) acceleration of the near sum,
-                              Sec. II.C, Table I): multipole and local expansions of order
-                              hsma_plan_desc.tree_order about the cells of a uniform octree over
-                              the 27 boxes (at most HSMA_TREE_LEAF images per leaf cell, 320 by
-                              default), direct sums between neighbouring leaf cells; double
-                              precision; periodic, grounded cube and slab; no adjoint and no
-                              serving in this mode */
+    HSMA_NEAR_TREE = 2     /* near set of HSMA_NEAR_BLOCK; from hsma_plan_desc.tree_min_n
+                              particles on, the near sum and the right-hand side are summed by
+                              the fast multipole method instead of directly (the O(N)
+                              acceleration of Sec. II.C, Table I): multipole and local
+                              expansions of order hsma_plan_desc.tree_order about the cells of a
+                              uniform octree over the 27 boxes (at most HSMA_TREE_LEAF images
+                              per leaf cell, 320 by default), direct sums between neighbouring
+                              leaf cells, in double precision whatever the plan's precision;
+                              below tree_min_n the direct kernels of HSMA_NEAR_BLOCK in the
+                              plan's precision; periodic, grounded cube and slab; no adjoint */
 } hsma_near_mode;
 
 typedef enum {
@@ -128,6 +130,10 @@ typedef struct {
                           2 <= max_a |k_a| <= S; 0 picks the smallest S whose omitted tail is
                           below 1e-13 sum|q|/L at the monitoring points */
     int tree_order;    /* HSMA_NEAR_TREE: expansion order, 1..20 (0 selects 16) */
+    int tree_min_n;    /* HSMA_NEAR_TREE: the fast multipole method from this many particles
+                          on, >= 1 (0 selects 16384 for HSMA_FP64 plans and 32768 for
+                          HSMA_FP32_COMP plans, near the measured crossovers with the direct
+                          double- and single-precision near sums) */
 } hsma_plan_desc;
 
 typedef struct {
@@ -150,6 +156,7 @@ typedef struct {
     double gamma;      /* dielectric box: image weight */
     int far_shells;    /* dielectric box: far image shells in use */
     int tree_order;    /* tree near sum: multipole order in use */
+    int tree_min_n;    /* tree near sum: used from this many particles on */
 } hsma_plan_info_t;
 
 /* Optional device outputs of the intermediate stages (any pointer may be NULL). */
@@ -229,7 +236,9 @@ size_t hsma_workspace_bytes(hsma_plan plan, int64_t N);
  *           pair is split into `slices` row slices of 64 * rows_per_lane rows
  *           and `parts` column parts, one wave each; `launches` counts every
  *           kernel launch of the sum.
- * Fields other than kind are 0 for kind 0.  Returns HSMA_E_INVALID for a NULL
+ *   kind 2: the fast multipole method (HSMA_NEAR_TREE plans from tree_min_n
+ *           particles on).
+ * Fields other than kind are 0 for kinds 0 and 2.  Returns HSMA_E_INVALID for a NULL
  * plan or output, or N < 1.
  */
 typedef struct {
@@ -363,10 +372,12 @@ typedef struct {
     size_t memory_bytes;   /* device arena for admitted requests (>= 1 MiB) */
     int max_active;        /* request slots (>= 1) */
     int precision;         /* hsma_precision of the pair sums */
-    double refine_below;   /* HSMA_FP32_COMP only (0 = off): a request whose
+    double refine_below;   /* 0 = off; applies to the requests of an
+                              HSMA_FP32_COMP server and to the requests on the
+                              fast multipole method of either: a request whose
                               energy E comes out with |E| below refine_below
-                              times 1/2 sum |q_i phi_i| is recomputed in double
-                              precision before it completes.  The single-
+                              times 1/2 sum |q_i phi_i| is recomputed with the
+                              direct double-precision sums before it completes.  The single-
                               precision error is a small fraction (~4e-9) of
                               that sum, so it is a large relative error only
                               when E is a small difference of large terms;
@@ -387,7 +398,12 @@ hsma_status hsma_server_create(const hsma_server_desc* desc, hsma_server* out);
 void        hsma_server_destroy(hsma_server server);
 
 /* Queue a request; x (N x 3) and q (N) are host arrays, copied.  *id receives
-   its handle.  HSMA_E_NOMEM if it could never fit the arena. */
+   its handle.  HSMA_E_NOMEM if it could never fit the arena.  The plan must use
+   the block near set (HSMA_NEAR_BLOCK, or HSMA_NEAR_TREE: the fast multipole
+   method from its tree_min_n on, in double precision whatever the server's
+   precision), exact dipoles and the surface mapping, and a periodic, grounded
+   cube or slab box (else HSMA_E_INVALID).  The double-precision refinement of
+   refine_below recomputes with the direct sums. */
 hsma_status hsma_server_submit(hsma_server server, hsma_plan plan, const double* x,
                                const double* q, int64_t N, int64_t* id);
 

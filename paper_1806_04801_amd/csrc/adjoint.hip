@@ -148,7 +148,7 @@ hsma_status backward(const hsma_plan_s* pl, const Layout& ly, char* ws, hipStrea
                        ly.sym ? ly.g_sym.n_pad : ly.g_near.nt_pad,
                        (const double*)(ws + ly.off_surf_part), ly.g_surf.S, ly.g_surf.nt_pad,
                        G_part, ly.g_G.S, ly.g_G.nt_pad, src64, ly.N,
-                       pl->bc == HSMA_BC_SLAB_METALLIC_Z ? 1 : 0, near_fix(pl, f32),
+                       pl->bc == HSMA_BC_SLAB_METALLIC_Z ? 1 : 0, near_fix(pl, ly),
                        &((const Result*)(ws + ly.off_result))->qnet, dEdx, dEdq);
     CK(hipGetLastError());
     return HSMA_OK;

@@ -113,8 +113,7 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
         d->near_mode != HSMA_NEAR_TREE)
         return fail(HSMA_E_INVALID, "unknown near mode");
     if (d->near_mode == HSMA_NEAR_TREE) {
-        if (d->precision != HSMA_FP64)
-            return fail(HSMA_E_INVALID, "the tree near sum runs in double precision only");
+        if (d->tree_min_n < 0) return fail(HSMA_E_INVALID, "tree_min_n must be >= 0");
         if (d->bc == HSMA_BC_DIELECTRIC)
             return fail(HSMA_E_INVALID, "the tree near sum serves the periodic, grounded and slab boxes");
         if (d->tree_order < 0 || d->tree_order > 20)
@@ -150,6 +149,10 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     pl->far_mode = d->far_mode;
     pl->dr = d->dr > 0.0 ? d->dr : 1e-5 * d->R;
     pl->tree_order = d->near_mode == HSMA_NEAR_TREE ? (d->tree_order > 0 ? d->tree_order : 16) : 0;
+    pl->tree_min_n = d->near_mode != HSMA_NEAR_TREE ? 0
+                     : d->tree_min_n > 0                ? d->tree_min_n
+                     : d->precision == HSMA_FP64         ? 16384
+                                                         : 32768;
     if (pl->near_mode == HSMA_NEAR_SPHERE) {
         // candidates |k_a| <= kr; a source has at most as many images inside the
         // sphere as there are shifted boxes that reach it
@@ -225,6 +228,7 @@ hsma_status hsma_plan_info(hsma_plan pl, hsma_plan_info_t* info) {
     info->gamma = pl->gamma;
     info->far_shells = pl->far_shells;
     info->tree_order = pl->tree_order;
+    info->tree_min_n = pl->tree_min_n;
     return HSMA_OK;
 }
 
@@ -254,7 +258,9 @@ hsma_status hsma_near_schedule(hsma_plan pl, int64_t N, hsma_near_schedule_t* ou
     if (N < 1 || N > (int64_t)1 << 28) return fail(HSMA_E_INVALID, "N out of range");
     const Layout ly = make_layout(pl, N, false);
     *out = hsma_near_schedule_t{};
-    if (ly.sym) {
+    if (ly.tree) {
+        out->kind = 2;
+    } else if (ly.sym) {
         out->kind = 1;
         out->rows_per_lane = ly.g_sym.T;
         out->block = ly.g_sym.B;

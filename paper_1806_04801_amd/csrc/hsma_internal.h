@@ -154,6 +154,7 @@ struct hsma_plan_s {
     double gamma = 0.0;   // dielectric box: image weight
     int far_shells = 0;   // dielectric box: far image shells
     int tree_order = 0;   // tree near sum: multipole order
+    int tree_min_n = 0;   // tree near sum: used from this many particles on
     // host geometry (centred)
     std::vector<double> chk;    // nchk x 3: monitoring points then twins
     std::vector<double> spts;   // M x 3

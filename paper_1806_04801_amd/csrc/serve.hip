@@ -9,8 +9,10 @@
 //      active request advances one stage:
 //        stage A (newly admitted): centring, single-precision records, and
 //          the right-hand-side and near-field tiles, or for requests of 1024
-//          particles and more the pair-once near sum, each on one of a few
-//          side streams, so that the near sums of several requests and the
+//          particles and more the pair-once near sum, and for requests on the
+//          fast multipole method (tree plans above their threshold) the tree,
+//          its near sum and its right-hand side, each on one of a few side
+//          streams, so that the near sums of several requests and the
 //          grouped tiles run at the same time;
 //        stage B (admitted one tick earlier): right-hand-side reduction, least
 //          squares, surface mapping, surface tiles, finalization, energy,
@@ -225,8 +227,9 @@ static hipEvent_t srv_event(hsma_server_s* sv) {
     return e;
 }
 
-static size_t req_device_bytes(const hsma_plan_s* pl, int N, int precision, Layout* ly) {
-    *ly = make_layout(pl, N, false, 1, precision);
+static size_t req_device_bytes(const hsma_plan_s* pl, int N, int precision, Layout* ly,
+                               bool no_tree = false) {
+    *ly = make_layout(pl, N, false, 1, precision, no_tree);
     const size_t a = 256;
     auto up = [&](size_t v) { return (v + a - 1) & ~(a - 1); };
     return up(sizeof(double) * 3 * N) * 2 + up(sizeof(double) * N) * 2 + ly->total;
@@ -308,7 +311,7 @@ static bool admit(hsma_server_s* sv, SrvReq* r) {
     d.near_part = (double*)(ws + ly.off_near_part);
     d.near_S = ly.sym ? ly.g_sym.C + ly.g_sym.s : ly.g_near.S;
     d.near_pad = ly.sym ? ly.g_sym.n_pad : ly.g_near.nt_pad;
-    d.fix = near_fix(pl, sv->desc.precision == HSMA_FP32_COMP);
+    d.fix = near_fix(pl, ly);
     d.surf_part = (double*)(ws + ly.off_surf_part);
     d.surf_S = ly.g_surf.S;
     d.surf_pad = ly.g_surf.nt_pad;
@@ -388,15 +391,15 @@ static hsma_status upload(hsma_server_s* sv, const std::vector<ReqDesc>& da,
     return HSMA_OK;
 }
 
-// Whether a finished single-precision result is recomputed in double
-// precision: its energy is below refine_below * 1/2 sum |q_i phi_i|, and the
-// double-precision block fits the arena.
+// Whether a finished single-precision or fast-multipole result is recomputed
+// with the direct double-precision sums: its energy is below refine_below *
+// 1/2 sum |q_i phi_i|, and the double-precision block fits the arena.
 static bool wants_refine(const hsma_server_s* sv, const SrvReq* r) {
-    if (sv->desc.precision != HSMA_FP32_COMP || !(sv->desc.refine_below > 0.0) ||
+    if ((sv->desc.precision != HSMA_FP32_COMP && !r->ly.tree) || !(sv->desc.refine_below > 0.0) ||
         r->status != HSMA_OK)
         return false;
     Layout ly64;
-    if (req_device_bytes(r->plan, r->N, HSMA_FP64, &ly64) > sv->arena->cap()) return false;
+    if (req_device_bytes(r->plan, r->N, HSMA_FP64, &ly64, true) > sv->arena->cap()) return false;
     const double* q = r->ext_q ? r->ext_q : r->hq.data();
     const double* phi = r->h_out + RES_D;
     double scale = 0.0;
@@ -448,8 +451,9 @@ static hsma_status start_refinements(hsma_server_s* sv, bool* blocked) {
     hipStream_t s = sv->rstream;
     while (!sv->refine.empty()) {
         SrvReq* r = sv->refine.front();
+        // the direct double-precision sums (not the tree's approximation)
         Layout ly64;
-        const size_t bytes = req_device_bytes(r->plan, r->N, HSMA_FP64, &ly64);
+        const size_t bytes = req_device_bytes(r->plan, r->N, HSMA_FP64, &ly64, true);
         size_t off = 0;
         if (!sv->arena->alloc(bytes, &off)) {
             *blocked = true;
@@ -483,6 +487,8 @@ static hsma_status start_refinements(hsma_server_s* sv, bool* blocked) {
 // and the right-hand side (27 N_s per check point).
 static double request_work(const hsma_plan_s* pl, int N) {
     const double ns = pl->bc == HSMA_BC_SLAB_METALLIC_Z ? 2.0 * N : (double)N;
+    if (pl->near_mode == HSMA_NEAR_TREE && N >= pl->tree_min_n)
+        return 5e5 * ns;   // the tree's near sum and right-hand side, in the same unit (measured)
     return 27.0 * ns * ((double)N + (double)pl->nchk);
 }
 
@@ -562,10 +568,11 @@ static hsma_status tick(hsma_server_s* sv) {
     }
     // tile groups: near first (the longest), then right-hand side, then surface;
     // requests large enough for the pair-once near sum run it in rounds of
-    // their own instead (see below)
+    // their own instead, and requests on the tree take their near sum and
+    // right-hand side from it (see below)
     for (SrvReq* r : newA) {
         const ReqDesc& d = r->d;
-        if (r->ly.sym) continue;
+        if (r->ly.sym || r->ly.tree) continue;
         const int l = list_of(TILE_NEAR, d.img);
         if (f32) add_group(lists[l], &nlist_tiles[l], TILE_NEAR, d.img, r->ly.g_near, d.src32, d.src32, d.near_part, d.L);
         else add_group(lists[l], &nlist_tiles[l], TILE_NEAR, d.img, r->ly.g_near, d.src64, d.src64, d.near_part, d.L);
@@ -573,6 +580,7 @@ static hsma_status tick(hsma_server_s* sv) {
     for (SrvReq* r : newA) {
         const hsma_plan_s* pl = r->plan;
         const ReqDesc& d = r->d;
+        if (r->ly.tree) continue;
         const int l = list_of(TILE_RHS, d.img);
         if (f32) add_group(lists[l], &nlist_tiles[l], TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk32, d.src32, d.rhs_part, d.L);
         else add_group(lists[l], &nlist_tiles[l], TILE_RHS, d.img, r->ly.g_rhs, pl->d_chk64, d.src64, d.rhs_part, d.L);
@@ -609,15 +617,16 @@ static hsma_status tick(hsma_server_s* sv) {
         if (f32) hipLaunchKernelGGL(k_g_rec32, dim3(maxA_ns, nA), dim3(SWG), 0, s, dA);
     }
     HSMA_HIP(hipGetLastError());
-    // Pair-once near sums of the new requests at or above the threshold: each
-    // request's launches go to one of the side streams (the one with the least
-    // work so far, largest requests first), forked from the server stream after
-    // the records above, so that the near sums of several requests and the
-    // grouped tiles below run at the same time; the side streams join back
-    // at the end of the tick.
+    // Pair-once near sums of the new requests at or above the threshold, and
+    // the tree (build, near sum, right-hand side) of requests on the fast
+    // multipole method: each request's launches go to one of the side streams
+    // (the one with the least work so far, largest requests first), forked
+    // from the server stream after the records above, so that the near sums
+    // of several requests and the grouped tiles below run at the same time;
+    // the side streams join back at the end of the tick.
     std::vector<SrvReq*> symr;
     for (SrvReq* r : newA)
-        if (r->ly.sym) symr.push_back(r);
+        if (r->ly.sym || r->ly.tree) symr.push_back(r);
     std::stable_sort(symr.begin(), symr.end(), [](const SrvReq* a, const SrvReq* b) { return a->N > b->N; });
     bool side_used[hsma_server_s::NSIDE] = {};
     if (!symr.empty()) {
@@ -627,13 +636,20 @@ static hsma_status tick(hsma_server_s* sv) {
             int w = 0;
             for (int k = 1; k < sv->nside; ++k)
                 if (load[k] < load[w]) w = k;
-            load[w] += (double)r->N * r->N;
+            // rough cost in one unit: pair-once ~ N^2, the tree ~ 2e4 N (measured)
+            load[w] += r->ly.tree ? 2e4 * r->N : (double)r->N * r->N;
             hipStream_t ss = sv->side[w];
             if (!side_used[w]) {
                 HSMA_HIP(hipStreamWaitEvent(ss, sv->fork_ev, 0));
                 side_used[w] = true;
             }
-            if (f32)
+            if (r->ly.tree) {
+                const hsma_plan_s* pl = r->plan;
+                char* tws = carve(sv->arena_base + r->off, r->N).ws + r->ly.off_tree;
+                HSMA_HIP(launch_tree_build(pl->img, r->d.src64, r->ly.ns, pl->L, r->ly.tl, tws, ss));
+                HSMA_HIP(launch_tree_points(pl->d_chk64, pl->nchk, pl->L, r->ly.tl, tws, r->d.rhs_part, ss));
+                HSMA_HIP(launch_tree_near(r->N, pl->L, r->ly.tl, tws, r->d.near_part, r->ly.g_near.nt_pad, ss));
+            } else if (f32)
                 HSMA_HIP(launch_sym_f32(r->ly.sym_img, r->d.src32, r->ly.g_sym, r->d.L, r->d.near_part, ss));
             else
                 HSMA_HIP(launch_sym_f64(r->ly.sym_img, r->d.src64, r->ly.g_sym, r->d.L, r->d.near_part, ss));
@@ -789,11 +805,11 @@ static hsma_status submit_impl(hsma_server sv, hsma_plan plan, const double* x, 
     if (sv == nullptr || plan == nullptr || x == nullptr || q == nullptr || id == nullptr)
         return fail(HSMA_E_INVALID, "NULL argument");
     if (N < 1 || N > ((int64_t)1 << 26)) return fail(HSMA_E_INVALID, "N out of range");
-    if (plan->near_mode != HSMA_NEAR_BLOCK || plan->dipole_mode != HSMA_DIPOLE_EXACT ||
-        plan->far_mode != HSMA_FAR_SURFACE || plan->bc == HSMA_BC_DIELECTRIC ||
-        plan->near_mode != HSMA_NEAR_BLOCK)
-        return fail(HSMA_E_INVALID, "the server runs block near-set, exact-dipole plans of the "
-                                    "periodic, grounded-cube and slab boxes only");
+    if ((plan->near_mode != HSMA_NEAR_BLOCK && plan->near_mode != HSMA_NEAR_TREE) ||
+        plan->dipole_mode != HSMA_DIPOLE_EXACT || plan->far_mode != HSMA_FAR_SURFACE ||
+        plan->bc == HSMA_BC_DIELECTRIC)
+        return fail(HSMA_E_INVALID, "the server runs block near-set (direct or tree), exact-dipole "
+                                    "plans of the periodic, grounded-cube and slab boxes only");
     Layout ly;
     if (req_device_bytes(plan, (int)N, sv->desc.precision, &ly) > sv->arena->cap() ||
         req_host_bytes((int)N) > sv->host_arena->cap()) {

@@ -56,10 +56,12 @@ struct Layout {
 struct NearFix {
     double own = 0.0, qc = 0.0;
 };
-NearFix near_fix(const hsma_plan_s* pl, bool f32);
+// The fixed near-potential terms for plan pl under layout ly.
+NearFix near_fix(const hsma_plan_s* pl, const Layout& ly);
 
+// no_tree: the direct near kernels even where the plan would use the tree.
 Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_override = 0,
-                   int precision_override = -1);
+                   int precision_override = -1, bool no_tree = false);
 // dtype (HSMA_DTYPE_F64 or HSMA_DTYPE_F32) is the type of x, q, phi and forces.
 hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, const void* q,
                     int dtype, char* ws, hipStream_t s, void* phi, void* forces,

@@ -22,17 +22,17 @@ static int env_int(const char* name, int dflt) {
     return atoi(v);
 }
 
-NearFix near_fix(const hsma_plan_s* pl, bool f32) {
+NearFix near_fix(const hsma_plan_s* pl, const Layout& ly) {
     NearFix f;
-    if (pl->near_mode != HSMA_NEAR_BLOCK || pl->img != IMG_PERIODIC) return f;
-    const double shift = f32 ? OWN_COLS_F32 : 0.0;
+    if (pl->near_mode == HSMA_NEAR_SPHERE || ly.tree || pl->img != IMG_PERIODIC) return f;
+    const double shift = ly.f32 ? OWN_COLS_F32 : 0.0;
     f.own = (OWN_IMAGES_PERIODIC - shift) / pl->L;
     if (pl->bc == HSMA_BC_PERIODIC) f.qc = shift / pl->L;
     return f;
 }
 
 Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_override,
-                   int precision_override) {
+                   int precision_override, bool no_tree) {
     Layout ly;
     ly.N = (int)N;
     ly.ns = (pl->bc == HSMA_BC_SLAB_METALLIC_Z) ? 2 * (int)N : (int)N;
@@ -40,7 +40,7 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     const bool f32 = prec == HSMA_FP32_COMP;
     ly.f32 = f32;
     const bool sphere = pl->near_mode == HSMA_NEAR_SPHERE;
-    const bool tree = pl->near_mode == HSMA_NEAR_TREE;
+    const bool tree = pl->near_mode == HSMA_NEAR_TREE && N >= pl->tree_min_n && !no_tree;
     // targets per lane of the near tiles: the image-block kernels run best
     // with one, the explicit-image tiles with two (measured); an override other
     // than 1 or 2 is ignored
@@ -345,7 +345,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
         hipLaunchKernelGGL(k_dup_insert, dim3((N + WG - 1) / WG), dim3(WG), 0, s, src64, N, dup,
                            (uint32_t)(ly.dup_T - 1), &res->status);
     }
-    const NearFix fix = near_fix(pl, f32);
+    const NearFix fix = near_fix(pl, ly);
     if (fix.qc != 0.0)
         hipLaunchKernelGGL(k_net_charge, dim3(1), dim3(SWG), 0, s, src64, N, &res->qnet);
     CK(hipGetLastError());

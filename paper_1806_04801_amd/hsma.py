@@ -44,7 +44,8 @@ class PlanDesc(ctypes.Structure):
                 ("M", ctypes.c_int), ("K", ctypes.c_int), ("R", ctypes.c_double),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("near_mode", ctypes.c_int),
                 ("dipole_mode", ctypes.c_int), ("dr", ctypes.c_double), ("far_mode", ctypes.c_int),
-                ("gamma", ctypes.c_double), ("far_shells", ctypes.c_int), ("tree_order", ctypes.c_int)]
+                ("gamma", ctypes.c_double), ("far_shells", ctypes.c_int), ("tree_order", ctypes.c_int),
+                ("tree_min_n", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -55,7 +56,7 @@ class PlanInfo(ctypes.Structure):
                 ("bytes_resident", ctypes.c_size_t), ("near_mode", ctypes.c_int),
                 ("max_images_per_source", ctypes.c_int), ("dipole_mode", ctypes.c_int),
                 ("dr", ctypes.c_double), ("far_mode", ctypes.c_int), ("gamma", ctypes.c_double),
-                ("far_shells", ctypes.c_int), ("tree_order", ctypes.c_int)]
+                ("far_shells", ctypes.c_int), ("tree_order", ctypes.c_int), ("tree_min_n", ctypes.c_int)]
 
 
 class Intermediates(ctypes.Structure):
@@ -172,12 +173,13 @@ class Plan:
 
     def __init__(self, L, bc, p, M, K, R, precision=FP64, seed=DEFAULT_SEED, near_mode=NEAR_BLOCK,
                  dipole_mode=DIPOLE_EXACT, dr=0.0, far_mode=FAR_SURFACE, gamma=0.0, far_shells=0,
-                 tree_order=0):
+                 tree_order=0, tree_min_n=0):
         lib = load()
         d = PlanDesc(L=float(L), bc=int(bc), p=int(p), M=int(M), K=int(K), R=float(R),
                      precision=int(precision), seed=int(seed), near_mode=int(near_mode),
                      dipole_mode=int(dipole_mode), dr=float(dr), far_mode=int(far_mode),
-                     gamma=float(gamma), far_shells=int(far_shells), tree_order=int(tree_order))
+                     gamma=float(gamma), far_shells=int(far_shells), tree_order=int(tree_order),
+                     tree_min_n=int(tree_min_n))
         h = ctypes.c_void_p()
         _check(lib.hsma_plan_create_ex(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -337,7 +339,8 @@ DEFAULT_REFINE_BELOW = 3e-3
 class Server:
     """Continuous-batching server of energy/force requests (see hsma.h).
     refine_below=None selects DEFAULT_REFINE_BELOW for a single-precision
-    server (0 turns the refinement off)."""
+    server and 0 (off) for a double-precision one; the refinement also
+    covers requests on the fast multipole method (tree plans)."""
 
     def __init__(self, memory_bytes=8 << 30, max_active=64, precision=FP32_COMP, refine_below=None):
         lib = load()

@@ -76,7 +76,7 @@ def check(tag, q, idx, pn, fn, ref_p, ref_f, order=16):
 def test_tree_near_sum_vs_direct_every_particle(hs, bc, n):
     announce("tree near bc=%d n=%d" % (bc, n))
     x, q = system(bc, n, 50 + n)
-    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
+    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=1)
     assert plan.info["tree_order"] == 16
     _, pn, fn, b = near_parts(hs, plan, x, q, with_b=True)
     idx = np.arange(n)
@@ -96,7 +96,7 @@ def test_tree_order_controls_the_error(hs):
     ref_p, ref_f = direct_near(0, x, q, idx)
     errs = []
     for order in (8, 12, 16):
-        plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=order)
+        plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=order, tree_min_n=1)
         _, pn, fn = near_parts(hs, plan, x, q)
         errs.append(check("order sweep", q, idx, pn, fn, ref_p, ref_f, order))
     assert errs[2]["phi"] < 0.1 * errs[1]["phi"] < 0.01 * errs[0]["phi"]
@@ -107,7 +107,7 @@ def test_tree_order_controls_the_error(hs):
 def test_tree_near_sum_sampled_at_size(hs, bc, n, ns):
     announce("tree near bc=%d n=%d sampled" % (bc, n))
     x, q = system(bc, n, 80)
-    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
+    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=1)
     near_parts(hs, plan, x, q)   # warm
     t0 = time.perf_counter()
     e, pn, fn, b = near_parts(hs, plan, x, q, with_b=True)
@@ -129,7 +129,7 @@ def test_tree_whole_step_vs_direct_step(hs, bc):
     announce("tree whole step bc=%d" % bc)
     x, q = system(bc, 10000, 91)
     xd, qd = torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda")
-    p_tree = hs.Plan(1.0, bc, 12, 1440, 1440, 2.7, near_mode=hs.NEAR_TREE)
+    p_tree = hs.Plan(1.0, bc, 12, 1440, 1440, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=1)
     p_dir = hs.Plan(1.0, bc, 12, 1440, 1440, 2.7)
     e1, phi1, F1 = p_tree.energy_forces(xd, qd)
     e0, phi0, F0 = p_dir.energy_forces(xd, qd)
@@ -146,14 +146,70 @@ def test_tree_whole_step_vs_direct_step(hs, bc):
 def test_tree_rejections(hs):
     announce("tree rejections")
     with pytest.raises(hs.HsmaError):
-        hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, precision=hs.FP32_COMP)
+        hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=-1)
     with pytest.raises(hs.HsmaError):
-        hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=25)
-    plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE)
+        hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=25, tree_min_n=1)
+    plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=1)
     x, q = W.uniform_neutral(100, 1.0, 3)
     with pytest.raises(hs.HsmaError):
         plan.energy_grad(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
-    srv = hs.Server(memory_bytes=64 << 20, max_active=2, precision=hs.FP64)
-    with pytest.raises(hs.HsmaError):
-        srv.submit(plan, x, q)
+    # the default threshold, and the near kernel either side of it
+    assert hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE).info["tree_min_n"] == 16384
+    p32 = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, precision=hs.FP32_COMP)
+    assert p32.info["tree_min_n"] == 32768
+    assert p32.near_schedule(32767)["kind"] == 1 and p32.near_schedule(32768)["kind"] == 2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tree_plans_in_the_server(hs, precision):
+    """Tree plans in the batched server: requests at or above tree_min_n run
+    the tree (build, near sum, right-hand side) on the side streams, smaller
+    ones the direct kernels, in one mix.  Each result equals the
+    single-request path of the same plan to rounding (same arithmetic), and
+    is bitwise the same alone and in the mix; the double-precision refinement
+    recomputes with the direct sums (bitwise the block plan's FP64 path), in
+    a double-precision server too."""
+    announce("server tree plans precision=%d" % precision)
+    plans = {bc: hs.Plan(1.0, bc, 8, 640, 640, 2.7, precision=precision, near_mode=hs.NEAR_TREE,
+                         tree_min_n=3000) for bc in (0, 1, 2)}
+    sizes = [(0, 1030), (1, 2050), (2, 1600), (0, 4100), (1, 5000), (2, 3000), (0, 12000), (1, 800)]
+    reqs = []
+    for i, (bc, n) in enumerate(sizes):
+        x, q = system(bc, n, 40 + i)
+        reqs.append((bc, x, q))
+    kinds = [plans[bc].near_schedule(len(q))["kind"] for bc, _, q in reqs]
+    assert kinds == [1, 1, 1, 2, 2, 2, 2, 0]
+    srv = hs.Server(memory_bytes=4 << 30, max_active=16, precision=precision, refine_below=0.0)
+    ids = [srv.submit(plans[bc], x, q) for bc, x, q in reqs]
+    mixed = []
+    for rid, (bc, x, q) in zip(ids, reqs):
+        srv.wait(rid)
+        done, e, phi, F, _ = srv.result(rid, len(q))
+        assert done
+        mixed.append((e, phi, F))
+    for (bc, x, q), (e, phi, F) in zip(reqs, mixed):
+        e1, phi1, F1 = plans[bc].energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+        phi1 = phi1.cpu().numpy()
+        scale = 0.5 * float(np.sum(np.abs(q * phi1)))
+        assert abs(e - e1) <= 1e-12 * scale
+        assert rel_max(phi, phi1, np.abs(phi1).max()) <= 1e-12
+        assert rel_max(F, F1.cpu().numpy()) <= 1e-11
+    for i in (3, 5):
+        bc, x, q = reqs[i]
+        rid = srv.submit(plans[bc], x, q)
+        srv.wait(rid)
+        done, e, phi, F, _ = srv.result(rid, len(q))
+        assert e == mixed[i][0] and np.array_equal(phi, mixed[i][1]) and np.array_equal(F, mixed[i][2])
+    srv.close()
+    # refinement of every request: the direct double-precision sums
+    srv = hs.Server(memory_bytes=4 << 30, max_active=16, precision=precision, refine_below=1.0)
+    block = {bc: hs.Plan(1.0, bc, 8, 640, 640, 2.7, precision=hs.FP64) for bc in (0, 2)}
+    for i in (3, 5):
+        bc, x, q = reqs[i]
+        rid = srv.submit(plans[bc], x, q)
+        srv.wait(rid)
+        done, e, phi, F, _ = srv.result(rid, len(q))
+        e0, phi0, F0 = block[bc].energy_forces(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+        assert e == e0 and np.array_equal(phi, phi0.cpu().numpy()) and np.array_equal(F, F0.cpu().numpy())
+    assert srv.stats()["refined"] == 2
     srv.close()

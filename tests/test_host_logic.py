@@ -169,3 +169,27 @@ def test_bench_counts_evaluated_near_pairs(n, block, bc):
     assert bench.near_evaluated_pairs(n, {"bc": bc}, sched) == imgs * cnt
     tiles = bench.near_evaluated_pairs(n, {"bc": bc}, {"kind": 0})
     assert tiles == 27.0 * n * (2 * n if bc == 2 else n)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of hsma_plan_desc and hsma_plan_info_t have the C
+    header's size and field offsets (a C program prints them)."""
+    import ctypes
+
+    from paper_1806_04801_amd import hsma
+    exe = tmp_path / "layout_check"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(HERE, "..", "include"),
+                           os.path.join(HERE, "layout_check.c"), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60, check=True).stdout
+    types = {"hsma_plan_desc": hsma.PlanDesc, "hsma_plan_info_t": hsma.PlanInfo}
+    seen = set()
+    for line in out.strip().splitlines():
+        name, size, *fields = line.split()
+        T = types[name]
+        assert ctypes.sizeof(T) == int(size), name
+        assert [f for f, _ in T._fields_] == [kv.split("=")[0] for kv in fields], name
+        for kv in fields:
+            f, off = kv.split("=")
+            assert getattr(T, f).offset == int(off), (name, f)
+        seen.add(name)
+    assert seen == set(types)
