@@ -51,7 +51,8 @@ typedef enum {
                                     gamma^|k|, |gamma| < 1 (hsma_plan_desc.gamma); the far images
                                     (shells 2..far_shells of the image lattice) are summed at the
                                     monitoring points and fitted; double precision, block near
-                                    set, no adjoint and no serving */
+                                    set (direct, or the fast multipole method of HSMA_NEAR_TREE),
+                                    no adjoint and no serving */
 } hsma_bc;
 
 typedef enum {

@@ -94,8 +94,8 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
         if (!(std::fabs(d->gamma) < 1.0)) return fail(HSMA_E_INVALID, "dielectric box needs |gamma| < 1");
         if (d->precision != HSMA_FP64)
             return fail(HSMA_E_INVALID, "the dielectric box runs in double precision only");
-        if (d->near_mode != HSMA_NEAR_BLOCK)
-            return fail(HSMA_E_INVALID, "the dielectric box uses the block near set");
+        if (d->near_mode != HSMA_NEAR_BLOCK && d->near_mode != HSMA_NEAR_TREE)
+            return fail(HSMA_E_INVALID, "the dielectric box uses the block near set (direct or tree)");
         if (d->far_shells < 0 || d->far_shells > 400)
             return fail(HSMA_E_INVALID, "far_shells must be in [0, 400]");
     }
@@ -114,8 +114,6 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
         return fail(HSMA_E_INVALID, "unknown near mode");
     if (d->near_mode == HSMA_NEAR_TREE) {
         if (d->tree_min_n < 0) return fail(HSMA_E_INVALID, "tree_min_n must be >= 0");
-        if (d->bc == HSMA_BC_DIELECTRIC)
-            return fail(HSMA_E_INVALID, "the tree near sum serves the periodic, grounded and slab boxes");
         if (d->tree_order < 0 || d->tree_order > 20)
             return fail(HSMA_E_INVALID, "tree_order must be in [0, 20]");
     }

@@ -85,13 +85,14 @@ Layout make_layout(const hsma_plan_s* pl, int64_t N, bool grad, int tpl_near_ove
     ly.off_A = take(sizeof(double) * (size_t)pl->nb);
     ly.off_surf = take(sizeof(double) * 12 * (size_t)pl->M);   // 8 per point, or 3 charges
     if (tree) {
-        // the tree writes eval_split copies of phi and E: chunks of the tile layout
-        // the right-hand side comes from the same tree (one chunk), on the
-        // caller's stream after the tree is built
+        // the tree writes eval_split copies of phi and E: chunks of the tile
+        // layout; the right-hand side comes from the same tree (one chunk),
+        // on the caller's stream after the tree is built, except for the
+        // dielectric box, whose right-hand side is the far shells'
         ly.tree = true;
         ly.tl = tree_layout(ly.ns, pl->tree_order);
         ly.g_near.S = ly.tl.eval_split;
-        ly.g_rhs.S = 1;
+        if (pl->img != IMG_DIELECTRIC) ly.g_rhs.S = 1;
         ly.single_stream = true;
     }
     {
@@ -384,7 +385,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
         // the tree (images, sort, multipoles) serves the near sum here and the
         // right-hand side below; the near sum's timing covers the build
         timing_begin(0, s);
-        CK(launch_tree_build(pl->img, src64, ly.ns, pl->L, ly.tl, ws + ly.off_tree, s));
+        CK(launch_tree_build(pl->img, pl->gamma, src64, ly.ns, pl->L, ly.tl, ws + ly.off_tree, s));
         CK(launch_tree_near(N, pl->L, ly.tl, ws + ly.off_tree, near_part, g_near.nt_pad, s));
         timing_end(0, s);
     }
@@ -412,13 +413,13 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
     }
     // right-hand side at the monitoring points (and twins)
     timing_begin(1, s1);
-    if (ly.tree)
+    if (pl->img == IMG_DIELECTRIC)   // the far shells (direct or tree near sum alike)
+        CK(launch_far_shells(pl->d_chk64, src64, g_rhs, pl->L, pl->gamma, pl->far_shells, rhs_part, s1));
+    else if (ly.tree)
         CK(launch_tree_points(pl->d_chk64, pl->nchk, pl->L, ly.tl, ws + ly.off_tree, rhs_part, s1));
     else if (sphere)
         CK(launch_explicit(f32, false, false, f32 ? (const void*)pl->d_chk32 : (const void*)pl->d_chk64,
                            f32 ? (const void*)img32 : (const void*)img64, g_rhs, pl->L, rhs_part, s1));
-    else if (pl->img == IMG_DIELECTRIC)
-        CK(launch_far_shells(pl->d_chk64, src64, g_rhs, pl->L, pl->gamma, pl->far_shells, rhs_part, s1));
     else if (f32)
         CK(launch_pair_f32(pl->img, false, false, pl->d_chk32, src32, g_rhs, pl->L, rhs_part, s1));
     else

@@ -31,10 +31,11 @@ double tree_leaf_images();
 TreeLayout tree_layout(int64_t ns, int p);
 
 // Images of the ns sources (img: IMG_PERIODIC, also for the slab's doubled
-// cube, or IMG_METALLIC), sorted into the octree, and their multipoles at
-// every level (ws: t.total bytes).  Run before the two calls below.
-hipError_t launch_tree_build(int img, const double4* src, int ns, double L, const TreeLayout& t, char* ws,
-                             hipStream_t s);
+// cube, IMG_METALLIC, or IMG_DIELECTRIC with reflection weight gamma), sorted
+// into the octree, and their multipoles at every level (ws: t.total bytes).
+// Run before the two calls below.
+hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, double L, const TreeLayout& t,
+                             char* ws, hipStream_t s);
 
 // Potential of all images at npts points (centred coordinates, inside the
 // image cube): out[i], i < npts.

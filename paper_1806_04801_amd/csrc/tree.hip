@@ -97,8 +97,8 @@ __host__ __device__ __forceinline__ uint32_t cell_key(int gx, int gy, int gz, in
 // kk * ns + j, with its leaf key; owner[slot] = j for the central image
 // (kk = 13) and -1 otherwise (the bare self term is the central image of the
 // target itself).
-__global__ void k_tree_images(const double4* __restrict__ src, int ns, int img, double L, int lev,
-                              double4* __restrict__ out, uint32_t* __restrict__ keys,
+__global__ void k_tree_images(const double4* __restrict__ src, int ns, int img, double gamma, double L,
+                              int lev, double4* __restrict__ out, uint32_t* __restrict__ keys,
                               int* __restrict__ vals) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int kk = blockIdx.y;
@@ -106,10 +106,12 @@ __global__ void k_tree_images(const double4* __restrict__ src, int ns, int img, 
     const int kx = kk / 9 - 1, ky = (kk / 3) % 3 - 1, kz = kk % 3 - 1;
     const double4 r = src[j];
     double px = r.x, py = r.y, pz = r.z, q = r.w;
-    if (img == IMG_METALLIC) {
-        if (kx) { px = -px; q = -q; }
-        if (ky) { py = -py; q = -q; }
-        if (kz) { pz = -pz; q = -q; }
+    if (img == IMG_METALLIC || img == IMG_DIELECTRIC) {
+        // reflections; each weighs -1 (grounded) or gamma (dielectric, Eq. (diel))
+        const double w = img == IMG_METALLIC ? -1.0 : gamma;
+        if (kx) { px = -px; q *= w; }
+        if (ky) { py = -py; q *= w; }
+        if (kz) { pz = -pz; q *= w; }
     }
     px += kx * L;
     py += ky * L;
@@ -972,8 +974,8 @@ __global__ void k_tree_m2m_table(int p, double2* __restrict__ tab) {
     }
 }
 
-hipError_t launch_tree_build(int img, const double4* src, int ns, double L, const TreeLayout& t, char* ws,
-                             hipStream_t s) {
+hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, double L, const TreeLayout& t,
+                             char* ws, hipStream_t s) {
     if (ns <= 0) return hipSuccess;
     if (t.p < 1 || t.p > TREE_MAX_ORDER || t.L < 1 || t.L > TREE_MAX_LEVEL) return hipErrorInvalidValue;
     double4* img4 = (double4*)(ws + t.off_img);
@@ -985,8 +987,8 @@ hipError_t launch_tree_build(int img, const double4* src, int ns, double L, cons
     int* owner = (int*)(ws + t.off_owner);
     int* offs = (int*)(ws + t.off_offs);
     const int64_t n = t.nimg;
-    hipLaunchKernelGGL(k_tree_images, dim3((ns + 255) / 256, 27), dim3(256), 0, s, src, ns, img, L, t.L,
-                       img4, keys, vals);
+    hipLaunchKernelGGL(k_tree_images, dim3((ns + 255) / 256, 27), dim3(256), 0, s, src, ns, img, gamma, L,
+                       t.L, img4, keys, vals);
     size_t cub = t.cub_bytes;
     const int end_bit = 3 * t.L + 5;   // box index < 27 < 2^5
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(ws + t.off_cub, cub, keys, keys2, vals, vals2,

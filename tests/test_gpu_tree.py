@@ -88,6 +88,33 @@ def test_tree_near_sum_vs_direct_every_particle(hs, bc, n):
     assert eb <= TOL_B[bc]
 
 
+@pytest.mark.parametrize("bc", [0, 1])
+def test_tree_clustered_and_single_charge(hs, bc):
+    """A strongly clustered system (two thirds of the charges in a ball of
+    radius 0.05 L, so that a few leaf cells hold thousands of images), and a
+    single charge in the grounded cube (every other cell empty)."""
+    announce("tree clustered bc=%d" % bc)
+    x, q = W.uniform_neutral(3000, 1.0, 33)
+    rng = np.random.default_rng(34)
+    d = rng.standard_normal((2000, 3))
+    d *= (0.05 * rng.random(2000) ** (1 / 3) / np.linalg.norm(d, axis=1))[:, None]
+    x[:2000] = np.array([0.3, 0.6, 0.4]) + d
+    plan = hs.Plan(1.0, bc, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=1)
+    _, pn, fn = near_parts(hs, plan, x, q)
+    idx = np.arange(len(q))
+    ref_p, ref_f = direct_near(bc, x, q, idx)
+    e = check("clustered bc=%d" % bc, q, idx, pn, fn, ref_p, ref_f)
+    assert e["phi"] <= TOL_PHI and e["E"] <= TOL_E and e["En"] <= TOL_EN
+    if bc == 1:
+        x1, q1 = np.array([[0.2, 0.7, 0.55]]), np.array([1.0])
+        _, pn, fn = near_parts(hs, plan, x1, q1)
+        ref_p, ref_f = direct_near(1, x1, q1, np.arange(1))
+        print("tree single charge: phi %.2e E %.2e" % (abs(pn[0] - ref_p[0]) / abs(ref_p[0]),
+                                                       rel_max(fn[:1], ref_f)))
+        assert abs(pn[0] - ref_p[0]) <= TOL_PHI * abs(ref_p[0])
+        assert rel_max(fn[:1], ref_f) <= TOL_E
+
+
 def test_tree_order_controls_the_error(hs):
     """The error falls geometrically with the multipole order."""
     announce("tree order sweep")
@@ -213,3 +240,30 @@ def test_tree_plans_in_the_server(hs, precision):
         assert e == e0 and np.array_equal(phi, phi0.cpu().numpy()) and np.array_equal(F, F0.cpu().numpy())
     assert srv.stats()["refined"] == 2
     srv.close()
+
+
+@pytest.mark.parametrize("gamma", [0.4, -0.7])
+def test_tree_dielectric_box(hs, gamma):
+    """The dielectric box (Eq. (diel)) with the fast multipole near sum: the
+    images carry gamma^|k| in the tree; the near sum matches the oracle's
+    direct dielectric near sum, and the whole step the direct step (its
+    right-hand side is the far shells' in both)."""
+    announce("tree dielectric gamma=%.2f" % gamma)
+    rng = np.random.default_rng(21)
+    n = 2000
+    x = rng.uniform(0.02, 0.98, (n, 3))
+    q = rng.choice([-1.0, 1.0], n)
+    kw = dict(gamma=gamma, far_shells=6)
+    plan = hs.Plan(1.0, hs.BC_DIELECTRIC, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=1, **kw)
+    _, pn, fn = near_parts(hs, plan, x, q)
+    idx = np.arange(n)
+    r = oracle.solve(oracle.make_plan(1.0, oracle.BC_DIELECTRIC, 4, 400, 100, 2.7, gamma=gamma, shells=6),
+                     x, q, targets=idx)
+    e = check("dielectric %.2f" % gamma, q, idx, pn, fn, r["phi_near"], r["field_near"])
+    assert e["phi"] <= TOL_PHI and e["E"] <= TOL_E and e["En"] <= TOL_EN
+    xd, qd = torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda")
+    e1, phi1, F1 = plan.energy_forces(xd, qd)
+    e0, phi0, F0 = hs.Plan(1.0, hs.BC_DIELECTRIC, 8, 1000, 300, 2.7, **kw).energy_forces(xd, qd)
+    phi0 = phi0.cpu().numpy()
+    assert abs(e1 - e0) <= TOL_EN * 0.5 * np.sum(np.abs(q * phi0))
+    assert rel_max(phi1.cpu().numpy(), phi0, rms(phi0)) <= TOL_PHI
