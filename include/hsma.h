@@ -256,8 +256,10 @@ hsma_status hsma_near_schedule(hsma_plan plan, int64_t N, hsma_near_schedule_t* 
 
 /*
  * Update step (Sec. II.C) on host arrays: x (N x 3), q (N); outputs energy
- * (one double), phi (N or NULL) and forces (N x 3 or NULL).  Allocates its
- * own device buffers and synchronizes before returning.
+ * (one double), phi (N or NULL) and forces (N x 3 or NULL).  The device
+ * buffers live in the plan: the first call, and a call with a larger N than
+ * any before, allocate; later calls reuse them.  Calls on one plan run one at
+ * a time (a lock of the plan); the call synchronizes before returning.
  */
 hsma_status hsma_energy_forces(hsma_plan plan, const double* x, const double* q, int64_t N,
                                double* energy, double* phi, double* forces);

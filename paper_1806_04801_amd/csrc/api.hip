@@ -374,16 +374,26 @@ hsma_status hsma_energy_forces(hsma_plan pl, const double* x, const double* q, i
         return fail(HSMA_E_NOT_NEUTRAL, "periodic/slab system is not neutral");
     HSMA_HIP(hipSetDevice(pl->device));
     const Layout ly = make_layout(pl, N, false);
-    char* base = nullptr;
     const size_t nx = sizeof(double) * 3 * (size_t)N, nq = sizeof(double) * (size_t)N;
     const size_t off_x = 0, off_q = (nx + 255) & ~(size_t)255,
                  off_phi = off_q + ((nq + 255) & ~(size_t)255),
                  off_f = off_phi + ((nq + 255) & ~(size_t)255),
                  off_ws = off_f + ((nx + 255) & ~(size_t)255);
-    if (hipMalloc((void**)&base, off_ws + ly.total) != hipSuccess)
-        return fail(HSMA_E_NOMEM, "device allocation failed");
+    // the plan's buffer, grown to this call's need (no allocation once it fits)
+    std::lock_guard<std::mutex> lk(pl->host_mu);
+    if (pl->host_cap < off_ws + ly.total) {
+        hipFree(pl->host_buf);
+        pl->host_buf = nullptr;
+        pl->host_cap = 0;
+        if (hipMalloc((void**)&pl->host_buf, off_ws + ly.total) != hipSuccess) {
+            pl->host_buf = nullptr;
+            return fail(HSMA_E_NOMEM, "device allocation failed");
+        }
+        pl->host_cap = off_ws + ly.total;
+    }
+    char* base = pl->host_buf;
     hipStream_t s = nullptr;
-    auto done = [&](hsma_status r) { hipFree(base); return r; };
+    auto done = [&](hsma_status r) { return r; };
     if (hipMemcpy(base + off_x, x, nx, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + off_q, q, nq, hipMemcpyHostToDevice) != hipSuccess)
         return done(fail(HSMA_E_DEVICE, "host to device copy failed"));

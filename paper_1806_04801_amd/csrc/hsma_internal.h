@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -167,6 +168,12 @@ struct hsma_plan_s {
     double4* d_chk64 = nullptr; // nchk     check points (x, y, z, 0)
     hsma::Rec32* d_chk32 = nullptr;  // nchk single-precision records
     size_t bytes = 0;
+    // device buffer of the host-array entry point (inputs, outputs and
+    // workspace), kept between calls and grown when a call needs more; calls
+    // of that entry point on one plan take the mutex in turn
+    std::mutex host_mu;
+    char* host_buf = nullptr;
+    size_t host_cap = 0;
 };
 
 namespace hsma {

@@ -494,6 +494,7 @@ void free_plan(hsma_plan_s* pl) {
     hipFree(pl->d_spos);
     hipFree(pl->d_chk64);
     hipFree(pl->d_chk32);
+    hipFree(pl->host_buf);
 }
 
 }  // namespace hsma

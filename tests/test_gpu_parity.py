@@ -120,13 +120,16 @@ def test_metallic_c2_sampled(hs):
 
 
 def test_host_entry_point_matches_device(hs):
+    """The host-array entry point equals the device path bitwise, over calls
+    that grow, keep and reuse the plan's device buffer."""
     announce("host entry point")
-    x, q = W.uniform_neutral(500, 1.0, seed=3)
     gplan = hs.Plan(1.0, 0, 10, 1000, 600, 2.7)
-    e1, phi1, F1 = gplan.energy_forces_host(x, q)
-    e2, phi2, F2, _ = run_gpu(hs, gplan, x, q, intermediates=False)
-    assert e1 == e2
-    assert np.array_equal(phi1, phi2) and np.array_equal(F1, F2)
+    for n, seed in ((500, 3), (3000, 4), (200, 5), (3000, 4)):
+        x, q = W.uniform_neutral(n, 1.0, seed=seed)
+        e1, phi1, F1 = gplan.energy_forces_host(x, q)
+        e2, phi2, F2, _ = run_gpu(hs, gplan, x, q, intermediates=False)
+        assert e1 == e2
+        assert np.array_equal(phi1, phi2) and np.array_equal(F1, F2)
 
 
 def test_bitwise_repeatable(hs):
