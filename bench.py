@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--n", type=int, default=0,
                     help="particles (default: the workload's own count); the same seeded recipe at "
                          "another size")
+    ap.add_argument("--fmm-steps", type=int, default=3,
+                    help="default workload: also time this many update steps with the fast multipole "
+                         "near sum and right-hand side (object 'fmm' of the line; 0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB device buffer (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -415,6 +418,37 @@ def adjoint_bench(args, cfg, x, q, prec):
     print(json.dumps(rec))
 
 
+def fmm_measure(cfg, xd, qd, steps, e_direct):
+    """The same workload with the fast multipole method for the near sum and
+    the right-hand side (FP64, expansion order 16): ms per update step, the
+    near sum's share (tree build included, HIP events), and the energy against
+    the direct step of this run."""
+    import torch
+
+    from paper_1806_04801_amd import hsma
+    plan = hsma.Plan(cfg["L"], cfg["bc"], cfg["p"], cfg["M"], cfg["K"], cfg["R"], precision=hsma.FP64,
+                     near_mode=hsma.NEAR_TREE)
+    plan.energy_forces(xd, qd)   # warm-up
+    torch.cuda.synchronize()
+    hsma.timing_read()
+    hsma.timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        e, _, _ = plan.energy_forces(xd, qd)
+        print("fmm step %d done: energy %.10e" % (i, e), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    hsma.timing_enable(False)
+    kt = hsma.timing_read()
+    sched = plan.near_schedule(len(qd))
+    info = plan.info
+    plan.close()
+    return {"steps": steps, "ms_per_step": 1e3 * dt, "near_ms": kt["near"][0] / max(kt["near"][1], 1),
+            "rhs_ms": kt["rhs"][0] / max(kt["rhs"][1], 1), "near_kernel": "fmm" if sched["kind"] == 2 else sched,
+            "order": info["tree_order"], "precision": "fp64", "energy": e,
+            "rel_energy_diff_vs_direct_fp32_step": abs(e - e_direct) / abs(e_direct)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -579,6 +613,8 @@ def main():
     if host_entry is not None:
         host_entry["pairs_per_s"] = pairs_step / (host_entry["ms_per_call"] / 1e3)
         rec["config"]["host_entry"] = host_entry
+    if args.fmm_steps > 0 and args.workload == "periodic1m" and args.n <= 0 and near_mode == hsma.NEAR_BLOCK:
+        rec["fmm"] = fmm_measure(cfg, xd, qd, args.fmm_steps, energies[-1])
     del xd, qd, phi, F
     plan.close()
     if not args.no_cpu_baseline:
