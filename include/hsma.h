@@ -172,6 +172,12 @@ typedef struct {
     double* field_out;   /* N x 3 far fields */
 } hsma_intermediates;
 
+/* Profiler ranges: with HSMA_ROCTX=1 in the environment (read once per
+   process) the library loads the roctx library (rocprofiler-sdk or roctx64)
+   and marks every update step ("hsma: update step", "hsma: update step (fast
+   multipole)") and every server tick ("hsma: server tick") as a range over
+   the host code that enqueues it, for rocprofv3 --marker-trace. */
+
 /* Status text and the calling thread's last error message.  hsma_version()
    is the version of this interface; it changes whenever a declaration or a
    struct layout in this header changes (2: the near-schedule query and the

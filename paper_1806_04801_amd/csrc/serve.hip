@@ -493,6 +493,7 @@ static double request_work(const hsma_plan_s* pl, int N) {
 }
 
 static hsma_status tick(hsma_server_s* sv) {
+    const Range range("hsma: server tick");
     HSMA_HIP(hipSetDevice(sv->device));
     retire(sv);
     // flow control: at most two ticks in flight

@@ -56,6 +56,21 @@ struct Layout {
 struct NearFix {
     double own = 0.0, qc = 0.0;
 };
+// A named range for profilers (rocprofv3 --marker-trace) over a scope of host
+// code (the enqueueing of a stage): with HSMA_ROCTX=1 in the environment (read
+// once per process) the roctx library is loaded at first use; otherwise, or
+// if it cannot be loaded, a no-op.  name must outlive the range.
+class Range {
+  public:
+    explicit Range(const char* name);
+    ~Range();
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+
+  private:
+    bool on_ = false;
+};
+
 // The fixed near-potential terms for plan pl under layout ly.
 NearFix near_fix(const hsma_plan_s* pl, const Layout& ly);
 

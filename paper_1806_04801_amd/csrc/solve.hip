@@ -1,6 +1,8 @@
 // Update step of the HSMA (Sec. II.C) on one GPU: sources -> right-hand side
 // at the monitoring points -> least-squares coefficients -> surface images ->
 // near-field and surface sums at the particles -> energy and forces.
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -312,9 +314,48 @@ static bool overlap_enabled() {
             return fail(HSMA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));  \
     } while (0)
 
+// ---------------------------------------------------------------- profiler ranges
+namespace {
+struct RoctxApi {
+    int (*push)(const char*) = nullptr;
+    int (*pop)() = nullptr;
+};
+const RoctxApi& roctx_api() {
+    static const RoctxApi api = [] {
+        RoctxApi a;
+        const char* e = getenv("HSMA_ROCTX");
+        if (e == nullptr || atoi(e) != 1) return a;
+        for (const char* lib : {"librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"}) {
+            void* h = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+            if (h == nullptr) continue;
+            a.push = (int (*)(const char*))dlsym(h, "roctxRangePushA");
+            a.pop = (int (*)())dlsym(h, "roctxRangePop");
+            if (a.push != nullptr && a.pop != nullptr) break;
+            a.push = nullptr;
+            a.pop = nullptr;
+        }
+        return a;
+    }();
+    return api;
+}
+}  // namespace
+
+Range::Range(const char* name) {
+    const RoctxApi& a = roctx_api();
+    if (a.push != nullptr) {
+        a.push(name);
+        on_ = true;
+    }
+}
+
+Range::~Range() {
+    if (on_) roctx_api().pop();
+}
+
 hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, const void* q,
                     int dtype, char* ws, hipStream_t s, void* phi, void* forces,
                     const hsma_intermediates* dbg) {
+    const Range range(ly.tree ? "hsma: update step (fast multipole)" : "hsma: update step");
     if (dtype != HSMA_DTYPE_F64 && dtype != HSMA_DTYPE_F32)
         return fail(HSMA_E_INVALID, "dtype must be HSMA_DTYPE_F64 or HSMA_DTYPE_F32");
     const bool in32 = dtype == HSMA_DTYPE_F32;
