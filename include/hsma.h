@@ -76,7 +76,8 @@ typedef enum {
                               per leaf cell, 320 by default), direct sums between neighbouring
                               leaf cells, in double precision whatever the plan's precision;
                               below tree_min_n the direct kernels of HSMA_NEAR_BLOCK in the
-                              plan's precision; periodic, grounded cube and slab; no adjoint */
+                              plan's precision; at most (2^31 - 1) / 27 sources on the tree
+                              (HSMA_E_INVALID above); every box; no adjoint */
 } hsma_near_mode;
 
 typedef enum {

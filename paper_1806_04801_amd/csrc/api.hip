@@ -280,6 +280,9 @@ hsma_status hsma::check_sizes(const hsma_plan_s* pl, int64_t N) {
     const int64_t ns = (pl->bc == HSMA_BC_SLAB_METALLIC_Z) ? 2 * N : N;
     if (pl->near_mode == HSMA_NEAR_SPHERE && ns * pl->maxper > (int64_t)INT32_MAX)
         return fail(HSMA_E_INVALID, "too many sphere images for N");
+    // the tree sorts and indexes its 27 images per source with 32-bit integers
+    if (pl->near_mode == HSMA_NEAR_TREE && N >= pl->tree_min_n && 27 * ns > (int64_t)INT32_MAX)
+        return fail(HSMA_E_INVALID, "too many images for the tree (27 N_s must stay below 2^31)");
     return HSMA_OK;
 }
 

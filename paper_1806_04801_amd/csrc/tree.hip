@@ -929,8 +929,9 @@ TreeLayout tree_layout(int64_t ns, int p) {
     t.off_part = take(sizeof(double2) * (size_t)nc * part_cells);
     // hipCUB temporary storage of the sort
     size_t sort_bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                       (int*)nullptr, (int*)nullptr, (int)t.nimg, 0, 32);
+    if (t.nimg <= (int64_t)INT32_MAX)   // larger trees are refused before any launch
+        hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (int*)nullptr, (int*)nullptr, (int)t.nimg, 0, 32);
     t.cub_bytes = sort_bytes;
     t.off_cub = take(t.cub_bytes);
     t.total = o;

@@ -180,6 +180,14 @@ def test_tree_rejections(hs):
     x, q = W.uniform_neutral(100, 1.0, 3)
     with pytest.raises(hs.HsmaError):
         plan.energy_grad(torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda"))
+    # 27 N_s images must stay below 2^31 (32-bit sort and offsets): refused
+    # by the argument checks, before any pointer is used
+    import ctypes
+    e = ctypes.c_double()
+    xd, qd = torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda")
+    st = hs.load().hsma_energy_forces_device(plan._h, xd.data_ptr(), qd.data_ptr(), 80_000_000, None,
+                                             xd.data_ptr(), 1, ctypes.byref(e), None, None, None)
+    assert st == -1
     # the default threshold, and the near kernel either side of it
     assert hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE).info["tree_min_n"] == 16384
     p32 = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, precision=hs.FP32_COMP)
