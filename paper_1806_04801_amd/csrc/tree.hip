@@ -450,6 +450,7 @@ __global__ void k_fmm_itab(int p2, double2* __restrict__ tab) {
 }
 
 constexpr int FWG = 256;   // threads of a downward-pass work-group (>= outputs (p+1)(p+2)/2)
+static_assert(FWG >= 216, "the M2L checks its 216 candidates a thread each");
 constexpr int NF = (TREE_MAX_ORDER + 1) * (TREE_MAX_ORDER + 1);
 constexpr int NI = (2 * TREE_MAX_ORDER + 1) * (2 * TREE_MAX_ORDER + 1);
 
@@ -525,21 +526,30 @@ k_fmm_m2l(const double2* __restrict__ mom, const int* __restrict__ offs, int l, 
         for (int n = 0; n < t; ++n) v /= h;
         hpow[t] = v;   // h^-t
     }
-    __syncthreads();
     const int GG = 3 << l;
     const int shift = 3 * (L - l);
     const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
+    // the 216 candidates (children of the parent's neighbours) checked at once,
+    // a thread each: inside the cube, not a neighbour of the cell, not empty
+    __shared__ unsigned char cand_ok[216];
+    if (t < 216) {
+        const int cx = 2 * px - 2 + t / 36, cy = 2 * py - 2 + (t / 6) % 6, cz = 2 * pz - 2 + t % 6;
+        bool ok = cx >= 0 && cx < GG && cy >= 0 && cy < GG && cz >= 0 && cz < GG &&
+                  !(abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1);
+        if (ok) {
+            const uint32_t ck = cell_key(cx, cy, cz, l);
+            ok = offs[(size_t)(ck + 1) << shift] != offs[(size_t)ck << shift];
+        }
+        cand_ok[t] = ok ? 1 : 0;
+    }
+    __syncthreads();
     double br = 0.0, bi = 0.0;
     int item = 0;
     for (int cx = 2 * px - 2; cx <= 2 * px + 3; ++cx) {
-        if (cx < 0 || cx >= GG) continue;
         for (int cy = 2 * py - 2; cy <= 2 * py + 3; ++cy) {
-            if (cy < 0 || cy >= GG) continue;
             for (int cz = 2 * pz - 2; cz <= 2 * pz + 3; ++cz) {
-                if (cz < 0 || cz >= GG) continue;
-                if (abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1) continue;
+                if (!cand_ok[(cx - 2 * px + 2) * 36 + (cy - 2 * py + 2) * 6 + (cz - 2 * pz + 2)]) continue;
                 const uint32_t ck = cell_key(cx, cy, cz, l);
-                if (offs[(size_t)(ck + 1) << shift] == offs[(size_t)ck << shift]) continue;
                 if ((item++) % G != g) continue;
                 stage_signed(mom + (size_t)ck * nc, p, hpow, Mt);
                 const int o = (tx - cx + 3) * 49 + (ty - cy + 3) * 7 + (tz - cz + 3);
@@ -798,39 +808,52 @@ k_tree_points(const double4* __restrict__ pts, const double4* __restrict__ srt,
         const int c = (int)floor((v[a] + 1.5 * Lbox) / hL);
         g[a] = c < 0 ? 0 : (c >= GL ? GL - 1 : c);
     }
-    // list the far cells (every lane walks the same list and writes its share)
-    int nitem = 0;
-    {
-        const int bx = g[0] >> L, by = g[1] >> L, bz = g[2] >> L;
-        for (int cx = 0; cx < 3; ++cx)
-            for (int cy = 0; cy < 3; ++cy)
-                for (int cz = 0; cz < 3; ++cz) {
-                    if (abs(cx - bx) <= 1 && abs(cy - by) <= 1 && abs(cz - bz) <= 1) continue;
-                    const uint32_t ck = (uint32_t)(cx * 9 + cy * 3 + cz);
-                    if (offs[(size_t)(ck + 1) << (3 * L)] == offs[(size_t)ck << (3 * L)]) continue;
-                    if (nitem % 64 == lane) { item_key[nitem] = (int)ck; item_lev[nitem] = 0; }
-                    ++nitem;
-                }
+    // the candidates of every level checked at once, the lanes sharing them
+    // (inside the cube, not adjacent, not empty), then listed in order (every
+    // lane walks the flags and writes its share of the list)
+    __shared__ unsigned char okf[27 + 216 * TREE_MAX_LEVEL];
+    const int bx = g[0] >> L, by = g[1] >> L, bz = g[2] >> L;
+    for (int c = lane; c < 27; c += 64) {
+        const int cx = c / 9, cy = (c / 3) % 3, cz = c % 3;
+        bool ok = !(abs(cx - bx) <= 1 && abs(cy - by) <= 1 && abs(cz - bz) <= 1);
+        if (ok) ok = offs[(size_t)(c + 1) << (3 * L)] != offs[(size_t)c << (3 * L)];
+        okf[c] = ok ? 1 : 0;
     }
     for (int l = 1; l <= L; ++l) {
         const int G = 3 << l;
         const int shift = 3 * (L - l);
         const int tx = g[0] >> (L - l), ty = g[1] >> (L - l), tz = g[2] >> (L - l);
         const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
-        for (int cx = 2 * px - 2; cx <= 2 * px + 3; ++cx) {
-            if (cx < 0 || cx >= G) continue;
-            for (int cy = 2 * py - 2; cy <= 2 * py + 3; ++cy) {
-                if (cy < 0 || cy >= G) continue;
-                for (int cz = 2 * pz - 2; cz <= 2 * pz + 3; ++cz) {
-                    if (cz < 0 || cz >= G) continue;
-                    if (abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1) continue;
-                    const uint32_t ck = cell_key(cx, cy, cz, l);
-                    if (offs[(size_t)(ck + 1) << shift] == offs[(size_t)ck << shift]) continue;
-                    if (nitem % 64 == lane) { item_key[nitem] = (int)ck; item_lev[nitem] = (char)l; }
-                    ++nitem;
-                }
+        for (int c = lane; c < 216; c += 64) {
+            const int cx = 2 * px - 2 + c / 36, cy = 2 * py - 2 + (c / 6) % 6, cz = 2 * pz - 2 + c % 6;
+            bool ok = cx >= 0 && cx < G && cy >= 0 && cy < G && cz >= 0 && cz < G &&
+                      !(abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1);
+            if (ok) {
+                const uint32_t ck = cell_key(cx, cy, cz, l);
+                ok = offs[(size_t)(ck + 1) << shift] != offs[(size_t)ck << shift];
             }
+            okf[27 + 216 * (l - 1) + c] = ok ? 1 : 0;
         }
+    }
+    __syncthreads();
+    int nitem = 0;
+    for (int c = 0; c < 27; ++c)
+        if (okf[c]) {
+            if (nitem % 64 == lane) { item_key[nitem] = c; item_lev[nitem] = 0; }
+            ++nitem;
+        }
+    for (int l = 1; l <= L; ++l) {
+        const int tx = g[0] >> (L - l), ty = g[1] >> (L - l), tz = g[2] >> (L - l);
+        const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
+        for (int c = 0; c < 216; ++c)
+            if (okf[27 + 216 * (l - 1) + c]) {
+                if (nitem % 64 == lane) {
+                    item_key[nitem] = (int)cell_key(2 * px - 2 + c / 36, 2 * py - 2 + (c / 6) % 6,
+                                                    2 * pz - 2 + c % 6, l);
+                    item_lev[nitem] = (char)l;
+                }
+                ++nitem;
+            }
     }
     __syncthreads();
     const int nc = tri(p + 1, 0);
