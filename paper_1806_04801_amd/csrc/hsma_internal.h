@@ -167,6 +167,7 @@ struct hsma_plan_s {
     double* d_spos = nullptr;   // M x 4    surface points (X, Y, Z, 0)
     double4* d_chk64 = nullptr; // nchk     check points (x, y, z, 0)
     hsma::Rec32* d_chk32 = nullptr;  // nchk single-precision records
+    int* d_chk_order = nullptr;      // nchk check points in Morton order of position (tree right-hand side)
     size_t bytes = 0;
     // device buffer of the host-array entry point (inputs, outputs and
     // workspace), kept between calls and grown when a call needs more; calls

@@ -1,8 +1,11 @@
 // Preparation step of the HSMA (Sec. II.C, Table I) on the GPU: monitoring
 // points, fitting matrix of real solid harmonics, Householder QR, the
 // pseudo-inverse R^-1 Q^T, Hannay-Nye surface points and the mapping matrices.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "hsma_internal.h"
 
@@ -396,6 +399,7 @@ hsma_status build_plan(hsma_plan_s* pl) {
     if ((st = dmalloc(&pl->d_spos, (size_t)M * 4, &tot)) != HSMA_OK) { cleanup(); return st; }
     if ((st = dmalloc(&pl->d_chk64, (size_t)pl->nchk, &tot)) != HSMA_OK) { cleanup(); return st; }
     if ((st = dmalloc(&pl->d_chk32, (size_t)pl->nchk, &tot)) != HSMA_OK) { cleanup(); return st; }
+    if ((st = dmalloc(&pl->d_chk_order, (size_t)pl->nchk, &tot)) != HSMA_OK) { cleanup(); return st; }
     pl->bytes = tot;
 
 #define PLAN_HIP(call)                                                                      \
@@ -430,6 +434,28 @@ hsma_status build_plan(hsma_plan_s* pl) {
         }
         PLAN_HIP(hipMemcpy(pl->d_chk64, c4.data(), sizeof(double) * 4 * pl->nchk, hipMemcpyHostToDevice));
         PLAN_HIP(launch_make_rec32(pl->d_chk64, pl->nchk, pl->L, pl->d_chk32, s));
+        // the points in Morton order of position over their bounding box, so
+        // that the tree right-hand side visits neighbouring points together
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int i = 0; i < pl->nchk; ++i)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], pl->chk[3 * i + a]);
+                hi[a] = std::max(hi[a], pl->chk[3 * i + a]);
+            }
+        std::vector<std::pair<uint64_t, int>> key((size_t)pl->nchk);
+        for (int i = 0; i < pl->nchk; ++i) {
+            uint64_t k = 0;
+            for (int a = 0; a < 3; ++a) {
+                const double w = hi[a] > lo[a] ? (pl->chk[3 * i + a] - lo[a]) / (hi[a] - lo[a]) : 0.0;
+                const uint64_t q = (uint64_t)std::min(1048575.0, std::max(0.0, w * 1048576.0));
+                for (int b = 0; b < 20; ++b) k |= ((q >> b) & 1u) << (3 * b + 2 - a);
+            }
+            key[i] = {k, i};
+        }
+        std::sort(key.begin(), key.end());
+        std::vector<int> ord((size_t)pl->nchk);
+        for (int i = 0; i < pl->nchk; ++i) ord[i] = key[i].second;
+        PLAN_HIP(hipMemcpy(pl->d_chk_order, ord.data(), sizeof(int) * pl->nchk, hipMemcpyHostToDevice));
     }
     // Householder QR of F
     PLAN_HIP(hipMemset(d_R, 0, sizeof(double) * nu * nu));
@@ -494,6 +520,7 @@ void free_plan(hsma_plan_s* pl) {
     hipFree(pl->d_spos);
     hipFree(pl->d_chk64);
     hipFree(pl->d_chk32);
+    hipFree(pl->d_chk_order);
     hipFree(pl->host_buf);
 }
 

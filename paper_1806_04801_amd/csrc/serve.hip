@@ -648,7 +648,7 @@ static hsma_status tick(hsma_server_s* sv) {
                 const hsma_plan_s* pl = r->plan;
                 char* tws = carve(sv->arena_base + r->off, r->N).ws + r->ly.off_tree;
                 HSMA_HIP(launch_tree_build(pl->img, pl->gamma, r->d.src64, r->ly.ns, pl->L, r->ly.tl, tws, ss));
-                HSMA_HIP(launch_tree_points(pl->d_chk64, pl->nchk, pl->L, r->ly.tl, tws, r->d.rhs_part, ss));
+                HSMA_HIP(launch_tree_points(pl->d_chk64, pl->d_chk_order, pl->nchk, pl->L, r->ly.tl, tws, r->d.rhs_part, ss));
                 HSMA_HIP(launch_tree_near(r->N, pl->L, r->ly.tl, tws, r->d.near_part, r->ly.g_near.nt_pad, ss));
             } else if (f32)
                 HSMA_HIP(launch_sym_f32(r->ly.sym_img, r->d.src32, r->ly.g_sym, r->d.L, r->d.near_part, ss));

@@ -457,7 +457,7 @@ hsma_status forward(const hsma_plan_s* pl, const Layout& ly, const void* x, cons
     if (pl->img == IMG_DIELECTRIC)   // the far shells (direct or tree near sum alike)
         CK(launch_far_shells(pl->d_chk64, src64, g_rhs, pl->L, pl->gamma, pl->far_shells, rhs_part, s1));
     else if (ly.tree)
-        CK(launch_tree_points(pl->d_chk64, pl->nchk, pl->L, ly.tl, ws + ly.off_tree, rhs_part, s1));
+        CK(launch_tree_points(pl->d_chk64, pl->d_chk_order, pl->nchk, pl->L, ly.tl, ws + ly.off_tree, rhs_part, s1));
     else if (sphere)
         CK(launch_explicit(f32, false, false, f32 ? (const void*)pl->d_chk32 : (const void*)pl->d_chk64,
                            f32 ? (const void*)img32 : (const void*)img64, g_rhs, pl->L, rhs_part, s1));

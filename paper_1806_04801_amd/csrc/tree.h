@@ -38,9 +38,10 @@ hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, 
                              char* ws, hipStream_t s);
 
 // Potential of all images at npts points (centred coordinates, inside the
-// image cube): out[i], i < npts.
-hipError_t launch_tree_points(const double4* pts, int npts, double L, const TreeLayout& t, char* ws,
-                              double* out, hipStream_t s);
+// image cube): out[i], i < npts.  order: a permutation of 0..npts-1 in which
+// the points are visited (neighbouring points together share cached cells).
+hipError_t launch_tree_points(const double4* pts, const int* order, int npts, double L, const TreeLayout& t,
+                              char* ws, double* out, hipStream_t s);
 
 // phi and E at the first nt sources (the real particles) from all 27 images
 // of the ns sources, bare self term left out, in t.eval_split chunks whose sum

@@ -1000,13 +1000,19 @@ constexpr int PT_MAX_ITEMS = 27 + 189 * TREE_MAX_LEVEL;   // far cells of one po
 // LDS first and then shared out over the lanes; the lane sums are combined
 // by a fixed butterfly.
 __global__ void __launch_bounds__(64)
-k_tree_points(const double4* __restrict__ pts, const double4* __restrict__ srt,
-              const int* __restrict__ offs, MomPtrs moms, int L, int p, double Lbox,
-              double* __restrict__ out) {
+k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, int npts, int share,
+              const double4* __restrict__ srt, const int* __restrict__ offs, MomPtrs moms, int L, int p,
+              double Lbox, double* __restrict__ out) {
     __shared__ int item_key[PT_MAX_ITEMS];
     __shared__ char item_lev[PT_MAX_ITEMS];
     const int lane = threadIdx.x;
-    const double4 P = pts[blockIdx.x];
+    // work-groups go round the XCDs in turn: XCD x takes the points x * share
+    // .. (x + 1) * share - 1 of the given order, whose far cells overlap in
+    // its L2
+    const int pos = (blockIdx.x & 7) * share + (blockIdx.x >> 3);
+    if (pos >= npts) return;   // the whole (one-wave) work-group
+    const int pi = order[pos];
+    const double4 P = pts[pi];
     const int GL = 3 << L;
     const double hL = Lbox / (double)(1 << L);
     int g[3];
@@ -1101,7 +1107,7 @@ k_tree_points(const double4* __restrict__ pts, const double4* __restrict__ srt,
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) out[blockIdx.x] = acc;
+    if (lane == 0) out[pi] = acc;
 }
 
 // ---------------------------------------------------------------- host
@@ -1274,14 +1280,15 @@ hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, 
     return hipGetLastError();
 }
 
-hipError_t launch_tree_points(const double4* pts, int npts, double L, const TreeLayout& t, char* ws,
-                              double* out, hipStream_t s) {
+hipError_t launch_tree_points(const double4* pts, const int* order, int npts, double L, const TreeLayout& t,
+                              char* ws, double* out, hipStream_t s) {
     if (npts <= 0) return hipSuccess;
     MomPtrs mp;
     for (int l = 0; l <= TREE_MAX_LEVEL; ++l)
         mp.lev[l] = l <= t.L ? (const double2*)(ws + t.off_mom[l]) : nullptr;
-    hipLaunchKernelGGL(k_tree_points, dim3(npts), dim3(64), 0, s, pts, (const double4*)(ws + t.off_srt),
-                       (const int*)(ws + t.off_offs), mp, t.L, t.p, L, out);
+    const int share = (npts + 7) / 8;
+    hipLaunchKernelGGL(k_tree_points, dim3(8 * share), dim3(64), 0, s, pts, order, npts, share,
+                       (const double4*)(ws + t.off_srt), (const int*)(ws + t.off_offs), mp, t.L, t.p, L, out);
     return hipGetLastError();
 }
 
