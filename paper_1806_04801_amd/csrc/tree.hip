@@ -233,25 +233,32 @@ k_tree_p2m_wave(const double4* __restrict__ srt, const int* __restrict__ offs, i
     }
 }
 
-// For many leaf cells: thread (cell, m), m = blockIdx.y uniform over the wave:
-// column m of the moments of leaf cell `cell`, summed over its sources in
-// sorted order.  The loops over n are unrolled to the largest order (guards n
-// <= p are uniform), so the accumulators stay in registers; the recurrence's
-// reciprocals depend on (n, m) only and are formed once per thread.
+// For many leaf cells: thread (cell, m), m uniform over the wave: column m of
+// the moments of leaf cell `cell`, summed over its sources in sorted order.
+// The loops over n are unrolled to the largest order (guards n <= p are
+// uniform), so the accumulators stay in registers; the recurrence's
+// reciprocals depend on (n, m) only and are formed once per thread.  Work-
+// groups go round the XCDs in turn; the p + 1 columns of a block of 64 cells
+// are consecutive on one XCD, so that they read the cells' sources through
+// one L2.
+template <int P>   // largest order the registers hold (p <= P)
 __global__ void __launch_bounds__(64)
 k_tree_p2m_cols(const double4* __restrict__ srt, const int* __restrict__ offs, int lev, int ncell, int p,
                 double L, double2* __restrict__ mom) {
-    const int m = blockIdx.y;
-    const int64_t cell = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int r = blockIdx.x >> 3;
+    const int m = r % (p + 1);
+    const int64_t cell = ((int64_t)(r / (p + 1)) * 8 + (blockIdx.x & 7)) * 64 + threadIdx.x;
     if (cell >= ncell || m > p) return;
     const int b = offs[cell], e = offs[cell + 1];
     double2* out = mom + (size_t)cell * tri(p + 1, 0);
-    constexpr int P = TREE_MAX_ORDER;
+    const int pm = p - m;   // orders n = m + i, i = 0..pm
     double ar[P + 1], ai[P + 1], rinv[P + 1];
+    double dscale = 1.0;   // 1 / (2^m m!)
+    for (int k = 1; k <= m; ++k) dscale *= 0.5 / (double)k;
 #pragma unroll
-    for (int n = 0; n <= P; ++n) {
-        ar[n] = ai[n] = 0.0;
-        rinv[n] = (n > m) ? 1.0 / ((double)(n + m) * (double)(n - m)) : 0.0;
+    for (int i = 0; i <= P; ++i) {
+        ar[i] = ai[i] = 0.0;
+        rinv[i] = i > 0 ? 1.0 / ((double)(2 * m + i) * (double)i) : 0.0;   // 1 / ((n + m)(n - m))
     }
     if (b < e) {
         // cell centre from its key: box index and Morton code within the box
@@ -267,40 +274,40 @@ k_tree_p2m_cols(const double4* __restrict__ srt, const int* __restrict__ offs, i
         const double cx = -1.5 * L + ((double)((box / 9) * (1u << lev) + ix) + 0.5) * h;
         const double cy = -1.5 * L + ((double)(((box / 3) % 3) * (1u << lev) + iy) + 0.5) * h;
         const double cz = -1.5 * L + ((double)((box % 3) * (1u << lev) + iz) + 0.5) * h;
+        double4 yn = srt[b];   // the next source, read one step ahead
         for (int s = b; s < e; ++s) {
-            const double4 y = srt[s];
+            const double4 y = yn;
+            yn = srt[min(s + 1, e - 1)];
             const double x = y.x - cx, yy = y.y - cy, z = y.z - cz;
             const double r2 = x * x + yy * yy + z * z;
             // R_m^m = (x + iy)^m / (2^m m!)
-            double dr = 1.0, di = 0.0;
-#pragma unroll
-            for (int k = 1; k <= P; ++k) {
-                if (k <= m) {
-                    const double c = 0.5 / (double)k;
-                    const double nr = (dr * x - di * yy) * c;
-                    const double ni = (dr * yy + di * x) * c;
-                    dr = nr;
-                    di = ni;
-                }
+            double wr = 1.0, wi = 0.0;
+            for (int k = 0; k < m; ++k) {
+                const double nr = __builtin_fma(wr, x, -wi * yy);
+                wi = __builtin_fma(wr, yy, wi * x);
+                wr = nr;
             }
-            double pr = 0.0, pi = 0.0, cr = dr, ci = di;   // R_{n-2}, R_{n-1}
+            double pr = 0.0, pi = 0.0, cr = wr * dscale, ci = wi * dscale;   // R_{n-2}, R_{n-1}
+            double zz = (double)(2 * m - 1) * z;   // (2n - 1) z, raised by 2z per order
+            const double z2 = 2.0 * z;
 #pragma unroll
-            for (int n = 0; n <= P; ++n) {
-                if (n < m || n > p) continue;
-                if (n > m) {
-                    const double nr = ((2 * n - 1) * z * cr - r2 * pr) * rinv[n];
-                    const double ni = ((2 * n - 1) * z * ci - r2 * pi) * rinv[n];
+            for (int i = 0; i <= P; ++i) {
+                if (i > pm) continue;
+                if (i > 0) {
+                    zz += z2;
+                    const double nr = __builtin_fma(zz, cr, -r2 * pr) * rinv[i];
+                    const double ni = __builtin_fma(zz, ci, -r2 * pi) * rinv[i];
                     pr = cr; pi = ci; cr = nr; ci = ni;
                 }
                 // M += q conj(R)
-                ar[n] = __builtin_fma(y.w, cr, ar[n]);
-                ai[n] = __builtin_fma(-y.w, ci, ai[n]);
+                ar[i] = __builtin_fma(y.w, cr, ar[i]);
+                ai[i] = __builtin_fma(-y.w, ci, ai[i]);
             }
         }
     }
 #pragma unroll
-    for (int n = 0; n <= P; ++n)
-        if (n >= m && n <= p) out[tri(n, m)] = make_double2(ar[n], ai[n]);
+    for (int i = 0; i <= P; ++i)
+        if (i <= pm) out[tri(m + i, m)] = make_double2(ar[i], ai[i]);
 }
 
 // ---------------------------------------------------------------- translation
@@ -1256,9 +1263,15 @@ hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, 
     if (t.ncell_leaf <= 32768)
         hipLaunchKernelGGL(k_tree_p2m_wave, dim3((unsigned)t.ncell_leaf), dim3(64), 0, s, srt, offs, t.L, t.p,
                            L, (double2*)(ws + t.off_mom[t.L]));
-    else
-        hipLaunchKernelGGL(k_tree_p2m_cols, dim3((unsigned)((t.ncell_leaf + 63) / 64), t.p + 1), dim3(64), 0, s,
-                           srt, offs, t.L, (int)t.ncell_leaf, t.p, L, (double2*)(ws + t.off_mom[t.L]));
+    else {
+        const dim3 grid((unsigned)((t.ncell_leaf + 511) / 512 * 8 * (t.p + 1)));
+        if (t.p <= 16)
+            hipLaunchKernelGGL(k_tree_p2m_cols<16>, grid, dim3(64), 0, s, srt, offs, t.L, (int)t.ncell_leaf, t.p,
+                               L, (double2*)(ws + t.off_mom[t.L]));
+        else
+            hipLaunchKernelGGL(k_tree_p2m_cols<TREE_MAX_ORDER>, grid, dim3(64), 0, s, srt, offs, t.L,
+                               (int)t.ncell_leaf, t.p, L, (double2*)(ws + t.off_mom[t.L]));
+    }
     double2* dtab = (double2*)(ws + t.off_tab);
     hipLaunchKernelGGL(k_tree_m2m_table, dim3(1), dim3(64), 0, s, t.p, dtab);
     const size_t lds_m2m = sizeof(double2) * 8 * (size_t)(t.p + 1) * (t.p + 1);
