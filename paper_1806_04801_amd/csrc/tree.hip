@@ -397,20 +397,22 @@ __global__ void k_tree_m2m_coef(const double2* __restrict__ child, const int* __
         const double2* T = tab + (size_t)o * (p + 1) * (p + 1);
         double sj = 1.0;
         for (int j = 0; j <= n; ++j) {
-            for (int k = -j; k <= j; ++k) {
-                const int mm = m - k, nn = n - j;
-                if (mm > nn || -mm > nn) continue;
+            // the k with |m - k| <= n - j only
+            const int nn = n - j;
+            const int k0 = max(-j, m - nn), k1 = min(j, m + nn);
+            double er = 0.0, ei = 0.0;
+            for (int k = k0; k <= k1; ++k) {
+                const int mm = m - k;
                 const double2 a = T[j * j + j + k];
                 // M~_nn^mm: stored for mm >= 0; (-1)^mm conj(M_nn^-mm) below
-                double2 b = M[tri(nn, mm < 0 ? -mm : mm)];
-                if (mm < 0) {
-                    b.y = -b.y;
-                    if ((-mm) & 1) { b.x = -b.x; b.y = -b.y; }
-                }
-                const double ar = a.x * sj, ai = a.y * sj;
-                sr += ar * b.x - ai * b.y;
-                si += ar * b.y + ai * b.x;
+                const double2 v = M[tri(nn, mm < 0 ? -mm : mm)];
+                const double sx = (mm < 0 && (mm & 1)) ? -1.0 : 1.0;
+                const double bx = sx * v.x, by = (mm < 0 ? -sx : sx) * v.y;
+                er += a.x * bx - a.y * by;
+                ei += a.x * by + a.y * bx;
             }
+            sr += sj * er;
+            si += sj * ei;
             sj *= side;
         }
     }
