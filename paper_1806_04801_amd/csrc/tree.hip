@@ -938,9 +938,7 @@ k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
                     if (cx < 0 || cx >= G || cy < 0 || cy >= G || cz < 0 || cz >= G) continue;
                     const uint32_t ck = cell_key(cx, cy, cz, L);
                     const int e0 = offs[ck], e1 = offs[ck + 1];
-                    for (int j = e0; j < e1; ++j) {
-                        if (j == s) continue;   // the bare self term
-                        const double4 r = srt[j];
+                    auto term = [&](const double4& r) {
                         const double dx = t.x - r.x, dy = t.y - r.y, dz = t.z - r.z;
                         const double d2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
                         const double y = rsqrt_f64(d2);
@@ -950,6 +948,20 @@ k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
                         ex = __builtin_fma(w, dx, ex);
                         ey = __builtin_fma(w, dy, ey);
                         ez = __builtin_fma(w, dz, ez);
+                    };
+                    if (cx == gx && cy == gy && cz == gz) {
+                        // the target's own cell: skip the bare self term
+                        for (int j = e0; j < e1; ++j)
+                            if (j != s) term(srt[j]);
+                    } else {
+                        // two sources a step, summed in order
+                        int j = e0;
+                        for (; j + 1 < e1; j += 2) {
+                            const double4 r0 = srt[j], r1 = srt[j + 1];
+                            term(r0);
+                            term(r1);
+                        }
+                        if (j < e1) term(srt[j]);
                     }
                 }
             }
