@@ -39,6 +39,24 @@ __device__ __forceinline__ void diffs_f64(double t, double s, double L, double (
 
 __device__ __forceinline__ float rsq_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq_t(double x) { return rsqrt_f64(x); }
+
+// rsqrt_f64 of x[lo..hi-1] (same operations, same results), the chains
+// advancing side by side, a step each in turn, so that no step waits on the
+// one before it in the same chain.
+template <int lo, int hi>
+__device__ __forceinline__ void rsq_col(const double (&x)[3], double (&y)[3]) {
+    double y0[3], e[3], c3[3], ye[3];
+#pragma unroll
+    for (int c = lo; c < hi; ++c) y0[c] = (double)__builtin_amdgcn_rsqf((float)x[c]);
+#pragma unroll
+    for (int c = lo; c < hi; ++c) e[c] = __builtin_fma(-(x[c] * y0[c]), y0[c], 1.0);
+#pragma unroll
+    for (int c = lo; c < hi; ++c) c3[c] = __builtin_fma(e[c], 0.375, 0.5);
+#pragma unroll
+    for (int c = lo; c < hi; ++c) ye[c] = y0[c] * e[c];
+#pragma unroll
+    for (int c = lo; c < hi; ++c) y[c] = __builtin_fma(ye[c], c3[c], y0[c]);
+}
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -103,11 +121,20 @@ __device__ __forceinline__ void images_sum(const R (&dx)[3], const R (&dy)[3], c
 #pragma unroll
         for (int b = lo; b < hi; ++b) {
             const R sxy = fma_t(dy[b], dy[b], sx[a]);
+            // double: the column's reciprocal square roots first, side by
+            // side; single precision: one image at a time (one instruction)
+            constexpr bool COL = sizeof(R) == sizeof(double);
+            R r2v[3], yv[3];
+            if constexpr (COL) {
+#pragma unroll
+                for (int c = lo; c < hi; ++c) r2v[c] = fma_t(dz[c], dz[c], sxy);
+                rsq_col<lo, hi>(r2v, yv);
+            }
 #pragma unroll
             for (int c = lo; c < hi; ++c) {
-                const R r2 = fma_t(dz[c], dz[c], sxy);
+                const R r2 = COL ? r2v[c] : fma_t(dz[c], dz[c], sxy);
                 if (a == 1 && b == 1 && c == 1) r2c = r2;
-                R y = rsq_t(r2);
+                R y = COL ? yv[c] : rsq_t(r2);
                 if (SELF && a == 1 && b == 1 && c == 1) y = (r2 > R(0)) ? y : R(0);
                 const bool neg = (IMG == IMG_METALLIC) && (((a != 1) + (b != 1) + (c != 1)) & 1);
                 const int nref = (a != 1) + (b != 1) + (c != 1);
