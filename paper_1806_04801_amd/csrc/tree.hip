@@ -39,6 +39,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <vector>
@@ -1139,19 +1140,29 @@ static size_t m2l_tile_lds(int p) {
     return sizeof(double2) * (nip + (size_t)M2L_NT * tri(p + 1, 0));
 }
 
+// LDS one work-group may take on the current device, asked once per device.
+static size_t lds_per_block() {
+    static std::atomic<int> known[64];   // 0: not asked yet
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    int v = known[dev].load();
+    if (v > 0) return (size_t)v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        v = 65536;
+    known[dev].store(v);
+    return (size_t)v;
+}
+
 // The blocked M2L serves the levels with at least M2L_NT cells per parent
-// corner, within the LDS a work-group may take without opting in (its
-// static tables included).
-static bool m2l_tiled(int l, int p) { return l >= 3 && m2l_tile_lds(p) + 2048 <= 65536; }
+// corner, within the LDS a work-group may take (its static tables included);
+// above 64 KB it is asked for explicitly at launch.
+static bool m2l_tiled(int l, int p) { return l >= 3 && m2l_tile_lds(p) + 2048 <= lds_per_block(); }
 
 // Work-groups per cell (direct M2L) or per tile of M2L_NT cells (blocked
 // M2L) at level l: enough that a level of few cells still spreads over the
 // GPU.
-static int fmm_split(int l, int p) {
-    const int cells = 1 << (3 * l);
-    if (m2l_tiled(l, p)) return std::max(1, std::min(32, 2048 / (cells / M2L_NT)));
-    return std::max(1, std::min(16, 2048 / cells));
-}
+static int split_cell(int l) { return std::max(1, std::min(16, 2048 / (1 << (3 * l)))); }
+static int split_tile(int l) { return std::max(1, std::min(32, 2048 / ((1 << (3 * l)) / M2L_NT))); }
 
 int tree_leaf_level(int64_t ns) {
     // at most tree_leaf_images() images per leaf cell (ns / 8^L: the 27 ns
@@ -1196,7 +1207,9 @@ TreeLayout tree_layout(int64_t ns, int p) {
     t.off_tab = take(sizeof(double2) * 8 * (size_t)(p + 1) * (p + 1));
     t.off_itab = take(sizeof(double2) * 343 * (size_t)(2 * p + 1) * (2 * p + 1));
     size_t part_cells = 0;
-    for (int l = 1; l <= t.L; ++l) part_cells = std::max(part_cells, (size_t)fmm_split(l, p) << (3 * l));
+    for (int l = 1; l <= t.L; ++l)   // room for either M2L's parts
+        part_cells = std::max(part_cells, (size_t)std::max(split_cell(l), m2l_tiled(l, p) ? split_tile(l) : 0)
+                                              << (3 * l));
     t.off_part = take(sizeof(double2) * (size_t)nc * part_cells);
     // hipCUB temporary storage of the sort
     size_t sort_bytes = 0;
@@ -1331,10 +1344,18 @@ hipError_t launch_tree_near(int nt, double L, const TreeLayout& t, char* ws, dou
     for (int l = 1; l <= t.L; ++l) {
         double2* loc = (double2*)(ws + t.off_loc[l]);
         const double2* ploc = l >= 2 ? (const double2*)(ws + t.off_loc[l - 1]) : nullptr;
-        const int G = fmm_split(l, t.p);
-        if (m2l_tiled(l, t.p)) {
+        bool tiled = m2l_tiled(l, t.p);
+        const size_t tlds = m2l_tile_lds(t.p);
+        if (tiled && tlds > 65536 &&
+            hipFuncSetAttribute((const void*)k_fmm_m2l_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)tlds) != hipSuccess) {
+            (void)hipGetLastError();   // not granted: the per-cell M2L (the parts have room for it)
+            tiled = false;
+        }
+        const int G = tiled ? split_tile(l) : split_cell(l);
+        if (tiled) {
             const int nthr = (m2l_groups(t.p) * M2L_TG + 63) / 64 * 64;
-            hipLaunchKernelGGL(k_fmm_m2l_tile, dim3((1u << (3 * l)) / M2L_NT, G), dim3(nthr), m2l_tile_lds(t.p), s,
+            hipLaunchKernelGGL(k_fmm_m2l_tile, dim3((1u << (3 * l)) / M2L_NT, G), dim3(nthr), tlds, s,
                                (const double2*)(ws + t.off_mom[l]), offs, l, t.L, t.p, L, itab, G, part);
         } else {
             const size_t lds = sizeof(double2) * ((size_t)(t.p + 1) * (t.p + 1) +

@@ -148,6 +148,24 @@ def test_tree_near_sum_sampled_at_size(hs, bc, n, ns):
     assert eb <= TOL_B[bc]
 
 
+def test_tree_high_orders_at_size(hs):
+    """Orders above 16 at 1e5 particles (leaf level 3, whose M2L is the
+    blocked kernel, with more than 64 KB of LDS per work-group where the
+    device grants it): within the tolerances, and order 20 no worse than 16."""
+    announce("tree high orders n=100000")
+    x, q = system(0, 100_000, 81)
+    idx = np.sort(np.random.default_rng(6).choice(100_000, 256, replace=False))
+    ref_p, ref_f = direct_near(0, x, q, idx)
+    errs = {}
+    for order in (16, 18, 20):
+        plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_order=order, tree_min_n=1)
+        _, pn, fn = near_parts(hs, plan, x, q)
+        errs[order] = check("high orders n=100000", q, idx, pn, fn, ref_p, ref_f, order)
+        plan.close()
+        assert errs[order]["phi"] <= TOL_PHI and errs[order]["E"] <= TOL_E and errs[order]["En"] <= TOL_EN
+    assert errs[20]["phi"] <= errs[16]["phi"] and errs[20]["E"] <= errs[16]["E"]
+
+
 @pytest.mark.parametrize("bc", [0, 1, 2])
 def test_tree_whole_step_vs_direct_step(hs, bc):
     """The whole update step in tree mode (near sum and right-hand side from
