@@ -39,7 +39,6 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <vector>
@@ -594,110 +593,90 @@ k_fmm_m2l(const double2* __restrict__ mom, const int* __restrict__ offs, int l, 
 // takes M2L_NT cells of the central box that sit at the same corner of their
 // parents, so that they share one list of interaction offsets D = c_T - c_S
 // (per axis D in [b - 3, b + 2] for the cell's corner bit b, minus the 27
-// neighbours: 189 offsets), and the offsets g, g + G, ... of that list.  Per
-// offset it stages I~(D) and the M2L_NT source moments (scaled by h^-n; an
-// empty source cell counts as zero), and each thread accumulates M2L_R
-// consecutive orders j of one k for M2L_C of the cells, so that every value
-// read from LDS serves several products:
-//   part_g L_j^k = (-1)^{j+k} h^-(j+1) sum_D sum_{n <= p, m} M~_n^m(T - D) I~_{n+j}^{m-k}(D).
-// The loop over m is outermost; along n the M2L_R values I~_{n+j}^{m-k} of a
-// thread slide by one order.
+// neighbours: 189 offsets), and the offsets g, g + G, ... of that list; each
+// of its waves takes M2L_C of the cells.  Per offset the work-group stages
+// I~(D) h^-N in LDS (orders N <= 2p, zero up to 2p + R), and each lane of a
+// wave accumulates R consecutive orders j of one k for the wave's cells:
+//   part_g L_j^k = (-1)^{j+k} h^-1 sum_D sum_{n <= p, m} M~_n^m(T - D) (I~_{n+j}^{m-k}(D) h^-(n+j)),
+// the same sum as (-1)^{j+k} h^-(j+1) sum (M~_n^m h^-n) I~_{n+j}^{m-k}(D) with
+// the cell side's powers moved into the table.  The source moments are the
+// same for every lane of a wave, so they are read through the scalar cache
+// from the multipole array itself (an empty cell's moments are zero); only
+// the I~ values come from LDS, R of them sliding by one order along n.  The
+// loop over m is outermost.  For m < 0 the source term is s conj(M_n^|m|),
+// s = (-1)^m; with y = (s Re I~, -s Im I~) the real part of I~ s conj(M) is
+// that of y M and the imaginary part minus it, so the imaginary sums run
+// negated through the columns m < 0 and one loop body serves every column.
 constexpr int M2L_NT = 16;                  // target cells per work-group
-constexpr int M2L_R = 3;                    // orders j per thread
-constexpr int M2L_C = 4;                    // target cells per thread
-constexpr int M2L_TG = M2L_NT / M2L_C;      // thread groups over the cells
-constexpr int M2L_BLOCK = 512;
+constexpr int M2L_C = 4;                    // target cells per wave
+constexpr int M2L_WAVES = M2L_NT / M2L_C;
 
-__host__ __device__ constexpr int m2l_groups(int p) {
+// Orders j per lane: 3 while the (k, j0) groups fit one wave, else 5.
+__host__ __device__ constexpr int m2l_rows(int p) { return p <= 17 ? 3 : 5; }
+__host__ __device__ constexpr int m2l_groups(int p, int R) {
     int ng = 0;
-    for (int k = 0; k <= p; ++k) ng += (p - k + M2L_R) / M2L_R;
+    for (int k = 0; k <= p; ++k) ng += (p - k + R) / R;
     return ng;
 }
-static_assert(m2l_groups(TREE_MAX_ORDER) * M2L_TG <= M2L_BLOCK, "one thread per (k, j0) group and cell group");
+static_assert(m2l_groups(17, 3) <= 64 && m2l_groups(TREE_MAX_ORDER, 5) <= 64, "a (k, j0) group per lane");
 
-// One column m of the blocked M2L: acc += I~_{n+j}^{m-k} x (source term of
-// order n) for n = |m|..p.  For m < 0 the source term is s conj(M_n^|m|),
-// s = (-1)^m; with y = (s Re I~, -s Im I~) the real part of I~ s conj(M) is
-// that of y M and the imaginary part is minus that of y M, so the caller
-// keeps the imaginary sums negated while m < 0 and one loop body serves
-// every column.  Two register sets alternate over the orders: the next
-// order's reads are issued (the scheduling barrier keeps them there) before
-// this order's products.
-__device__ __forceinline__ void m2l_load(const double2* __restrict__ mb, int msr, int c0,
-                                         double (&br)[M2L_C], double (&bi)[M2L_C]) {
-#pragma unroll
-    for (int c = 0; c < M2L_C; ++c) {
-        const double2 v = mb[c * M2L_TG * msr + c0];
-        br[c] = v.x;
-        bi[c] = v.y;
-    }
-}
-
-__device__ __forceinline__ void m2l_step(const double2* __restrict__ It, int N, int mu, double sr, double si,
-                                         const double (&br)[M2L_C], const double (&bi)[M2L_C],
-                                         double (&xr)[M2L_R], double (&xi)[M2L_R],
-                                         double (&ar)[M2L_R][M2L_C], double (&ai)[M2L_R][M2L_C]) {
-    const double2 top = It[N * N + N + mu];   // the next order's top value (padded table)
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int r = 0; r < M2L_R; ++r)
-#pragma unroll
-        for (int c = 0; c < M2L_C; ++c) {
-            ar[r][c] = __builtin_fma(xr[r], br[c], __builtin_fma(-xi[r], bi[c], ar[r][c]));
-            ai[r][c] = __builtin_fma(xi[r], br[c], __builtin_fma(xr[r], bi[c], ai[r][c]));
-        }
-#pragma unroll
-    for (int r = 0; r + 1 < M2L_R; ++r) {
-        xr[r] = xr[r + 1];
-        xi[r] = xi[r + 1];
-    }
-    xr[M2L_R - 1] = sr * top.x;
-    xi[M2L_R - 1] = si * top.y;
-}
-
-__device__ __forceinline__ void m2l_column(const double2* __restrict__ It, const double2* __restrict__ Ms,
-                                           int msr, int p, int m, int k, int j0, int tg,
-                                           double (&ar)[M2L_R][M2L_C], double (&ai)[M2L_R][M2L_C]) {
+template <int R>
+__device__ __forceinline__ void m2l_column(const double2* __restrict__ It, const double2* const (&ms)[M2L_C],
+                                           int p, int m, int k, int j0, double (&ar)[R][M2L_C],
+                                           double (&ai)[R][M2L_C]) {
     const int am = m < 0 ? -m : m;
     const int mu = m - k;
     const double sr = (m < 0 && (am & 1)) ? -1.0 : 1.0;
     const double si = m < 0 ? -sr : sr;
-    double xr[M2L_R], xi[M2L_R];
+    double xr[R], xi[R];
 #pragma unroll
-    for (int r = 0; r < M2L_R; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int N = am + j0 + r;
         const double2 v = It[N * N + N + mu];
         xr[r] = sr * v.x;
         xi[r] = si * v.y;
     }
-    const double2* mb = Ms + tg * msr;
-    double b0r[M2L_C], b0i[M2L_C], b1r[M2L_C], b1i[M2L_C];
-    m2l_load(mb, msr, tri(am, am), b0r, b0i);
-    for (int n = am;; n += 2) {
-        m2l_load(mb, msr, tri(min(n + 1, p), am), b1r, b1i);
-        m2l_step(It, n + j0 + M2L_R, mu, sr, si, b0r, b0i, xr, xi, ar, ai);
-        if (n + 1 > p) break;
-        m2l_load(mb, msr, tri(min(n + 2, p), am), b0r, b0i);
-        m2l_step(It, n + 1 + j0 + M2L_R, mu, sr, si, b1r, b1i, xr, xi, ar, ai);
-        if (n + 2 > p) break;
+#pragma unroll 4
+    for (int n = am; n <= p; ++n) {
+        const int cb = tri(n, am);
+        double br[M2L_C], bi[M2L_C];
+#pragma unroll
+        for (int c = 0; c < M2L_C; ++c) {
+            const double2 v = ms[c][cb];
+            br[c] = v.x;
+            bi[c] = v.y;
+        }
+        const int N = n + j0 + R;   // the next order's top value (padded table)
+        const double2 top = It[N * N + N + mu];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < M2L_C; ++c) {
+                ar[r][c] = __builtin_fma(xr[r], br[c], __builtin_fma(-xi[r], bi[c], ar[r][c]));
+                ai[r][c] = __builtin_fma(xi[r], br[c], __builtin_fma(xr[r], bi[c], ai[r][c]));
+            }
+#pragma unroll
+        for (int r = 0; r + 1 < R; ++r) {
+            xr[r] = xr[r + 1];
+            xi[r] = xi[r + 1];
+        }
+        xr[R - 1] = sr * top.x;
+        xi[R - 1] = si * top.y;
     }
 }
 
-__global__ void __launch_bounds__(M2L_BLOCK)
-k_fmm_m2l_tile(const double2* __restrict__ mom, const int* __restrict__ offs, int l, int L, int p,
-               double Lbox, const double2* __restrict__ itab, int G, double2* __restrict__ part) {
-    extern __shared__ double2 lds[];
+template <int R>
+__global__ void __launch_bounds__(64 * M2L_WAVES)
+k_fmm_m2l_tile(const double2* __restrict__ mom, int l, int p, double Lbox, const double2* __restrict__ itab,
+               int G, double2* __restrict__ part) {
+    extern __shared__ double2 It[];   // (2p + R + 1)^2
+    __shared__ int dlist[189];
+    __shared__ double hpow[2 * TREE_MAX_ORDER + 6];
     const int nc = tri(p + 1, 0);
     const int ni = (2 * p + 1) * (2 * p + 1);
-    const int nip = (2 * p + M2L_R + 1) * (2 * p + M2L_R + 1);   // orders up to 2p + R, padded with zeros
-    const int msr = nc;                                           // row of a cell's moments
-    double2* It = lds;
-    double2* Ms = lds + nip;
-    __shared__ int dlist[189];
-    __shared__ int tcell[M2L_NT][3];
-    __shared__ char nof[(TREE_MAX_ORDER + 1) * (TREE_MAX_ORDER + 2) / 2];
-    __shared__ double hpow[TREE_MAX_ORDER + 1];
-    const int t = threadIdx.x, nt = blockDim.x;
+    const int nip = (2 * p + R + 1) * (2 * p + R + 1);
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int cls = blockIdx.x & 7, tile = blockIdx.x >> 3, g = blockIdx.y;
     const double h = Lbox / (double)(1 << l);
     const int bx = (cls >> 2) & 1, by = (cls >> 1) & 1, bz = cls & 1;
@@ -710,87 +689,77 @@ k_fmm_m2l_tile(const double2* __restrict__ mom, const int* __restrict__ offs, in
                     dlist[c++] = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
                 }
     }
-    if (t < M2L_NT) {
-        const int cid = (tile * M2L_NT + t) * 8 + cls;
-        central_cell(cid, l, tcell[t][0], tcell[t][1], tcell[t][2]);
-    }
-    for (int c = t; c < nc; c += nt) {
-        int n = 0;
-        while (tri(n + 1, 0) <= c) ++n;
-        nof[c] = (char)n;
-    }
-    if (t <= p) {
+    for (int N = t; N <= 2 * p + R; N += blockDim.x) {
         double v = 1.0;
-        for (int n = 0; n < t; ++n) v /= h;
-        hpow[t] = v;   // h^-t
+        for (int i = 0; i < N; ++i) v /= h;
+        hpow[N] = v;   // h^-N
     }
-    // this thread's (k, j0) group and cells
-    const int tg = t % M2L_TG, gi = t / M2L_TG;
+    // the wave's cells
+    int tc[M2L_C][3];
+#pragma unroll
+    for (int c = 0; c < M2L_C; ++c)
+        central_cell((tile * M2L_NT + wave * M2L_C + c) * 8 + cls, l, tc[c][0], tc[c][1], tc[c][2]);
+    // this lane's (k, j0) group
     int k = 0, j0 = 0;
     bool act = false;
     {
         int c = 0;
         for (int kk = 0; kk <= p && !act; ++kk)
-            for (int jj = kk; jj <= p; jj += M2L_R, ++c)
-                if (c == gi) { k = kk; j0 = jj; act = true; break; }
+            for (int jj = kk; jj <= p; jj += R, ++c)
+                if (c == lane) { k = kk; j0 = jj; act = true; break; }
     }
-    double ar[M2L_R][M2L_C], ai[M2L_R][M2L_C];
+    double ar[R][M2L_C], ai[R][M2L_C];
 #pragma unroll
-    for (int r = 0; r < M2L_R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < M2L_C; ++c) ar[r][c] = ai[r][c] = 0.0;
-    const int shift = 3 * (L - l);
     for (int it = g; it < 189; it += G) {
-        __syncthreads();   // the lists above, or the previous offset's reads, are done
+        __syncthreads();   // the tables above, or the previous offset's reads, are done
         const int o = dlist[it];
         const int dx = o / 49 - 3, dy = (o / 7) % 7 - 3, dz = o % 7 - 3;
         const double2* I = itab + (size_t)o * ni;
-        for (int idx = t; idx < nip; idx += nt) {
+        for (int idx = t; idx < nip; idx += blockDim.x) {
             int N = 0;
             while ((N + 1) * (N + 1) <= idx) ++N;
-            It[idx] = N <= 2 * p ? I[idx] : make_double2(0.0, 0.0);
-        }
-        for (int idx = t; idx < M2L_NT * nc; idx += nt) {
-            const int i = idx / nc, c = idx - i * nc;
-            const uint32_t ck = cell_key(tcell[i][0] - dx, tcell[i][1] - dy, tcell[i][2] - dz, l);
             double2 v = make_double2(0.0, 0.0);
-            if (offs[(size_t)(ck + 1) << shift] != offs[(size_t)ck << shift]) {
-                v = mom[(size_t)ck * nc + c];
-                const double f = hpow[nof[c]];
-                v.x *= f;
-                v.y *= f;
+            if (N <= 2 * p) {
+                v = I[idx];
+                v.x *= hpow[N];
+                v.y *= hpow[N];
             }
-            Ms[i * msr + c] = v;
+            It[idx] = v;
         }
         __syncthreads();
-        if (act) {
-            // the imaginary sums run negated through the columns m < 0
+        const double2* ms[M2L_C];
 #pragma unroll
-            for (int r = 0; r < M2L_R; ++r)
+        for (int c = 0; c < M2L_C; ++c)
+            ms[c] = mom + (size_t)cell_key(tc[c][0] - dx, tc[c][1] - dy, tc[c][2] - dz, l) * nc;
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int c = 0; c < M2L_C; ++c) ai[r][c] = -ai[r][c];
             for (int m = -p; m <= p; ++m) {
                 if (m == 0) {
 #pragma unroll
-                    for (int r = 0; r < M2L_R; ++r)
+                    for (int r = 0; r < R; ++r)
 #pragma unroll
                         for (int c = 0; c < M2L_C; ++c) ai[r][c] = -ai[r][c];
                 }
-                m2l_column(It, Ms, msr, p, m, k, j0, tg, ar, ai);
+                m2l_column<R>(It, ms, p, m, k, j0, ar, ai);
             }
         }
     }
     if (act) {
         const int ncell = 1 << (3 * l);
 #pragma unroll
-        for (int r = 0; r < M2L_R; ++r) {
+        for (int r = 0; r < R; ++r) {
             const int j = j0 + r;
             if (j > p) continue;
-            double f = ((j + k) & 1) ? -1.0 : 1.0;
-            f *= hpow[j] / h;   // h^-(j+1)
+            const double f = (((j + k) & 1) ? -1.0 : 1.0) / h;
 #pragma unroll
             for (int c = 0; c < M2L_C; ++c) {
-                const int cid = (tile * M2L_NT + c * M2L_TG + tg) * 8 + cls;
+                const int cid = (tile * M2L_NT + wave * M2L_C + c) * 8 + cls;
                 part[((size_t)g * ncell + cid) * nc + tri(j, k)] = make_double2(f * ar[r][c], f * ai[r][c]);
             }
         }
@@ -1133,36 +1102,26 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
 }
 
 // ---------------------------------------------------------------- host
-// Dynamic LDS of the blocked M2L: I~ up to order 2p + R and the moments of
-// its target cells.
+// Dynamic LDS of the blocked M2L: I~ up to order 2p + R (34 KB at order 20).
 static size_t m2l_tile_lds(int p) {
-    const size_t nip = (size_t)(2 * p + M2L_R + 1) * (2 * p + M2L_R + 1);
-    return sizeof(double2) * (nip + (size_t)M2L_NT * tri(p + 1, 0));
-}
-
-// LDS one work-group may take on the current device, asked once per device.
-static size_t lds_per_block() {
-    static std::atomic<int> known[64];   // 0: not asked yet
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
-    int v = known[dev].load();
-    if (v > 0) return (size_t)v;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-        v = 65536;
-    known[dev].store(v);
-    return (size_t)v;
+    const size_t nip = (size_t)(2 * p + m2l_rows(p) + 1) * (2 * p + m2l_rows(p) + 1);
+    return sizeof(double2) * nip;
 }
 
 // The blocked M2L serves the levels with at least M2L_NT cells per parent
-// corner, within the LDS a work-group may take (its static tables included);
-// above 64 KB it is asked for explicitly at launch.
-static bool m2l_tiled(int l, int p) { return l >= 3 && m2l_tile_lds(p) + 2048 <= lds_per_block(); }
+// corner.
+static bool m2l_tiled(int l) { return l >= 3; }
 
 // Work-groups per cell (direct M2L) or per tile of M2L_NT cells (blocked
 // M2L) at level l: enough that a level of few cells still spreads over the
 // GPU.
 static int split_cell(int l) { return std::max(1, std::min(16, 2048 / (1 << (3 * l)))); }
-static int split_tile(int l) { return std::max(1, std::min(32, 2048 / ((1 << (3 * l)) / M2L_NT))); }
+// The blocked M2L keeps 5 work-groups per compute unit resident at 3 orders
+// per lane (4 at 5): the split fills the 256 compute units for whole rounds.
+static int split_tile(int l, int p) {
+    const int round = 256 * (m2l_rows(p) == 3 ? 5 : 4);
+    return std::max(1, std::min(48, round / ((1 << (3 * l)) / M2L_NT)));
+}
 
 int tree_leaf_level(int64_t ns) {
     // at most tree_leaf_images() images per leaf cell (ns / 8^L: the 27 ns
@@ -1208,7 +1167,7 @@ TreeLayout tree_layout(int64_t ns, int p) {
     t.off_itab = take(sizeof(double2) * 343 * (size_t)(2 * p + 1) * (2 * p + 1));
     size_t part_cells = 0;
     for (int l = 1; l <= t.L; ++l)   // room for either M2L's parts
-        part_cells = std::max(part_cells, (size_t)std::max(split_cell(l), m2l_tiled(l, p) ? split_tile(l) : 0)
+        part_cells = std::max(part_cells, (size_t)std::max(split_cell(l), m2l_tiled(l) ? split_tile(l, p) : 0)
                                               << (3 * l));
     t.off_part = take(sizeof(double2) * (size_t)nc * part_cells);
     // hipCUB temporary storage of the sort
@@ -1344,19 +1303,16 @@ hipError_t launch_tree_near(int nt, double L, const TreeLayout& t, char* ws, dou
     for (int l = 1; l <= t.L; ++l) {
         double2* loc = (double2*)(ws + t.off_loc[l]);
         const double2* ploc = l >= 2 ? (const double2*)(ws + t.off_loc[l - 1]) : nullptr;
-        bool tiled = m2l_tiled(l, t.p);
-        const size_t tlds = m2l_tile_lds(t.p);
-        if (tiled && tlds > 65536 &&
-            hipFuncSetAttribute((const void*)k_fmm_m2l_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)tlds) != hipSuccess) {
-            (void)hipGetLastError();   // not granted: the per-cell M2L (the parts have room for it)
-            tiled = false;
-        }
-        const int G = tiled ? split_tile(l) : split_cell(l);
+        const bool tiled = m2l_tiled(l);
+        const int G = tiled ? split_tile(l, t.p) : split_cell(l);
         if (tiled) {
-            const int nthr = (m2l_groups(t.p) * M2L_TG + 63) / 64 * 64;
-            hipLaunchKernelGGL(k_fmm_m2l_tile, dim3((1u << (3 * l)) / M2L_NT, G), dim3(nthr), tlds, s,
-                               (const double2*)(ws + t.off_mom[l]), offs, l, t.L, t.p, L, itab, G, part);
+            const dim3 grid((1u << (3 * l)) / M2L_NT, G);
+            if (m2l_rows(t.p) == 3)
+                hipLaunchKernelGGL(k_fmm_m2l_tile<3>, grid, dim3(64 * M2L_WAVES), m2l_tile_lds(t.p), s,
+                                   (const double2*)(ws + t.off_mom[l]), l, t.p, L, itab, G, part);
+            else
+                hipLaunchKernelGGL(k_fmm_m2l_tile<5>, grid, dim3(64 * M2L_WAVES), m2l_tile_lds(t.p), s,
+                                   (const double2*)(ws + t.off_mom[l]), l, t.p, L, itab, G, part);
         } else {
             const size_t lds = sizeof(double2) * ((size_t)(t.p + 1) * (t.p + 1) +
                                                   (size_t)(2 * t.p + 1) * (2 * t.p + 1)) +
