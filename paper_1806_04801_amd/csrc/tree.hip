@@ -274,13 +274,53 @@ k_tree_p2m_cols(const double4* __restrict__ srt, const int* __restrict__ offs, i
         const double cx = -1.5 * L + ((double)((box / 9) * (1u << lev) + ix) + 0.5) * h;
         const double cy = -1.5 * L + ((double)(((box / 3) % 3) * (1u << lev) + iy) + 0.5) * h;
         const double cz = -1.5 * L + ((double)((box % 3) * (1u << lev) + iz) + 0.5) * h;
-        double4 yn = srt[b];   // the next source, read one step ahead
-        for (int s = b; s < e; ++s) {
-            const double4 y = yn;
-            yn = srt[min(s + 1, e - 1)];
+        // two sources a step (their recurrences interleave; each sum still
+        // takes them in order), the next two read one step ahead
+        double4 na = srt[b], nb = srt[min(b + 1, e - 1)];
+        int s = b;
+        for (; s + 1 < e; s += 2) {
+            const double4 ya = na, yb = nb;
+            na = srt[min(s + 2, e - 1)];
+            nb = srt[min(s + 3, e - 1)];
+            const double xa = ya.x - cx, ja = ya.y - cy, za = ya.z - cz;
+            const double xb = yb.x - cx, jb = yb.y - cy, zb = yb.z - cz;
+            const double r2a = xa * xa + ja * ja + za * za, r2b = xb * xb + jb * jb + zb * zb;
+            // R_m^m = (x + iy)^m / (2^m m!)
+            double wra = 1.0, wia = 0.0, wrb = 1.0, wib = 0.0;
+            for (int k = 0; k < m; ++k) {
+                const double nra = __builtin_fma(wra, xa, -wia * ja);
+                const double nrb = __builtin_fma(wrb, xb, -wib * jb);
+                wia = __builtin_fma(wra, ja, wia * xa);
+                wib = __builtin_fma(wrb, jb, wib * xb);
+                wra = nra;
+                wrb = nrb;
+            }
+            double pra = 0.0, pia = 0.0, cra = wra * dscale, cia = wia * dscale;
+            double prb = 0.0, pib = 0.0, crb = wrb * dscale, cib = wib * dscale;
+            double zza = (double)(2 * m - 1) * za, zzb = (double)(2 * m - 1) * zb;
+            const double z2a = 2.0 * za, z2b = 2.0 * zb;
+#pragma unroll
+            for (int i = 0; i <= P; ++i) {
+                if (i > pm) continue;
+                if (i > 0) {
+                    zza += z2a;
+                    zzb += z2b;
+                    const double nra = __builtin_fma(zza, cra, -r2a * pra) * rinv[i];
+                    const double nia = __builtin_fma(zza, cia, -r2a * pia) * rinv[i];
+                    const double nrb = __builtin_fma(zzb, crb, -r2b * prb) * rinv[i];
+                    const double nib = __builtin_fma(zzb, cib, -r2b * pib) * rinv[i];
+                    pra = cra; pia = cia; cra = nra; cia = nia;
+                    prb = crb; pib = cib; crb = nrb; cib = nib;
+                }
+                // M += q conj(R), source a then b
+                ar[i] = __builtin_fma(yb.w, crb, __builtin_fma(ya.w, cra, ar[i]));
+                ai[i] = __builtin_fma(-yb.w, cib, __builtin_fma(-ya.w, cia, ai[i]));
+            }
+        }
+        if (s < e) {   // the last source of an odd count (na holds it)
+            const double4 y = na;
             const double x = y.x - cx, yy = y.y - cy, z = y.z - cz;
             const double r2 = x * x + yy * yy + z * z;
-            // R_m^m = (x + iy)^m / (2^m m!)
             double wr = 1.0, wi = 0.0;
             for (int k = 0; k < m; ++k) {
                 const double nr = __builtin_fma(wr, x, -wi * yy);
@@ -299,7 +339,6 @@ k_tree_p2m_cols(const double4* __restrict__ srt, const int* __restrict__ offs, i
                     const double ni = __builtin_fma(zz, ci, -r2 * pi) * rinv[i];
                     pr = cr; pi = ci; cr = nr; ci = ni;
                 }
-                // M += q conj(R)
                 ar[i] = __builtin_fma(y.w, cr, ar[i]);
                 ai[i] = __builtin_fma(-y.w, ci, ai[i]);
             }
