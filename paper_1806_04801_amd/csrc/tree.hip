@@ -963,14 +963,16 @@ k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
                         for (int j = e0; j < e1; ++j)
                             if (j != s) term(srt[j]);
                     } else {
-                        // two sources a step, summed in order
+                        // four sources a step, summed in order
                         int j = e0;
-                        for (; j + 1 < e1; j += 2) {
-                            const double4 r0 = srt[j], r1 = srt[j + 1];
+                        for (; j + 3 < e1; j += 4) {
+                            const double4 r0 = srt[j], r1 = srt[j + 1], r2 = srt[j + 2], r3 = srt[j + 3];
                             term(r0);
                             term(r1);
+                            term(r2);
+                            term(r3);
                         }
-                        if (j < e1) term(srt[j]);
+                        for (; j < e1; ++j) term(srt[j]);
                     }
                 }
             }
