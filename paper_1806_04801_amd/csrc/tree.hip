@@ -859,8 +859,9 @@ k_fmm_l2l(const double2* __restrict__ part, int G, int l, int p, double Lbox,
 }
 
 // ---------------------------------------------------------------- evaluation
-// Wave (leaf cell of the central box, chunk g of Gs), a lane per target
-// (central images of real particles): chunk 0 evaluates the cell's local
+// Work-group (leaf cell of the central box, chunk g of Gs), a lane per target
+// (central images of real particles; its waves take the passes of 64 targets
+// in turn, reading the same sources together): chunk 0 evaluates the cell's local
 // expansion at the target,
 //   phi = sum L_n^m R_n^m(d),  E_z = -sum L_n^m R_{n-1}^m(d),
 //   E_x + i E_y = sum_{m >= 0} L_n^m R_{n-1}^{m+1}(d) - sum_{m >= 1} conj(L_n^m R_{n-1}^{m-1}(d))
@@ -868,13 +869,14 @@ k_fmm_l2l(const double2* __restrict__ part, int G, int l, int p, double Lbox,
 // -R_{n-1}^{m+1}), and every chunk sums the sources of the neighbouring leaf
 // cells g, g + Gs, ... of the 27 directly.  out[(g * 4 + comp) * npad + i],
 // comp 0 = phi, 1..3 = E, for target i.
-__global__ void __launch_bounds__(TWG)
+constexpr int EWG = 256;   // evaluation work-group: a wave per pass of 64 targets
+__global__ void __launch_bounds__(EWG)
 k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
             const int* __restrict__ offs, const double2* __restrict__ loc, int L, int p, double Lbox,
             int nt, double* __restrict__ out, int npad) {
     const int g = blockIdx.y, Gs = gridDim.y;
     out += (size_t)g * 4 * npad;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int side = 1 << L;
     const int cid = blockIdx.x;   // Morton index within the central box
     uint32_t ix = 0, iy = 0, iz = 0;
@@ -891,7 +893,9 @@ k_tree_eval(const double4* __restrict__ srt, const int* __restrict__ owner,
     const double ccy = -1.5 * Lbox + (gy + 0.5) * h;
     const double ccz = -1.5 * Lbox + (gz + 0.5) * h;
     const double2* LL = loc + (size_t)cid * tri(p + 1, 0);
-    for (int base = b0; base < b1; base += TWG) {
+    // the waves take the target passes in turn; they read the same sources
+    const int w0 = 64 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int base = b0 + w0; base < b1; base += EWG) {
         const int s = base + lane;
         const bool act = s < b1;
         const int me = act ? owner[s] : -1;
@@ -1364,7 +1368,7 @@ hipError_t launch_tree_near(int nt, double L, const TreeLayout& t, char* ws, dou
         hipLaunchKernelGGL(k_fmm_l2l, dim3(1u << (3 * l)), dim3(FWG), 0, s, part, G, l, t.p, L, dtab, ploc,
                            loc);
     }
-    hipLaunchKernelGGL(k_tree_eval, dim3(1u << (3 * t.L), t.eval_split), dim3(TWG), 0, s,
+    hipLaunchKernelGGL(k_tree_eval, dim3(1u << (3 * t.L), t.eval_split), dim3(EWG), 0, s,
                        (const double4*)(ws + t.off_srt), (const int*)(ws + t.off_owner), offs,
                        (const double2*)(ws + t.off_loc[t.L]), t.L, t.p, L, nt, out, npad);
     return hipGetLastError();
