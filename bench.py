@@ -256,7 +256,7 @@ def serving_measure(n_requests, refine, log=sys.stderr):
     K = M = 10 p^2, R = 2.7L.  Closed loop (all requests at t = 0) gives
     solves/s of six paths: the served path (batched FP32-comp with
     ill-conditioned energies refined in FP64), the same with tree plans
-    (requests of 32768 particles and more on the fast multipole method), and
+    (requests of 24576 particles and more on the fast multipole method), and
     the batched server and one solve per request, each in FP32-comp and in
     FP64 without refinement (equal-precision comparisons).  Open loop
     (Poisson arrivals at 0.8 of a path's closed-loop rate) gives p50/p99
@@ -361,7 +361,7 @@ def serving_measure(n_requests, refine, log=sys.stderr):
         # the served single-precision path (every energy within 1e-5) against
         # the plain double-precision path
         "gain_served_fp32_vs_sequential_fp64": mu32 / mu64,
-        # the served path with tree plans (fast multipole method from 32768
+        # the served path with tree plans (fast multipole method from 24576
         # particles on, same refinement) against the plain double-precision path
         "gain_served_fmm_vs_sequential_fp64": mufmm / mu64,
         "latency": lat,

@@ -73,7 +73,7 @@ typedef enum {
                               acceleration of Sec. II.C, Table I): multipole and local
                               expansions of order hsma_plan_desc.tree_order about the cells of a
                               uniform octree over the 27 boxes (at most HSMA_TREE_LEAF images
-                              per leaf cell, 320 by default), direct sums between neighbouring
+                              per leaf cell, 1000 by default), direct sums between neighbouring
                               leaf cells, in double precision whatever the plan's precision;
                               below tree_min_n the direct kernels of HSMA_NEAR_BLOCK in the
                               plan's precision; at most (2^31 - 1) / 27 sources on the tree
@@ -133,7 +133,7 @@ typedef struct {
                           below 1e-13 sum|q|/L at the monitoring points */
     int tree_order;    /* HSMA_NEAR_TREE: expansion order, 1..20 (0 selects 16) */
     int tree_min_n;    /* HSMA_NEAR_TREE: the fast multipole method from this many particles
-                          on, >= 1 (0 selects 16384 for HSMA_FP64 plans and 32768 for
+                          on, >= 1 (0 selects 16384 for HSMA_FP64 plans and 24576 for
                           HSMA_FP32_COMP plans, near the measured crossovers with the direct
                           double- and single-precision near sums) */
 } hsma_plan_desc;

@@ -150,7 +150,7 @@ hsma_status hsma_plan_create_ex(const hsma_plan_desc* d, hsma_plan* out) {
     pl->tree_min_n = d->near_mode != HSMA_NEAR_TREE ? 0
                      : d->tree_min_n > 0                ? d->tree_min_n
                      : d->precision == HSMA_FP64         ? 16384
-                                                         : 32768;
+                                                         : 24576;
     if (pl->near_mode == HSMA_NEAR_SPHERE) {
         // candidates |k_a| <= kr; a source has at most as many images inside the
         // sphere as there are shifted boxes that reach it

@@ -1181,7 +1181,7 @@ double tree_leaf_images() {
     static const double v = [] {
         const char* e = getenv("HSMA_TREE_LEAF");
         const double d = e ? atof(e) : 0.0;
-        return d >= 1.0 ? d : 320.0;
+        return d >= 1.0 ? d : 1000.0;
     }();
     return v;
 }

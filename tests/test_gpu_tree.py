@@ -1,6 +1,6 @@
 """The fast-multipole near sum (HSMA_NEAR_TREE) against the oracle's direct
 near sum over the 3x3x3 image block: element-wise at every particle for small
-systems, on sampled particles at 1e5 and 1e6, for the periodic cube, the
+systems, on sampled particles at 4e4 (leaf level 2), 1e5 and 1e6, for the periodic cube, the
 grounded cube and the slab, in double precision."""
 import time
 
@@ -130,7 +130,8 @@ def test_tree_order_controls_the_error(hs):
     assert errs[2]["E"] < 0.1 * errs[0]["E"]
 
 
-@pytest.mark.parametrize("bc,n,ns", [(0, 100_000, 512), (1, 100_000, 512), (0, 1_000_000, 256)])
+@pytest.mark.parametrize("bc,n,ns", [(0, 40_000, 512), (2, 40_000, 512), (0, 100_000, 512), (1, 100_000, 512),
+                                     (0, 1_000_000, 256)])
 def test_tree_near_sum_sampled_at_size(hs, bc, n, ns):
     announce("tree near bc=%d n=%d sampled" % (bc, n))
     x, q = system(bc, n, 80)
@@ -209,8 +210,8 @@ def test_tree_rejections(hs):
     # the default threshold, and the near kernel either side of it
     assert hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE).info["tree_min_n"] == 16384
     p32 = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, precision=hs.FP32_COMP)
-    assert p32.info["tree_min_n"] == 32768
-    assert p32.near_schedule(32767)["kind"] == 1 and p32.near_schedule(32768)["kind"] == 2
+    assert p32.info["tree_min_n"] == 24576
+    assert p32.near_schedule(24575)["kind"] == 1 and p32.near_schedule(24576)["kind"] == 2
 
 
 @pytest.mark.parametrize("precision", [0, 1])
