@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 # the grounded cube every charge and its mirror image cancel, so b is a small
 # remainder of the image potentials and the tree's error (set by the far
 # cells' potentials) is larger relative to it: measured 8e-6 to 3e-5 there,
-# against 1e-7 to 3e-7 at the circumsphere points of the periodic cube and
+# against 1e-7 to 8e-7 at the circumsphere points of the periodic cube and
 # the slab.
 TOL_PHI, TOL_E, TOL_EN = 5e-6, 1e-6, 1e-7
 TOL_B = {0: 1e-6, 1: 1e-4, 2: 1e-6}
