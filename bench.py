@@ -452,7 +452,7 @@ def fmm_measure(cfg, xd, qd, steps, e_direct):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print("bench.py: runs on one GPU only (there is no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
