@@ -464,35 +464,36 @@ __global__ void k_tree_m2m_coef(const double2* __restrict__ child, const int* __
 // full layout n*n + n + m for m in [-n, n] with I~_n^-m = (-1)^m conj(I_n^m).
 // Offsets of neighbouring cells (|D_a| <= 1) are never used and left unset.
 __global__ void k_fmm_itab(int p2, double2* __restrict__ tab) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    // a thread per (offset, column m): I_m^m by the diagonal recurrence, then
+    // up the column in n
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int o = id / (p2 + 1), m = id - o * (p2 + 1);
     if (o >= 343) return;
     const int dx = o / 49 - 3, dy = (o / 7) % 7 - 3, dz = o % 7 - 3;
     if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) return;
     const double x = dx, y = dy, z = dz;
     const double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
     double2* T = tab + (size_t)o * (p2 + 1) * (p2 + 1);
-    double dr = 1.0 / sqrt(r2), di = 0.0;   // I_m^m
-    for (int m = 0; m <= p2; ++m) {
-        if (m > 0) {
-            const double f = (2 * m - 1) * ir2;
-            const double nr = f * (x * dr - y * di);
-            const double ni = f * (x * di + y * dr);
-            dr = nr;
-            di = ni;
+    double dr = 1.0 / sqrt(r2), di = 0.0;   // I_0^0, then I_k^k up to k = m
+    for (int k = 1; k <= m; ++k) {
+        const double f = (2 * k - 1) * ir2;
+        const double nr = f * (x * dr - y * di);
+        const double ni = f * (x * di + y * dr);
+        dr = nr;
+        di = ni;
+    }
+    double pr = 0.0, pi = 0.0, cr = dr, ci = di;
+    for (int n = m; n <= p2; ++n) {
+        if (n > m) {
+            const double c2 = (double)((n - 1) * (n - 1) - m * m);
+            const double nr = ((2 * n - 1) * z * cr - c2 * pr) * ir2;
+            const double ni = ((2 * n - 1) * z * ci - c2 * pi) * ir2;
+            pr = cr; pi = ci; cr = nr; ci = ni;
         }
-        double pr = 0.0, pi = 0.0, cr = dr, ci = di;
-        for (int n = m; n <= p2; ++n) {
-            if (n > m) {
-                const double c2 = (double)((n - 1) * (n - 1) - m * m);
-                const double nr = ((2 * n - 1) * z * cr - c2 * pr) * ir2;
-                const double ni = ((2 * n - 1) * z * ci - c2 * pi) * ir2;
-                pr = cr; pi = ci; cr = nr; ci = ni;
-            }
-            T[n * n + n + m] = make_double2(cr, ci);
-            if (m > 0) {
-                const double sg = (m & 1) ? -1.0 : 1.0;
-                T[n * n + n - m] = make_double2(sg * cr, -sg * ci);
-            }
+        T[n * n + n + m] = make_double2(cr, ci);
+        if (m > 0) {
+            const double sg = (m & 1) ? -1.0 : 1.0;
+            T[n * n + n - m] = make_double2(sg * cr, -sg * ci);
         }
     }
 }
@@ -1230,35 +1231,36 @@ TreeLayout tree_layout(int64_t ns, int p) {
 // -1/4 or +1/4, octant o = Morton digit), (p+1)^2 entries per octant (index
 // j*j + j + k), by the recurrences of the leaf moments.  One thread per octant.
 __global__ void k_tree_m2m_table(int p, double2* __restrict__ tab) {
-    const int o = threadIdx.x;
+    // a thread per (octant, column m): R_m^m by the diagonal recurrence, then
+    // up the column in n
+    const int id = threadIdx.x;
+    const int o = id / (p + 1), m = id - o * (p + 1);
     if (o >= 8) return;
     const double x = ((o >> 2) & 1) ? 0.25 : -0.25;
     const double y = ((o >> 1) & 1) ? 0.25 : -0.25;
     const double z = (o & 1) ? 0.25 : -0.25;
     const double r2 = x * x + y * y + z * z;
     double2* T = tab + (size_t)o * (p + 1) * (p + 1);
-    double dr = 1.0, di = 0.0;   // R_m^m
-    for (int m = 0; m <= p; ++m) {
-        if (m > 0) {
-            const double nr = (dr * x - di * y) / (2.0 * m);
-            const double ni = (dr * y + di * x) / (2.0 * m);
-            dr = nr;
-            di = ni;
+    double dr = 1.0, di = 0.0;   // R_0^0, then R_k^k up to k = m
+    for (int k = 1; k <= m; ++k) {
+        const double nr = (dr * x - di * y) / (2.0 * k);
+        const double ni = (dr * y + di * x) / (2.0 * k);
+        dr = nr;
+        di = ni;
+    }
+    double pr = 0.0, pi = 0.0, cr = dr, ci = di;
+    for (int n = m; n <= p; ++n) {
+        if (n > m) {
+            const double inv = 1.0 / ((double)(n + m) * (double)(n - m));
+            const double nr = ((2 * n - 1) * z * cr - r2 * pr) * inv;
+            const double ni = ((2 * n - 1) * z * ci - r2 * pi) * inv;
+            pr = cr; pi = ci; cr = nr; ci = ni;
         }
-        double pr = 0.0, pi = 0.0, cr = dr, ci = di;
-        for (int n = m; n <= p; ++n) {
-            if (n > m) {
-                const double inv = 1.0 / ((double)(n + m) * (double)(n - m));
-                const double nr = ((2 * n - 1) * z * cr - r2 * pr) * inv;
-                const double ni = ((2 * n - 1) * z * ci - r2 * pi) * inv;
-                pr = cr; pi = ci; cr = nr; ci = ni;
-            }
-            // conj(R~_n^m) = conj(R_n^m); conj(R~_n^-m) = (-1)^m R_n^m
-            T[n * n + n + m] = make_double2(cr, -ci);
-            if (m > 0) {
-                const double sg = (m & 1) ? -1.0 : 1.0;
-                T[n * n + n - m] = make_double2(sg * cr, sg * ci);
-            }
+        // conj(R~_n^m) = conj(R_n^m); conj(R~_n^-m) = (-1)^m R_n^m
+        T[n * n + n + m] = make_double2(cr, -ci);
+        if (m > 0) {
+            const double sg = (m & 1) ? -1.0 : 1.0;
+            T[n * n + n - m] = make_double2(sg * cr, sg * ci);
         }
     }
 }
@@ -1304,7 +1306,7 @@ hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, 
                                (int)t.ncell_leaf, t.p, L, (double2*)(ws + t.off_mom[t.L]));
     }
     double2* dtab = (double2*)(ws + t.off_tab);
-    hipLaunchKernelGGL(k_tree_m2m_table, dim3(1), dim3(64), 0, s, t.p, dtab);
+    hipLaunchKernelGGL(k_tree_m2m_table, dim3(1), dim3(8 * (TREE_MAX_ORDER + 1)), 0, s, t.p, dtab);
     const size_t lds_m2m = sizeof(double2) * 8 * (size_t)(t.p + 1) * (t.p + 1);
     const int nc = tri(t.p + 1, 0);
     for (int l = t.L - 1; l >= 0; --l) {
@@ -1343,7 +1345,7 @@ hipError_t launch_tree_near(int nt, double L, const TreeLayout& t, char* ws, dou
     const double2* dtab = (const double2*)(ws + t.off_tab);
     // local expansions of the central box, level by level
     double2* itab = (double2*)(ws + t.off_itab);
-    hipLaunchKernelGGL(k_fmm_itab, dim3(2), dim3(256), 0, s, 2 * t.p, itab);
+    hipLaunchKernelGGL(k_fmm_itab, dim3((343 * (2 * t.p + 1) + 255) / 256), dim3(256), 0, s, 2 * t.p, itab);
     double2* part = (double2*)(ws + t.off_part);
     for (int l = 1; l <= t.L; ++l) {
         double2* loc = (double2*)(ws + t.off_loc[l]);
