@@ -1027,27 +1027,30 @@ __device__ double m2p_phi(const double2* __restrict__ M, int p, double x, double
 
 constexpr int PT_MAX_ITEMS = 27 + 189 * TREE_MAX_LEVEL;   // far cells of one point, all levels
 
-// One wave per point (monitoring points and twins, centred coordinates):
+// A work-group of four waves per point (monitoring points and twins, centred
+// coordinates):
 // the potential of every image in the 3x3x3 block, from the multipoles of
 // the point's far cells at every level and the images of its 27 neighbouring
 // leaf cells directly.  Far cells: at level 0 the boxes not adjacent to the
 // point's box (a point outside the central box has such boxes), at level
 // l >= 1 the children of the neighbours of the point's level-(l - 1) cell
 // that are not neighbours of its level-l cell.  The far cells are listed in
-// LDS first and then shared out over the lanes; the lane sums are combined
-// by a fixed butterfly.
-__global__ void __launch_bounds__(64)
+// LDS first and then shared out over the work-group's lanes, like the
+// neighbours' images; the lane sums are combined by a fixed butterfly in each
+// wave and the waves' sums in order.
+constexpr int PT_WG = 256;   // a work-group (four waves) per point
+__global__ void __launch_bounds__(PT_WG)
 k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, int npts, int share,
               const double4* __restrict__ srt, const int* __restrict__ offs, MomPtrs moms, int L, int p,
               double Lbox, double* __restrict__ out) {
     __shared__ int item_key[PT_MAX_ITEMS];
     __shared__ char item_lev[PT_MAX_ITEMS];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x;   // thread of the work-group (PT_WG)
     // work-groups go round the XCDs in turn: XCD x takes the points x * share
     // .. (x + 1) * share - 1 of the given order, whose far cells overlap in
     // its L2
     const int pos = (blockIdx.x & 7) * share + (blockIdx.x >> 3);
-    if (pos >= npts) return;   // the whole (one-wave) work-group
+    if (pos >= npts) return;   // the whole work-group, before any barrier
     const int pi = order[pos];
     const double4 P = pts[pi];
     const int GL = 3 << L;
@@ -1063,7 +1066,7 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
     // lane walks the flags and writes its share of the list)
     __shared__ unsigned char okf[27 + 216 * TREE_MAX_LEVEL];
     const int bx = g[0] >> L, by = g[1] >> L, bz = g[2] >> L;
-    for (int c = lane; c < 27; c += 64) {
+    for (int c = lane; c < 27; c += PT_WG) {
         const int cx = c / 9, cy = (c / 3) % 3, cz = c % 3;
         bool ok = !(abs(cx - bx) <= 1 && abs(cy - by) <= 1 && abs(cz - bz) <= 1);
         if (ok) ok = offs[(size_t)(c + 1) << (3 * L)] != offs[(size_t)c << (3 * L)];
@@ -1074,7 +1077,7 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
         const int shift = 3 * (L - l);
         const int tx = g[0] >> (L - l), ty = g[1] >> (L - l), tz = g[2] >> (L - l);
         const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
-        for (int c = lane; c < 216; c += 64) {
+        for (int c = lane; c < 216; c += PT_WG) {
             const int cx = 2 * px - 2 + c / 36, cy = 2 * py - 2 + (c / 6) % 6, cz = 2 * pz - 2 + c % 6;
             bool ok = cx >= 0 && cx < G && cy >= 0 && cy < G && cz >= 0 && cz < G &&
                       !(abs(cx - tx) <= 1 && abs(cy - ty) <= 1 && abs(cz - tz) <= 1);
@@ -1089,7 +1092,7 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
     int nitem = 0;
     for (int c = 0; c < 27; ++c)
         if (okf[c]) {
-            if (nitem % 64 == lane) { item_key[nitem] = c; item_lev[nitem] = 0; }
+            if (nitem % PT_WG == lane) { item_key[nitem] = c; item_lev[nitem] = 0; }
             ++nitem;
         }
     for (int l = 1; l <= L; ++l) {
@@ -1097,7 +1100,7 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
         const int px = tx >> 1, py = ty >> 1, pz = tz >> 1;
         for (int c = 0; c < 216; ++c)
             if (okf[27 + 216 * (l - 1) + c]) {
-                if (nitem % 64 == lane) {
+                if (nitem % PT_WG == lane) {
                     item_key[nitem] = (int)cell_key(2 * px - 2 + c / 36, 2 * py - 2 + (c / 6) % 6,
                                                     2 * pz - 2 + c % 6, l);
                     item_lev[nitem] = (char)l;
@@ -1108,7 +1111,7 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
     __syncthreads();
     const int nc = tri(p + 1, 0);
     double acc = 0.0;
-    for (int i = lane; i < nitem; i += 64) {
+    for (int i = lane; i < nitem; i += PT_WG) {
         const int l = item_lev[i];
         const uint32_t ck = (uint32_t)item_key[i];
         // centre of cell ck of level l
@@ -1134,7 +1137,7 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
                 if (cz < 0 || cz >= GL) continue;
                 const uint32_t ck = cell_key(cx, cy, cz, L);
                 const int e1 = offs[ck + 1];
-                for (int j = offs[ck] + lane; j < e1; j += 64) {
+                for (int j = offs[ck] + lane; j < e1; j += PT_WG) {
                     const double4 r = srt[j];
                     const double dx = P.x - r.x, dy = P.y - r.y, dz = P.z - r.z;
                     acc += r.w / sqrt(dx * dx + dy * dy + dz * dz);
@@ -1144,7 +1147,15 @@ k_tree_points(const double4* __restrict__ pts, const int* __restrict__ order, in
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) out[pi] = acc;
+    // the waves' sums, added in order
+    __shared__ double wsum[PT_WG / 64];
+    if ((lane & 63) == 0) wsum[lane >> 6] = acc;
+    __syncthreads();
+    if (lane == 0) {
+        double v = wsum[0];
+        for (int w = 1; w < PT_WG / 64; ++w) v += wsum[w];
+        out[pi] = v;
+    }
 }
 
 // ---------------------------------------------------------------- host
@@ -1333,7 +1344,7 @@ hipError_t launch_tree_points(const double4* pts, const int* order, int npts, do
     for (int l = 0; l <= TREE_MAX_LEVEL; ++l)
         mp.lev[l] = l <= t.L ? (const double2*)(ws + t.off_mom[l]) : nullptr;
     const int share = (npts + 7) / 8;
-    hipLaunchKernelGGL(k_tree_points, dim3(8 * share), dim3(64), 0, s, pts, order, npts, share,
+    hipLaunchKernelGGL(k_tree_points, dim3(8 * share), dim3(PT_WG), 0, s, pts, order, npts, share,
                        (const double4*)(ws + t.off_srt), (const int*)(ws + t.off_offs), mp, t.L, t.p, L, out);
     return hipGetLastError();
 }
