@@ -1302,9 +1302,10 @@ hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, 
                        n, t.ncell_leaf, offs);
     // multipoles: leaf level directly, coarser levels (down to the 27 boxes
     // of level 0) by translation
-    // leaf multipoles: a wave per cell while the cells are few, a thread per
-    // (cell, m) for many (measured faster at each end)
-    if (t.ncell_leaf <= 32768)
+    // leaf multipoles: a wave per cell for leaf levels 1-2 (equal to the
+    // columns at level 2), a thread per (cell, m) from level 3 on (1.9 against
+    // 1.2 ms at 3e5 particles)
+    if (t.ncell_leaf <= 2048)
         hipLaunchKernelGGL(k_tree_p2m_wave, dim3((unsigned)t.ncell_leaf), dim3(64), 0, s, srt, offs, t.L, t.p,
                            L, (double2*)(ws + t.off_mom[t.L]));
     else {
