@@ -350,27 +350,30 @@ k_tree_p2m_cols(const double4* __restrict__ srt, const int* __restrict__ offs, i
 }
 
 // ---------------------------------------------------------------- translation
-// For few parents: a work-group per parent cell of level l, a thread per
-// moment M_n^m (m >= 0) of the parent, from its 8 children at level l + 1
-// (children with no source skipped), whose moments are staged in LDS in the
-// full signed layout.  tab holds conj(R~_j^k(d_o)) of the 8 child offsets d_o
-// (per axis +-1/4 of the parent's side, octant o = Morton digit) for the unit
-// side, 8 x (p+1)^2 entries (index j*j + j + k), scaled here by side^j.
-__global__ void __launch_bounds__(256)
+// For few parents: a work-group per parent cell of level l and per moment
+// M_n^m (m >= 0) of the parent M2M_Q threads, each translating two of its 8
+// children at level l + 1 (children with no source skipped), whose moments
+// are staged in LDS in the full signed layout; the M2M_Q parts are added in
+// order.  tab holds conj(R~_j^k(d_o)) of the 8 child offsets d_o (per axis
+// +-1/4 of the parent's side, octant o = Morton digit) for the unit side,
+// 8 x (p+1)^2 entries (index j*j + j + k), scaled here by side^j.
+constexpr int M2M_Q = 4;
+__global__ void __launch_bounds__(1024)
 k_tree_m2m_group(const double2* __restrict__ child, const int* __restrict__ offs, int l, int L, int p,
                  double side, const double2* __restrict__ tab, double2* __restrict__ parent) {
-    extern __shared__ double2 Ct[];   // 8 (p+1)^2
+    extern __shared__ double2 Ct[];   // 8 (p+1)^2; afterwards the M2M_Q x nc parts
     __shared__ int full[8];
     const int nc = tri(p + 1, 0);
     const int nf = (p + 1) * (p + 1);
+    const int ncp = (nc + 63) / 64 * 64;   // threads per child pair
     const int64_t cell = blockIdx.x;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
     const int shift = 3 * (L - l - 1);
     if (t < 8) {
         const int64_t c = cell * 8 + t;
         full[t] = offs[(c + 1) << shift] != offs[c << shift];
     }
-    for (int idx = t; idx < 8 * nf; idx += 256) {
+    for (int idx = t; idx < 8 * nf; idx += nt) {
         const int o = idx / nf, r = idx - o * nf;
         int n = 0;
         while ((n + 1) * (n + 1) <= r) ++n;
@@ -383,31 +386,44 @@ k_tree_m2m_group(const double2* __restrict__ child, const int* __restrict__ offs
         Ct[idx] = v;
     }
     __syncthreads();
-    if (t >= nc) return;
-    int n = 0;
-    while (tri(n + 1, 0) <= t) ++n;
-    const int m = t - tri(n, 0);
+    const int q = t / ncp, ti = t - q * ncp;
     double sr = 0.0, si = 0.0;
-    for (int o = 0; o < 8; ++o) {
-        if (!full[o]) continue;
-        const double2* M = Ct + (size_t)o * nf;
-        const double2* T = tab + (size_t)o * nf;
-        double sj = 1.0;
-        for (int j = 0; j <= n; ++j) {
-            const int nn = n - j;
-            for (int k = -j; k <= j; ++k) {
-                const int mm = m - k;
-                if (mm > nn || -mm > nn) continue;
-                const double2 a = T[j * j + j + k];
-                const double2 bb = M[nn * nn + nn + mm];
-                const double ar = a.x * sj, ai = a.y * sj;
-                sr += ar * bb.x - ai * bb.y;
-                si += ar * bb.y + ai * bb.x;
+    if (ti < nc) {
+        int n = 0;
+        while (tri(n + 1, 0) <= ti) ++n;
+        const int m = ti - tri(n, 0);
+        for (int o = 2 * q; o < 2 * q + 2; ++o) {
+            if (!full[o]) continue;
+            const double2* M = Ct + (size_t)o * nf;
+            const double2* T = tab + (size_t)o * nf;
+            double sj = 1.0;
+            for (int j = 0; j <= n; ++j) {
+                const int nn = n - j;
+                for (int k = -j; k <= j; ++k) {
+                    const int mm = m - k;
+                    if (mm > nn || -mm > nn) continue;
+                    const double2 a = T[j * j + j + k];
+                    const double2 bb = M[nn * nn + nn + mm];
+                    const double ar = a.x * sj, ai = a.y * sj;
+                    sr += ar * bb.x - ai * bb.y;
+                    si += ar * bb.y + ai * bb.x;
+                }
+                sj *= side;
             }
-            sj *= side;
         }
     }
-    parent[(size_t)cell * nc + t] = make_double2(sr, si);
+    __syncthreads();   // the children's moments are read: their LDS takes the parts
+    double2* partq = Ct;
+    if (ti < nc) partq[q * nc + ti] = make_double2(sr, si);
+    __syncthreads();
+    if (q == 0 && ti < nc) {
+        double2 v = partq[ti];
+        for (int qq = 1; qq < M2M_Q; ++qq) {
+            v.x += partq[qq * nc + ti].x;
+            v.y += partq[qq * nc + ti].y;
+        }
+        parent[(size_t)cell * nc + ti] = v;
+    }
 }
 
 // For many parents: thread (parent cell, n, m >= 0) of level l: the moment
@@ -1319,7 +1335,7 @@ hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, 
     }
     double2* dtab = (double2*)(ws + t.off_tab);
     hipLaunchKernelGGL(k_tree_m2m_table, dim3(1), dim3(8 * (TREE_MAX_ORDER + 1)), 0, s, t.p, dtab);
-    const size_t lds_m2m = sizeof(double2) * 8 * (size_t)(t.p + 1) * (t.p + 1);
+    const size_t lds_m2m = sizeof(double2) * 8 * (size_t)(t.p + 1) * (t.p + 1);   // >= M2M_Q nc parts
     const int nc = tri(t.p + 1, 0);
     for (int l = t.L - 1; l >= 0; --l) {
         // a work-group per parent while the parents are few, a thread per
@@ -1327,7 +1343,8 @@ hipError_t launch_tree_build(int img, double gamma, const double4* src, int ns, 
         const int64_t ncell = (int64_t)27 << (3 * l);
         const double side = L / (double)(1 << l);
         if (ncell <= 512)
-            hipLaunchKernelGGL(k_tree_m2m_group, dim3((unsigned)ncell), dim3(256), lds_m2m, s,
+            hipLaunchKernelGGL(k_tree_m2m_group, dim3((unsigned)ncell), dim3(M2M_Q * ((nc + 63) / 64 * 64)),
+                               lds_m2m, s,
                                (const double2*)(ws + t.off_mom[l + 1]), offs, l, t.L, t.p, side, dtab,
                                (double2*)(ws + t.off_mom[l]));
         else
