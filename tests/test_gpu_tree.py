@@ -167,6 +167,27 @@ def test_tree_high_orders_at_size(hs):
     assert errs[20]["phi"] <= errs[16]["phi"] and errs[20]["E"] <= errs[16]["E"]
 
 
+def test_tree_step_is_bitwise_reproducible(hs):
+    """Every sum of the tree path runs in a fixed order (no atomics): the same
+    inputs give bitwise the same energy, potentials and forces, from one plan
+    called twice and from a second plan (1e5 particles: leaf level 3, whose
+    M2L is the blocked kernel with split offset lists)."""
+    announce("tree bitwise repeat n=100000")
+    x, q = system(0, 100_000, 82)
+    xd, qd = torch.tensor(x, device="cuda"), torch.tensor(q, device="cuda")
+    runs = []
+    for _ in range(2):
+        plan = hs.Plan(1.0, 0, 8, 1000, 300, 2.7, near_mode=hs.NEAR_TREE, tree_min_n=1)
+        for _ in range(2):
+            e, phi, F = plan.energy_forces(xd, qd)
+            torch.cuda.synchronize()
+            runs.append((e, phi.cpu().numpy(), F.cpu().numpy()))
+        plan.close()
+    e0, phi0, F0 = runs[0]
+    for e, phi, F in runs[1:]:
+        assert e == e0 and np.array_equal(phi, phi0) and np.array_equal(F, F0)
+
+
 @pytest.mark.parametrize("bc", [0, 1, 2])
 def test_tree_whole_step_vs_direct_step(hs, bc):
     """The whole update step in tree mode (near sum and right-hand side from
